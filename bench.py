@@ -1,0 +1,195 @@
+"""Throughput benchmark of the FDTD hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|bare:N]
+                    [--schemes systolic,plain] [--no-cpu-baseline]
+
+A "step" is one full Yee time step (E half-step, sources, H half-step) over
+the whole grid of the workload.  The default workload is the 1024x1024x512
+PEC box with 2000 random dielectric boxes and three dipoles, FP32.  Inputs
+are resident in HBM before the timed region; the timed region is K steps
+bracketed by stream synchronisation.  Prints ONE JSON line for the headline
+scheme (systolic when available, else plain), with the other scheme's
+figures alongside, a roofline object for the dominant kernel (per-launch
+device time from HIP events recorded on the library's stream inside the
+timed region) and the oracle timed on the host cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+# FP32 vector peak without FMA and without packed math: 256 CUs x 64 lanes x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+FLOPS_PER_CELL = 36            # 6 components x 6 flops (Section 2)
+PLAIN_E_BYTES, PLAIN_H_BYTES = 48, 36   # algorithmic bytes per cell, per half-step kernel
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from paper_2502_20610_amd import workloads as wl
+    if name == "c3":
+        return wl.c3_large_dielectric()
+    if name == "c2":
+        return wl.c2_periodic_dielectric()
+    if name == "c1":
+        return wl.c1_cavity_pulse()
+    if name.startswith("bare:"):
+        return wl.bare_bones(int(name.split(":")[1]))
+    raise SystemExit("unknown workload %r" % name)
+
+
+def run_scheme(w, scheme: str, steps: int, warmup: int):
+    import torch
+    from paper_2502_20610_amd import fdtd
+    stream = torch.cuda.current_stream()
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, stream=stream.cuda_stream)
+    try:
+        dev = torch.device("cuda:0")
+        sim.set_materials(torch.from_numpy(w.eps).to(dev))
+        if w.fields is not None:
+            sim.set_fields([torch.from_numpy(f).to(dev) for f in w.fields])
+        for s in w.sources:
+            sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"], s.get("first_step", 0))
+        torch.cuda.synchronize()
+        log("%s: warmup %d steps" % (scheme, warmup))
+        if warmup:
+            sim.step(warmup)
+        sim.synchronize()
+        sim.set_option(fdtd.OPT_PROFILE, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        stats = {k: sim.kernel_stats(k) for k in (fdtd.KERNEL_PLAIN_E, fdtd.KERNEL_PLAIN_H,
+                                                   fdtd.KERNEL_SOURCES, fdtd.KERNEL_SYSTOLIC)}
+        log("%s: %d steps in %.3f s" % (scheme, steps, t))
+        return t, stats
+    finally:
+        sim.close()
+
+
+def cpu_baseline(w, budget_s: float = 12.0):
+    """The FP32 oracle, as it stands, on a bounded centre crop of the workload."""
+    import oracle
+    nx, ny, nz = w.shape
+    cx, cy, cz = min(nx, 192), min(ny, 192), min(nz, 128)
+    ox, oy, oz = (nx - cx) // 2, (ny - cy) // 2, (nz - cz) // 2
+    eps = np.ascontiguousarray(w.eps[ox:ox + cx, oy:oy + cy, oz:oz + cz])
+    shape = (cx, cy, cz)
+    fields = tuple(np.zeros(shape, np.float32) for _ in range(6))
+    fields[2][cx // 2, cy // 2, cz // 2] = 1.0
+    cE = [oracle.round_f32(c) for c in oracle.coeff_E([eps] * 3, (0, 0, 0), w.dt, w.dx)]
+    cH = np.float32(w.dt / w.dx)
+    f = tuple(np.array(a) for a in fields)
+    t0 = time.perf_counter()
+    oracle.step(cE, cH, f, 2, dtype=np.float32)
+    per = (time.perf_counter() - t0) / 2
+    n = int(max(2, min(400, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.step(cE, cH, f, n, step0=2, dtype=np.float32)
+    t = time.perf_counter() - t0
+    cells = cx * cy * cz
+    return {"value": cells * n / t, "unit": "cell updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "FP32 oracle, %dx%dx%d centre crop of the workload's permittivity, PEC, "
+                      "%d steps (%.1f s)" % (cx, cy, cz, n, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=128)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--schemes", default="systolic,plain")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_20610_amd import fdtd
+    torch.cuda.set_device(0)
+    log("building workload %s" % args.workload)
+    w = make_workload(args.workload)
+    cells = w.cells
+    log("workload %s: %d cells, %d sources" % (w.name, cells, len(w.sources)))
+
+    results = {}
+    for scheme in args.schemes.split(","):
+        try:
+            t, stats = run_scheme(w, scheme, args.steps, args.warmup)
+        except fdtd.FdtdError as e:
+            if e.code == fdtd.FDTD_EUNSUPPORTED:
+                log("%s unavailable: %s" % (scheme, e))
+                continue
+            raise
+        results[scheme] = (t, stats)
+    if not results:
+        raise SystemExit("no scheme ran")
+    head = "systolic" if "systolic" in results else next(iter(results))
+    t, stats = results[head]
+    cups = cells * args.steps / t
+
+    if head == "systolic":
+        n, ms = stats[fdtd.KERNEL_SYSTOLIC]
+        avg_s = ms / 1e3 / max(n, 1)
+        steps_per_launch = args.steps / max(n, 1)
+        achieved = FLOPS_PER_CELL * cells * steps_per_launch / avg_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": None,
+                "kernel": "systolic_kernel", "launches": n, "avg_launch_ms": avg_s * 1e3}
+    else:
+        n, ms = stats[fdtd.KERNEL_PLAIN_E]
+        avg_s = ms / 1e3 / max(n, 1)
+        achieved = PLAIN_E_BYTES * cells / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "plain_E_kernel",
+                "launches": n, "avg_launch_ms": avg_s * 1e3}
+
+    out = {
+        "metric": "cell updates/s, systolic vs plain Yee FDTD, %dx%dx%d FP32" % w.shape,
+        "value": cups, "unit": "cell updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "shape": list(w.shape), "bc": list(w.bc),
+                   "sources": len(w.sources), "scheme": head},
+        "roofline": roof,
+    }
+    for scheme, (ts, st) in results.items():
+        c = cells * args.steps / ts
+        entry = {"cups": c, "ms_per_step": ts / args.steps * 1e3}
+        if scheme == "plain":
+            ne, mse = st[fdtd.KERNEL_PLAIN_E]
+            nh, msh = st[fdtd.KERNEL_PLAIN_H]
+            entry["E_avg_ms"] = mse / max(ne, 1)
+            entry["H_avg_ms"] = msh / max(nh, 1)
+            entry["hbm_frac_84B"] = c * 84 / (HBM_PEAK_GBS * 1e9)
+        out[scheme] = entry
+    if "plain" in results and "systolic" in results:
+        out["systolic_over_plain"] = out["systolic"]["cups"] / out["plain"]["cups"]
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) systolic 3D Yee FDTD library, libfdtd.so.
+ *
+ * The library advances Maxwell's equations with the Yee leapfrog scheme of the
+ * paper's Section 2, Eq. (1): for every cell, first the three E components are
+ * updated from backward differences of H, e.g.
+ *
+ *     Ex = (Ex + cEx*(Hz - Hz[j-1])) - cEx*(Hy - Hy[k-1]),
+ *
+ * (Ey, Ez by cyclic permutation), then point sources are added, then the three
+ * H components are updated from forward differences of the new E with
+ * Faraday's sign, e.g. Hx = (Hx - cH*(Ez[j+1] - Ez)) + cH*(Ey[k+1] - Ey).
+ * E is updated before H within a step as in the horizontal-bar scheme (caption
+ * of Fig. 7).  cE_c = dt/(eps_c*dx) per component and cell (the "structural
+ * fields" of Section 4), computed in double and rounded to float; cH = dt/dx
+ * (mu = 1).  Units are normalised, c = eps0 = mu0 = 1, as in Eq. (1).  Every
+ * arithmetic operation is a separately rounded FP32 operation, evaluated left
+ * to right as written, with no fused multiply-add; the results are therefore
+ * a single well-defined FP32 value per cell and step, independent of the
+ * scheme that computes them.
+ *
+ * Schemes:
+ *   FDTD_SCHEME_PLAIN    one kernel launch per half-step over the whole grid:
+ *                        the naive implementation of Section 2 / Fig. 1.
+ *   FDTD_SCHEME_SYSTOLIC one persistent launch per call: subdomain tiles stay
+ *                        resident on chip for many steps, move one cell along
+ *                        the x-y-z-t diagonal per step and exchange only their
+ *                        boundary faces through device memory, synchronising
+ *                        with neighbour flags (Sections 3 and 4).
+ *
+ * Layout: every field and coefficient array is FP32, C order [nx][ny][nz]
+ * (z fastest), one array per component (Ex, Ey, Ez, Hx, Hy, Hz).
+ *
+ * Boundaries: indices are periodic on every axis; a PEC axis additionally
+ * holds the two E components tangential to its planes at +0 on its index-0
+ * plane (cE = 0 there), which closes a perfectly conducting wall at 0 == n.
+ *
+ * Conventions for every function:
+ *   - returns FDTD_OK (0) or a negative FDTD_E* code; no exception or abort
+ *     crosses the ABI; fdtd_last_error() gives a message for the last failure;
+ *   - a context is not thread-safe; distinct contexts are independent;
+ *   - `where` says where a caller pointer lives: FDTD_HOST (read or written
+ *     before the call returns) or FDTD_DEVICE (a device pointer on the
+ *     context's device, accessed in order on the context's stream: the caller
+ *     keeps it alive until fdtd_synchronize());
+ *   - the library owns every allocation it makes and frees it in
+ *     fdtd_destroy();
+ *   - after FDTD_EHIP or FDTD_ETIMEOUT the context is poisoned: every later
+ *     call except fdtd_last_error/fdtd_destroy returns FDTD_ESTATE.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_ctx fdtd_ctx; /* opaque */
+
+enum {
+    FDTD_OK = 0,
+    FDTD_EINVAL = -1,      /* bad argument (sizes, ranges, Courant, PEC source) */
+    FDTD_ENOMEM = -2,      /* device or host allocation failed                  */
+    FDTD_EHIP = -3,        /* a HIP runtime call failed (message has the string)*/
+    FDTD_ESTATE = -4,      /* context poisoned, or call out of order            */
+    FDTD_EUNSUPPORTED = -5,/* valid request this build does not implement       */
+    FDTD_ETIMEOUT = -6     /* a bounded wait inside the systolic kernel expired */
+};
+
+enum { FDTD_BC_PEC = 0, FDTD_BC_PERIODIC = 1 };
+enum { FDTD_SCHEME_PLAIN = 0, FDTD_SCHEME_SYSTOLIC = 1 };
+enum { FDTD_FP32 = 0, FDTD_FP16_STORAGE = 1 };
+enum { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_HY = 4, FDTD_HZ = 5 };
+enum { FDTD_HOST = 0, FDTD_DEVICE = 1 };
+
+typedef struct {
+    uint32_t struct_size;  /* = sizeof(fdtd_config); versions the struct          */
+    int32_t nx, ny, nz;    /* cells per axis, each >= 1; nx*ny*nz <= 2^30         */
+    double dt, dx;         /* time step and uniform cell size (dx = dy = dz),
+                              both > 0, with dt*sqrt(3) < dx (Courant for eps>=1) */
+    int32_t bc[3];         /* FDTD_BC_PEC or FDTD_BC_PERIODIC for x, y, z        */
+    int32_t scheme;        /* FDTD_SCHEME_*                                      */
+    int32_t storage;       /* FDTD_FP32 (FDTD_FP16_STORAGE: FDTD_EUNSUPPORTED)   */
+    int32_t device;        /* HIP device ordinal                                 */
+    void* stream;          /* hipStream_t to run on; NULL = a stream the library
+                              creates (default priority) and destroys           */
+} fdtd_config;
+
+/* Create a simulation: validates cfg (FDTD_EINVAL before any HIP call),
+ * allocates the six field arrays and the three coefficient arrays on the
+ * device, zero-fills the fields and sets eps = 1 everywhere.  On success
+ * *out receives the context; on failure *out is NULL. */
+int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out);
+
+/* Free everything the context owns.  NULL is accepted.  Waits for the
+ * context's outstanding work first. */
+int fdtd_destroy(fdtd_ctx* ctx);
+
+/* Set the per-cell permittivity of each E component (the structural fields
+ * of Section 4): three arrays of nx*ny*nz floats, each >= 1 and finite (else
+ * FDTD_EINVAL, checked on host input; device input is checked on the
+ * device and reported at the next synchronising call).  The library
+ * computes cE_c = (float)(dt / ((double)eps_c * dx)) and zeroes it on the
+ * index-0 planes of PEC axes tangential to component c.  The arrays are
+ * copied; the caller keeps ownership. */
+int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
+                       const float* eps_z, int where);
+
+/* Set the components selected by comp_mask (bit c = component c) from
+ * src[c] (nx*ny*nz floats each; src entries for unselected components are
+ * ignored and may be NULL).  The fields are E^n and H^(n+1/2) of the current
+ * step count.  PEC-tangential E entries on index-0 planes are forced to +0. */
+int fdtd_set_fields(fdtd_ctx* ctx, uint32_t comp_mask, const float* const src[6], int where);
+
+/* Add a soft point source on E component comp (FDTD_EX..FDTD_EZ) at cell
+ * (i, j, k): in the step that starts at step count s, after the E half-step,
+ * E_comp[i][j][k] += waveform[s - first_step] for 0 <= s - first_step < len.
+ * The waveform is copied.  FDTD_EINVAL if the cell is out of range or lies on
+ * a PEC-frozen entry.  Returns the source id (>= 0) on success. */
+int fdtd_add_source(fdtd_ctx* ctx, int comp, int32_t i, int32_t j, int32_t k,
+                    const float* waveform, int64_t len, int64_t first_step, int where);
+
+/* Advance nsteps (>= 0) full Yee steps.  Asynchronous: work is queued on the
+ * context's stream.  The systolic scheme never falls back to another scheme;
+ * configurations it does not cover return FDTD_EUNSUPPORTED. */
+int fdtd_step(fdtd_ctx* ctx, int64_t nsteps);
+
+/* Copy the components selected by comp_mask into dst[c].  A host destination
+ * synchronises the stream before returning; a device destination is written
+ * in stream order. */
+int fdtd_read_fields(fdtd_ctx* ctx, uint32_t comp_mask, float* const dst[6], int where);
+
+/* Wait for all work queued on the context's stream; reports a watchdog
+ * timeout of the systolic kernel as FDTD_ETIMEOUT. */
+int fdtd_synchronize(fdtd_ctx* ctx);
+
+/* Number of completed steps since creation (queued steps count as done);
+ * -1 for a NULL context. */
+int64_t fdtd_current_step(const fdtd_ctx* ctx);
+
+/* Message describing the last failure of this context (never NULL).  With a
+ * NULL context, the message of the last failed fdtd_create on this thread. */
+const char* fdtd_last_error(const fdtd_ctx* ctx);
+
+/* Gradient of an objective with respect to permittivity (reverse-time
+ * adjoint).  Not implemented in this build: returns FDTD_EUNSUPPORTED. */
+int fdtd_adjoint(fdtd_ctx* ctx, const void* objective, float* grad_eps, int where);
+
+/* ---- tuning and measurement ------------------------------------------- */
+
+enum {
+    FDTD_OPT_SCHEME = 0,      /* switch scheme on a live context (state kept) */
+    FDTD_OPT_BAND_STEPS = 1,  /* systolic: steps each tile stays resident (>=1) */
+    FDTD_OPT_WORKGROUPS = 2,  /* systolic: persistent grid size, 0 = auto       */
+    FDTD_OPT_SPIN_LIMIT = 3,  /* systolic: polls before a wait times out        */
+    FDTD_OPT_PROFILE = 4      /* 1 = time every kernel launch with HIP events    */
+};
+
+/* Set a tuning option (see FDTD_OPT_*).  FDTD_EINVAL for unknown options or
+ * out-of-range values. */
+int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value);
+
+enum {
+    FDTD_KERNEL_PLAIN_E = 0,   /* plain E half-step                        */
+    FDTD_KERNEL_PLAIN_H = 1,   /* plain H half-step                        */
+    FDTD_KERNEL_SOURCES = 2,   /* plain-scheme point-source injection      */
+    FDTD_KERNEL_SYSTOLIC = 3,  /* persistent systolic kernel               */
+    FDTD_KERNEL_COUNT = 4
+};
+
+/* With FDTD_OPT_PROFILE on, the number of launches of a kernel and their
+ * total device time in milliseconds (HIP events on the context's stream).
+ * Synchronises the stream.  FDTD_OPT_PROFILE = 1 also resets the counters. */
+int fdtd_kernel_stats(fdtd_ctx* ctx, int kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_H */

@@ -1,0 +1,593 @@
+// Host runtime of libfdtd.so: context lifetime, validation, allocation, the
+// coefficient build, sources, field I/O, timing and dispatch to a scheme.
+// The public contract is include/fdtd.h.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "fdtd_internal.h"
+
+using namespace fdtd;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+constexpr int kThreads = 256;
+
+// cE_c = (float)(dt / ((double)eps * dx)), zero on the index-0 plane of every
+// PEC axis tangential to component `comp` (bc[a] == 0 means PEC).  The
+// division is IEEE double, so the rounded result is the same on any
+// conforming machine.  Bad permittivity (< 1 or not finite) sets bit 0 of
+// *err.
+__global__ void build_coef_kernel(const float* __restrict__ eps, float* __restrict__ out, int comp,
+                                  int nx, int ny, int nz, int bcx, int bcy, int bcz, double dt,
+                                  double dx, int* err)
+{
+    const long long n = (long long)nx * ny * nz;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        int k = (int)(p % nz);
+        long long r = p / nz;
+        int j = (int)(r % ny);
+        int i = (int)(r / ny);
+        float e = eps[p];
+        if (!(e >= 1.0f) || !(e <= 3.0e38f)) atomicOr(err, 1);
+        double c = dt / ((double)e * dx);
+        if ((comp != 0 && bcx == FDTD_BC_PEC && i == 0) || (comp != 1 && bcy == FDTD_BC_PEC && j == 0) ||
+            (comp != 2 && bcz == FDTD_BC_PEC && k == 0))
+            c = 0.0;
+        out[p] = (float)c;
+    }
+}
+
+// Force the PEC-tangential entries of E component `comp` to +0.
+__global__ void zero_pec_kernel(float* __restrict__ f, int comp, int nx, int ny, int nz, int bcx,
+                                int bcy, int bcz)
+{
+    // three planes at most; one thread per element of the largest plane
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // plane normal to x (i = 0): ny*nz entries
+    if (comp != 0 && bcx == FDTD_BC_PEC && t < (long long)ny * nz) f[t] = 0.0f;
+    // plane normal to y (j = 0): nx*nz entries
+    if (comp != 1 && bcy == FDTD_BC_PEC && t < (long long)nx * nz) {
+        long long i = t / nz, k = t % nz;
+        f[(i * ny) * nz + k] = 0.0f;
+    }
+    // plane normal to z (k = 0): nx*ny entries
+    if (comp != 2 && bcz == FDTD_BC_PEC && t < (long long)nx * ny) f[t * nz] = 0.0f;
+}
+
+__global__ void sources_kernel(float* Ex, float* Ey, float* Ez, const DevSource* __restrict__ src,
+                               int nsrc, long long s, int ny, int nz)
+{
+    // One thread; sources are applied in table order (several sources on one
+    // cell add up in the same order as in any other scheme).
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int q = 0; q < nsrc; ++q) {
+        long long m = s - src[q].first;
+        if (m < 0 || m >= src[q].len) continue;
+        float* f = src[q].comp == 0 ? Ex : (src[q].comp == 1 ? Ey : Ez);
+        long long p = ((long long)src[q].i * ny + src[q].j) * nz + src[q].k;
+        f[p] = f[p] + src[q].wave[m];
+    }
+}
+
+bool ok_ptr(const void* p) { return p != nullptr; }
+
+int check_live(fdtd_ctx* ctx)
+{
+    if (!ctx) return FDTD_EINVAL;
+    if (ctx->poisoned) {
+        return FDTD_ESTATE;
+    }
+    return FDTD_OK;
+}
+
+hipMemcpyKind kind_from(int where, bool to_device)
+{
+    if (where == FDTD_DEVICE) return hipMemcpyDeviceToDevice;
+    return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+}
+
+int collect_timings(fdtd_ctx* ctx)
+{
+    for (auto& t : ctx->pending) {
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, t.start, t.stop);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+        ctx->launches[t.kernel] += 1;
+        ctx->total_ms[t.kernel] += ms;
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    ctx->pending.clear();
+    return FDTD_OK;
+}
+
+int check_device_error(fdtd_ctx* ctx)
+{
+    int h = 0;
+    hipError_t e = hipMemcpy(&h, ctx->dev_error, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(error word)");
+    if (h & 2) {
+        ctx->poisoned = true;
+        return fail(ctx, FDTD_ETIMEOUT,
+                    "systolic kernel: a neighbour-flag wait exceeded the spin limit");
+    }
+    if (h & 1) {
+        int z = 0;
+        (void)hipMemcpy(ctx->dev_error, &z, sizeof(int), hipMemcpyHostToDevice);
+        return fail(ctx, FDTD_EINVAL, "set_materials: permittivity < 1 or not finite (device input)");
+    }
+    return FDTD_OK;
+}
+
+int rebuild_dev_sources(fdtd_ctx* ctx)
+{
+    if (ctx->dev_sources) {
+        (void)hipFree(ctx->dev_sources);
+        ctx->dev_sources = nullptr;
+    }
+    ctx->dev_sources_n = (int)ctx->sources.size();
+    if (ctx->sources.empty()) return FDTD_OK;
+    std::vector<DevSource> h(ctx->sources.size());
+    for (size_t q = 0; q < ctx->sources.size(); ++q) {
+        const SourceRec& s = ctx->sources[q];
+        h[q] = DevSource{s.comp, s.i, s.j, s.k, (long long)s.len, (long long)s.first, s.wave};
+    }
+    hipError_t e = hipMalloc(&ctx->dev_sources, h.size() * sizeof(DevSource));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(sources)");
+    e = hipMemcpyAsync(ctx->dev_sources, h.data(), h.size() * sizeof(DevSource),
+                       hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(sources)");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    return FDTD_OK;
+}
+
+int grid_for(long long n)
+{
+    long long g = (n + kThreads - 1) / kThreads;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+namespace fdtd {
+
+int fail(fdtd_ctx* ctx, int code, const std::string& msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+int hip_fail(fdtd_ctx* ctx, hipError_t e, const char* what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    if (ctx) ctx->poisoned = true;
+    return fail(ctx, FDTD_EHIP, msg);
+}
+
+void timing_begin(fdtd_ctx* ctx, int kernel, PendingTiming* t)
+{
+    t->kernel = -1;
+    if (!ctx->profile) return;
+    if (hipEventCreate(&t->start) != hipSuccess) return;
+    if (hipEventCreate(&t->stop) != hipSuccess) {
+        (void)hipEventDestroy(t->start);
+        return;
+    }
+    t->kernel = kernel;
+    (void)hipEventRecord(t->start, ctx->stream);
+}
+
+void timing_end(fdtd_ctx* ctx, PendingTiming* t)
+{
+    if (t->kernel < 0) return;
+    (void)hipEventRecord(t->stop, ctx->stream);
+    ctx->pending.push_back(*t);
+}
+
+bool sources_active(const fdtd_ctx* ctx, int64_t s)
+{
+    for (const auto& q : ctx->sources)
+        if (s - q.first >= 0 && s - q.first < q.len) return true;
+    return false;
+}
+
+int launch_sources(fdtd_ctx* ctx, int64_t s)
+{
+    PendingTiming t;
+    timing_begin(ctx, FDTD_KERNEL_SOURCES, &t);
+    hipLaunchKernelGGL(sources_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->field[0],
+                       ctx->field[1], ctx->field[2], ctx->dev_sources, ctx->dev_sources_n,
+                       (long long)s, ctx->ny, ctx->nz);
+    timing_end(ctx, &t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch(sources)");
+    return FDTD_OK;
+}
+
+}  // namespace fdtd
+
+extern "C" {
+
+int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
+{
+    if (!out) return fail(nullptr, FDTD_EINVAL, "fdtd_create: out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, FDTD_EINVAL, "fdtd_create: cfg is NULL");
+    if (cfg->struct_size != sizeof(fdtd_config))
+        return fail(nullptr, FDTD_EINVAL, "fdtd_create: struct_size != sizeof(fdtd_config)");
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
+        return fail(nullptr, FDTD_EINVAL, "fdtd_create: every dimension must be >= 1");
+    const int64_t ncell = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    if (ncell > (int64_t(1) << 30))
+        return fail(nullptr, FDTD_EINVAL, "fdtd_create: nx*ny*nz must be <= 2^30");
+    if (!(cfg->dt > 0.0) || !(cfg->dx > 0.0) || !isfinite(cfg->dt) || !isfinite(cfg->dx))
+        return fail(nullptr, FDTD_EINVAL, "fdtd_create: dt and dx must be finite and > 0");
+    if (!(cfg->dt * sqrt(3.0) < cfg->dx))
+        return fail(nullptr, FDTD_EINVAL, "fdtd_create: Courant condition dt*sqrt(3) < dx violated");
+    for (int a = 0; a < 3; ++a)
+        if (cfg->bc[a] != FDTD_BC_PEC && cfg->bc[a] != FDTD_BC_PERIODIC)
+            return fail(nullptr, FDTD_EINVAL, "fdtd_create: bc must be FDTD_BC_PEC or FDTD_BC_PERIODIC");
+    if (cfg->scheme != FDTD_SCHEME_PLAIN && cfg->scheme != FDTD_SCHEME_SYSTOLIC)
+        return fail(nullptr, FDTD_EINVAL, "fdtd_create: unknown scheme");
+    if (cfg->storage != FDTD_FP32 && cfg->storage != FDTD_FP16_STORAGE)
+        return fail(nullptr, FDTD_EINVAL, "fdtd_create: unknown storage");
+    if (cfg->storage == FDTD_FP16_STORAGE)
+        return fail(nullptr, FDTD_EUNSUPPORTED, "fdtd_create: FP16 storage is not implemented");
+    if (cfg->device < 0) return fail(nullptr, FDTD_EINVAL, "fdtd_create: device must be >= 0");
+
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) return fail(nullptr, FDTD_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+
+    fdtd_ctx* ctx = new (std::nothrow) fdtd_ctx();
+    if (!ctx) return fail(nullptr, FDTD_ENOMEM, "fdtd_create: host allocation failed");
+    ctx->cfg = *cfg;
+    ctx->nx = cfg->nx;
+    ctx->ny = cfg->ny;
+    ctx->nz = cfg->nz;
+    ctx->ncell = ncell;
+    ctx->device = cfg->device;
+    ctx->scheme = cfg->scheme;
+    ctx->band_steps = 0;  // 0 = choose per call
+    ctx->workgroups = 0;
+    ctx->spin_limit = int64_t(1) << 26;
+    ctx->profile = false;
+    ctx->cH = (float)(cfg->dt / cfg->dx);
+    ctx->err = "no error";
+
+    auto bail = [&](int code) {
+        fdtd_destroy(ctx);
+        return code;
+    };
+    if (cfg->stream) {
+        ctx->stream = (hipStream_t)cfg->stream;
+        ctx->own_stream = false;
+    } else {
+        e = hipStreamCreate(&ctx->stream);
+        if (e != hipSuccess) {
+            fail(nullptr, FDTD_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+            delete ctx;
+            return FDTD_EHIP;
+        }
+        ctx->own_stream = true;
+    }
+    const size_t bytes = (size_t)ncell * sizeof(float);
+    for (int c = 0; c < 6; ++c) {
+        e = hipMalloc(&ctx->field[c], bytes);
+        if (e != hipSuccess) {
+            fail(nullptr, FDTD_ENOMEM, std::string("hipMalloc(field): ") + hipGetErrorString(e));
+            return bail(FDTD_ENOMEM);
+        }
+        e = hipMemsetAsync(ctx->field[c], 0, bytes, ctx->stream);
+        if (e != hipSuccess) {
+            fail(nullptr, FDTD_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+            return bail(FDTD_EHIP);
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        e = hipMalloc(&ctx->coef[c], bytes);
+        if (e != hipSuccess) {
+            fail(nullptr, FDTD_ENOMEM, std::string("hipMalloc(coef): ") + hipGetErrorString(e));
+            return bail(FDTD_ENOMEM);
+        }
+    }
+    e = hipMalloc(&ctx->dev_error, sizeof(int));
+    if (e != hipSuccess) {
+        fail(nullptr, FDTD_ENOMEM, std::string("hipMalloc(error): ") + hipGetErrorString(e));
+        return bail(FDTD_ENOMEM);
+    }
+    e = hipMemsetAsync(ctx->dev_error, 0, sizeof(int), ctx->stream);
+    if (e != hipSuccess) {
+        fail(nullptr, FDTD_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+        return bail(FDTD_EHIP);
+    }
+    // eps = 1 everywhere: build the coefficients from a device array of ones
+    float* ones = nullptr;
+    e = hipMalloc(&ones, bytes);
+    if (e != hipSuccess) {
+        fail(nullptr, FDTD_ENOMEM, std::string("hipMalloc(eps): ") + hipGetErrorString(e));
+        return bail(FDTD_ENOMEM);
+    }
+    // fill with 1.0f: 0x3f800000
+    e = hipMemsetD32Async((hipDeviceptr_t)ones, 0x3f800000, (size_t)ncell, ctx->stream);
+    if (e == hipSuccess) {
+        for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+            hipLaunchKernelGGL(build_coef_kernel, dim3(grid_for(ncell)), dim3(kThreads), 0, ctx->stream,
+                               ones, ctx->coef[c], c, ctx->nx, ctx->ny, ctx->nz, cfg->bc[0],
+                               cfg->bc[1], cfg->bc[2], cfg->dt, cfg->dx, ctx->dev_error);
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ones);
+    if (e != hipSuccess) {
+        fail(nullptr, FDTD_EHIP, std::string("fdtd_create init: ") + hipGetErrorString(e));
+        return bail(FDTD_EHIP);
+    }
+    *out = ctx;
+    return FDTD_OK;
+}
+
+int fdtd_destroy(fdtd_ctx* ctx)
+{
+    if (!ctx) return FDTD_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& t : ctx->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    ctx->pending.clear();
+    systolic_release(ctx);
+    for (int c = 0; c < 6; ++c)
+        if (ctx->field[c]) (void)hipFree(ctx->field[c]);
+    for (int c = 0; c < 3; ++c)
+        if (ctx->coef[c]) (void)hipFree(ctx->coef[c]);
+    for (auto& s : ctx->sources)
+        if (s.wave) (void)hipFree(s.wave);
+    if (ctx->dev_sources) (void)hipFree(ctx->dev_sources);
+    if (ctx->dev_error) (void)hipFree(ctx->dev_error);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return FDTD_OK;
+}
+
+int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y, const float* eps_z,
+                       int where)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (where != FDTD_HOST && where != FDTD_DEVICE) return fail(ctx, FDTD_EINVAL, "bad `where`");
+    const float* eps[3] = {eps_x, eps_y, eps_z};
+    for (int c = 0; c < 3; ++c)
+        if (!ok_ptr(eps[c])) return fail(ctx, FDTD_EINVAL, "set_materials: NULL array");
+    if (where == FDTD_HOST) {
+        for (int c = 0; c < 3; ++c)
+            for (int64_t p = 0; p < ctx->ncell; ++p) {
+                float v = eps[c][p];
+                if (!(v >= 1.0f) || !(v <= 3.0e38f))
+                    return fail(ctx, FDTD_EINVAL, "set_materials: permittivity < 1 or not finite");
+            }
+    }
+    (void)hipSetDevice(ctx->device);
+    const size_t bytes = (size_t)ctx->ncell * sizeof(float);
+    float* stage = nullptr;
+    if (where == FDTD_HOST) {
+        hipError_t e = hipMalloc(&stage, bytes);
+        if (e != hipSuccess) return fail(ctx, FDTD_ENOMEM, "set_materials: staging allocation failed");
+    }
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        const float* src = eps[c];
+        if (where == FDTD_HOST) {
+            e = hipMemcpyAsync(stage, eps[c], bytes, hipMemcpyHostToDevice, ctx->stream);
+            src = stage;
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(build_coef_kernel, dim3(grid_for(ctx->ncell)), dim3(kThreads), 0,
+                               ctx->stream, src, ctx->coef[c], c, ctx->nx, ctx->ny, ctx->nz,
+                               ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2], ctx->cfg.dt,
+                               ctx->cfg.dx, ctx->dev_error);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+    }
+    if (stage) {
+        hipError_t e2 = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess) e = e2;
+        (void)hipFree(stage);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_materials");
+    return FDTD_OK;
+}
+
+int fdtd_set_fields(fdtd_ctx* ctx, uint32_t comp_mask, const float* const src[6], int where)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (where != FDTD_HOST && where != FDTD_DEVICE) return fail(ctx, FDTD_EINVAL, "bad `where`");
+    if (comp_mask & ~0x3Fu) return fail(ctx, FDTD_EINVAL, "set_fields: comp_mask has bits above 5");
+    if (comp_mask && !src) return fail(ctx, FDTD_EINVAL, "set_fields: src is NULL");
+    for (int c = 0; c < 6; ++c)
+        if ((comp_mask >> c & 1u) && !src[c]) return fail(ctx, FDTD_EINVAL, "set_fields: NULL array");
+    (void)hipSetDevice(ctx->device);
+    const size_t bytes = (size_t)ctx->ncell * sizeof(float);
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 6 && e == hipSuccess; ++c) {
+        if (!(comp_mask >> c & 1u)) continue;
+        e = hipMemcpyAsync(ctx->field[c], src[c], bytes, kind_from(where, true), ctx->stream);
+        if (e == hipSuccess && c < 3) {
+            long long m = (long long)ctx->ny * ctx->nz;
+            m = m > (long long)ctx->nx * ctx->nz ? m : (long long)ctx->nx * ctx->nz;
+            m = m > (long long)ctx->nx * ctx->ny ? m : (long long)ctx->nx * ctx->ny;
+            hipLaunchKernelGGL(zero_pec_kernel, dim3((unsigned)((m + kThreads - 1) / kThreads)),
+                               dim3(kThreads), 0, ctx->stream, ctx->field[c], c, ctx->nx, ctx->ny,
+                               ctx->nz, ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2]);
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_fields");
+    return FDTD_OK;
+}
+
+int fdtd_add_source(fdtd_ctx* ctx, int comp, int32_t i, int32_t j, int32_t k, const float* waveform,
+                    int64_t len, int64_t first_step, int where)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (where != FDTD_HOST && where != FDTD_DEVICE) return fail(ctx, FDTD_EINVAL, "bad `where`");
+    if (comp < FDTD_EX || comp > FDTD_EZ) return fail(ctx, FDTD_EINVAL, "add_source: comp must be Ex, Ey or Ez");
+    if (i < 0 || i >= ctx->nx || j < 0 || j >= ctx->ny || k < 0 || k >= ctx->nz)
+        return fail(ctx, FDTD_EINVAL, "add_source: cell out of range");
+    if (len < 1 || !waveform) return fail(ctx, FDTD_EINVAL, "add_source: empty waveform");
+    if (first_step < 0) return fail(ctx, FDTD_EINVAL, "add_source: first_step must be >= 0");
+    const int coord[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a)
+        if (a != comp && ctx->cfg.bc[a] == FDTD_BC_PEC && coord[a] == 0)
+            return fail(ctx, FDTD_EINVAL, "add_source: cell lies on a PEC-frozen entry");
+    (void)hipSetDevice(ctx->device);
+    SourceRec s{comp, i, j, k, len, first_step, nullptr};
+    hipError_t e = hipMalloc(&s.wave, (size_t)len * sizeof(float));
+    if (e != hipSuccess) return fail(ctx, FDTD_ENOMEM, "add_source: allocation failed");
+    e = hipMemcpyAsync(s.wave, waveform, (size_t)len * sizeof(float), kind_from(where, true), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(s.wave);
+        return hip_fail(ctx, e, "add_source copy");
+    }
+    ctx->sources.push_back(s);
+    rc = rebuild_dev_sources(ctx);
+    if (rc) return rc;
+    return (int)ctx->sources.size() - 1;
+}
+
+int fdtd_step(fdtd_ctx* ctx, int64_t nsteps)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (nsteps < 0) return fail(ctx, FDTD_EINVAL, "step: nsteps must be >= 0");
+    if (nsteps == 0) return FDTD_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->scheme == FDTD_SCHEME_PLAIN) return plain_step(ctx, nsteps);
+    std::string why;
+    if (!systolic_supported(ctx, &why)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: " + why);
+    return systolic_step(ctx, nsteps);
+}
+
+int fdtd_read_fields(fdtd_ctx* ctx, uint32_t comp_mask, float* const dst[6], int where)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (where != FDTD_HOST && where != FDTD_DEVICE) return fail(ctx, FDTD_EINVAL, "bad `where`");
+    if (comp_mask & ~0x3Fu) return fail(ctx, FDTD_EINVAL, "read_fields: comp_mask has bits above 5");
+    if (comp_mask && !dst) return fail(ctx, FDTD_EINVAL, "read_fields: dst is NULL");
+    for (int c = 0; c < 6; ++c)
+        if ((comp_mask >> c & 1u) && !dst[c]) return fail(ctx, FDTD_EINVAL, "read_fields: NULL array");
+    (void)hipSetDevice(ctx->device);
+    const size_t bytes = (size_t)ctx->ncell * sizeof(float);
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 6 && e == hipSuccess; ++c)
+        if (comp_mask >> c & 1u)
+            e = hipMemcpyAsync(dst[c], ctx->field[c], bytes, kind_from(where, false), ctx->stream);
+    if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read_fields");
+    if (where == FDTD_HOST) return check_device_error(ctx);
+    return FDTD_OK;
+}
+
+int fdtd_synchronize(fdtd_ctx* ctx)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    return check_device_error(ctx);
+}
+
+int64_t fdtd_current_step(const fdtd_ctx* ctx) { return ctx ? ctx->step_count : -1; }
+
+const char* fdtd_last_error(const fdtd_ctx* ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+int fdtd_adjoint(fdtd_ctx* ctx, const void* objective, float* grad_eps, int where)
+{
+    (void)objective;
+    (void)grad_eps;
+    (void)where;
+    if (!ctx) return FDTD_EINVAL;
+    return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: not implemented in this build");
+}
+
+int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    switch (option) {
+    case FDTD_OPT_SCHEME:
+        if (value != FDTD_SCHEME_PLAIN && value != FDTD_SCHEME_SYSTOLIC)
+            return fail(ctx, FDTD_EINVAL, "set_option: unknown scheme");
+        ctx->scheme = (int)value;
+        return FDTD_OK;
+    case FDTD_OPT_BAND_STEPS:
+        if (value < 0 || value > 4096) return fail(ctx, FDTD_EINVAL, "set_option: band steps out of range");
+        ctx->band_steps = (int)value;
+        return FDTD_OK;
+    case FDTD_OPT_WORKGROUPS:
+        if (value < 0 || value > (1 << 20)) return fail(ctx, FDTD_EINVAL, "set_option: workgroups out of range");
+        ctx->workgroups = (int)value;
+        return FDTD_OK;
+    case FDTD_OPT_SPIN_LIMIT:
+        if (value < 1) return fail(ctx, FDTD_EINVAL, "set_option: spin limit must be >= 1");
+        ctx->spin_limit = value;
+        return FDTD_OK;
+    case FDTD_OPT_PROFILE:
+        if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: profile is 0 or 1");
+        if (value == 1) {
+            rc = collect_timings(ctx);
+            if (rc) return rc;
+            for (int k = 0; k < FDTD_KERNEL_COUNT; ++k) {
+                ctx->launches[k] = 0;
+                ctx->total_ms[k] = 0.0;
+            }
+        }
+        ctx->profile = value == 1;
+        return FDTD_OK;
+    default:
+        return fail(ctx, FDTD_EINVAL, "set_option: unknown option");
+    }
+}
+
+int fdtd_kernel_stats(fdtd_ctx* ctx, int kernel, int64_t* launches, double* total_ms)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (kernel < 0 || kernel >= FDTD_KERNEL_COUNT) return fail(ctx, FDTD_EINVAL, "kernel_stats: bad kernel id");
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    rc = collect_timings(ctx);
+    if (rc) return rc;
+    if (launches) *launches = ctx->launches[kernel];
+    if (total_ms) *total_ms = ctx->total_ms[kernel];
+    return FDTD_OK;
+}
+
+}  // extern "C"

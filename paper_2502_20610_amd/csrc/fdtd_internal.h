@@ -1,0 +1,104 @@
+// Internal declarations shared by the translation units of libfdtd.so.
+// Not part of the public ABI (see include/fdtd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fdtd.h"
+
+namespace fdtd {
+
+// One soft point source: E_comp[cell] += wave[s - first] during the step that
+// starts at step count s.
+struct SourceRec {
+    int comp;
+    int i, j, k;
+    int64_t len;
+    int64_t first;
+    float* wave;  // device copy of the waveform
+};
+
+// Device-side source table entry (plain scheme and systolic kernel).
+struct DevSource {
+    int comp;
+    int i, j, k;
+    long long len;
+    long long first;
+    const float* wave;
+};
+
+struct PendingTiming {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
+struct SystolicState;  // defined in systolic.hip
+
+}  // namespace fdtd
+
+struct fdtd_ctx {
+    fdtd_config cfg;
+    int nx, ny, nz;
+    int64_t ncell;
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+
+    float* field[6];  // Ex Ey Ez Hx Hy Hz
+    float* coef[3];   // cEx cEy cEz
+    float cH;
+
+    std::vector<fdtd::SourceRec> sources;
+    fdtd::DevSource* dev_sources;  // device table, rebuilt when sources change
+    int dev_sources_n;
+
+    int64_t step_count;
+    bool poisoned;
+    std::string err;
+
+    // options
+    int scheme;
+    int band_steps;
+    int workgroups;
+    int64_t spin_limit;
+    bool profile;
+
+    // kernel timing
+    std::vector<fdtd::PendingTiming> pending;
+    int64_t launches[FDTD_KERNEL_COUNT];
+    double total_ms[FDTD_KERNEL_COUNT];
+
+    int* dev_error;  // device error word: bit 0 bad eps, bit 1 watchdog timeout
+
+    fdtd::SystolicState* sys;
+};
+
+namespace fdtd {
+
+// Error helpers (set ctx->err, return the code).
+int fail(fdtd_ctx* ctx, int code, const std::string& msg);
+int hip_fail(fdtd_ctx* ctx, hipError_t e, const char* what);
+
+// Timing wrappers around a launch on ctx->stream (no-ops when profiling is off).
+void timing_begin(fdtd_ctx* ctx, int kernel, PendingTiming* t);
+void timing_end(fdtd_ctx* ctx, PendingTiming* t);
+
+// Plain scheme: advance n steps starting at ctx->step_count (plain.hip).
+int plain_step(fdtd_ctx* ctx, int64_t nsteps);
+
+// Systolic scheme (systolic.hip).
+int systolic_supported(const fdtd_ctx* ctx, std::string* why);
+int systolic_step(fdtd_ctx* ctx, int64_t nsteps);
+void systolic_release(fdtd_ctx* ctx);
+
+// Launch the source-injection kernel for the step that starts at step count s.
+int launch_sources(fdtd_ctx* ctx, int64_t s);
+
+// True if any source is active in the step starting at step count s.
+bool sources_active(const fdtd_ctx* ctx, int64_t s);
+
+}  // namespace fdtd

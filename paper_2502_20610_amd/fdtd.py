@@ -1,0 +1,255 @@
+"""Thin ctypes binding over libfdtd.so (the C ABI declared in include/fdtd.h).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  Host arrays are numpy float32; device buffers are torch CUDA
+(HIP) tensors, passed by pointer with ``where=FDTD_DEVICE``.  PyTorch is used
+for device memory and streams only.
+
+The library is loaded from this package's directory; if it has not been
+built, loading raises immediately (there is no fallback of any kind).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdtd.so")
+
+FDTD_OK, FDTD_EINVAL, FDTD_ENOMEM, FDTD_EHIP, FDTD_ESTATE, FDTD_EUNSUPPORTED, FDTD_ETIMEOUT = \
+    0, -1, -2, -3, -4, -5, -6
+ERROR_NAMES = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ENOMEM", -3: "FDTD_EHIP",
+               -4: "FDTD_ESTATE", -5: "FDTD_EUNSUPPORTED", -6: "FDTD_ETIMEOUT"}
+BC_PEC, BC_PERIODIC = 0, 1
+SCHEME_PLAIN, SCHEME_SYSTOLIC = 0, 1
+FP32, FP16_STORAGE = 0, 1
+HOST, DEVICE = 0, 1
+OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE = range(5)
+KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC = range(4)
+SCHEMES = {"plain": SCHEME_PLAIN, "systolic": SCHEME_SYSTOLIC}
+
+# every symbol the header declares
+EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_fields",
+           "fdtd_add_source", "fdtd_step", "fdtd_read_fields", "fdtd_synchronize",
+           "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
+           "fdtd_kernel_stats")
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERROR_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("dt", ctypes.c_double), ("dx", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 3), ("scheme", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libfdtd.so and declare its signatures; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfdtd.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    fp = ctypes.POINTER(ctypes.c_float)
+    sig = {
+        "fdtd_create": ([ctypes.POINTER(Config), ctypes.POINTER(vp)], ctypes.c_int),
+        "fdtd_destroy": ([vp], ctypes.c_int),
+        "fdtd_set_materials": ([vp, vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "fdtd_set_fields": ([vp, u32, ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+        "fdtd_add_source": ([vp, ctypes.c_int, i32, i32, i32, vp, i64, i64, ctypes.c_int],
+                            ctypes.c_int),
+        "fdtd_step": ([vp, i64], ctypes.c_int),
+        "fdtd_read_fields": ([vp, u32, ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+        "fdtd_synchronize": ([vp], ctypes.c_int),
+        "fdtd_current_step": ([vp], i64),
+        "fdtd_last_error": ([vp], ctypes.c_char_p),
+        "fdtd_adjoint": ([vp, vp, fp, ctypes.c_int], ctypes.c_int),
+        "fdtd_set_option": ([vp, ctypes.c_int, i64], ctypes.c_int),
+        "fdtd_kernel_stats": ([vp, ctypes.c_int, ctypes.POINTER(i64),
+                               ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _pointer(a, ncell: int):
+    """(pointer, where, keepalive) for a numpy array or a torch CUDA tensor."""
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.float32 or a.numel() != ncell or not a.is_contiguous():
+            raise ValueError("device arrays must be contiguous float32 with %d elements" % ncell)
+        if not a.is_cuda:
+            a = a.numpy()
+        else:
+            return ctypes.c_void_p(a.data_ptr()), DEVICE, a
+    arr = np.ascontiguousarray(a, dtype=np.float32)
+    if arr.size != ncell:
+        raise ValueError("host arrays must have %d elements" % ncell)
+    return ctypes.c_void_p(arr.ctypes.data), HOST, arr
+
+
+class Simulation:
+    """One FDTD context.  ``shape`` = (nx, ny, nz); ``bc`` per axis 0 = PEC, 1 = periodic."""
+
+    def __init__(self, shape: Sequence[int], dt: float = 0.5, dx: float = 1.0,
+                 bc: Sequence[int] = (0, 0, 0), scheme: str = "plain", device: int = 0,
+                 stream: Optional[int] = None):
+        self._lib = load_library()
+        self.shape = tuple(int(s) for s in shape)
+        self.ncell = self.shape[0] * self.shape[1] * self.shape[2]
+        cfg = Config()
+        cfg.struct_size = ctypes.sizeof(Config)
+        cfg.nx, cfg.ny, cfg.nz = self.shape
+        cfg.dt, cfg.dx = float(dt), float(dx)
+        for a in range(3):
+            cfg.bc[a] = int(bc[a])
+        cfg.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        cfg.storage = FP32
+        cfg.device = int(device)
+        cfg.stream = ctypes.c_void_p(stream) if stream else None
+        h = ctypes.c_void_p()
+        rc = self._lib.fdtd_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != FDTD_OK:
+            raise FdtdError(rc, self._lib.fdtd_last_error(None).decode())
+        self._h = h
+
+    # -- helpers ------------------------------------------------------------
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise FdtdError(rc, self._lib.fdtd_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fdtd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- API ------------------------------------------------------------------
+    def set_materials(self, eps_x, eps_y=None, eps_z=None):
+        eps_y = eps_x if eps_y is None else eps_y
+        eps_z = eps_x if eps_z is None else eps_z
+        ptrs = [_pointer(e, self.ncell) for e in (eps_x, eps_y, eps_z)]
+        wheres = {p[1] for p in ptrs}
+        if len(wheres) != 1:
+            raise ValueError("all permittivity arrays must live on the same side")
+        self._check(self._lib.fdtd_set_materials(self._h, ptrs[0][0], ptrs[1][0], ptrs[2][0],
+                                                 ptrs[0][1]))
+
+    def set_fields(self, fields, mask: Optional[int] = None):
+        """``fields``: six arrays (None entries skipped) in (Ex..Hz) order."""
+        arr = (ctypes.c_void_p * 6)()
+        keep, where, m = [], None, 0
+        for c, f in enumerate(fields):
+            if f is None:
+                continue
+            p, w, k = _pointer(f, self.ncell)
+            if where is not None and w != where:
+                raise ValueError("all field arrays must live on the same side")
+            where = w
+            arr[c] = p
+            keep.append(k)
+            m |= 1 << c
+        if mask is not None:
+            m &= mask
+        self._check(self._lib.fdtd_set_fields(self._h, m, arr, HOST if where is None else where))
+
+    def add_source(self, comp: int, i: int, j: int, k: int, waveform, first_step: int = 0) -> int:
+        w = np.ascontiguousarray(waveform, dtype=np.float32)
+        return self._check(self._lib.fdtd_add_source(self._h, int(comp), int(i), int(j), int(k),
+                                                     ctypes.c_void_p(w.ctypes.data), int(w.size),
+                                                     int(first_step), HOST))
+
+    def step(self, nsteps: int):
+        self._check(self._lib.fdtd_step(self._h, int(nsteps)))
+
+    def read_fields(self, mask: int = 0x3F, out=None):
+        """Return a tuple of six arrays (None where not selected).  With ``out``
+        (six torch CUDA tensors) the copy is device-to-device in stream order."""
+        arr = (ctypes.c_void_p * 6)()
+        res = [None] * 6
+        where = HOST
+        for c in range(6):
+            if not (mask >> c) & 1:
+                continue
+            if out is not None:
+                p, where, k = _pointer(out[c], self.ncell)
+                res[c] = out[c]
+            else:
+                k = np.empty(self.shape, dtype=np.float32)
+                p = ctypes.c_void_p(k.ctypes.data)
+                res[c] = k
+            arr[c] = p
+        self._check(self._lib.fdtd_read_fields(self._h, mask, arr, where))
+        return tuple(res)
+
+    def synchronize(self):
+        self._check(self._lib.fdtd_synchronize(self._h))
+
+    @property
+    def current_step(self) -> int:
+        return int(self._lib.fdtd_current_step(self._h))
+
+    def set_option(self, option: int, value: int):
+        self._check(self._lib.fdtd_set_option(self._h, int(option), int(value)))
+
+    def kernel_stats(self, kernel: int):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        self._check(self._lib.fdtd_kernel_stats(self._h, int(kernel), ctypes.byref(n),
+                                                ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    def adjoint(self):
+        self._check(self._lib.fdtd_adjoint(self._h, None, None, HOST))
+
+
+def run_workload(w, scheme: str = "plain", nsteps: Optional[int] = None, device: int = 0,
+                 options=None):
+    """Run a workloads.Workload through the library and return the six fields (host)."""
+    sim = Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, device=device)
+    try:
+        for k, v in (options or {}).items():
+            sim.set_option(k, v)
+        sim.set_materials(w.eps)
+        if w.fields is not None:
+            sim.set_fields(w.fields)
+        for s in w.sources:
+            sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"], s.get("first_step", 0))
+        sim.step(w.nsteps if nsteps is None else nsteps)
+        return sim.read_fields()
+    finally:
+        sim.close()

@@ -1,0 +1,93 @@
+"""CPU checks of the systolic schedule (plan, dependencies, data flow).
+
+The emulator in tests/systolic_emulator.py runs the tile tickets as
+interleaved coroutines with the kernel's waits; with every interleaving the
+result must be bit-identical to the FP32 oracle, because the scheme performs
+exactly the same update equations in an order that respects every
+dependency (Section 3: one-directional dependencies along the x-t diagonal).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_20610_amd import workloads as wl
+from tests import systolic_emulator as emu
+
+PEC = 0
+
+
+def _oracle(w, n):
+    return oracle.run(w.fields, w.eps3(), w.bc, w.dt, w.dx, n, sources=w.sources,
+                      dtype=np.float32)
+
+
+def _coeffs(w):
+    cE = oracle.coeff_E(w.eps3(), w.bc, w.dt, w.dx)
+    return [oracle.round_f32(c) for c in cE], np.float32(w.dt / w.dx)
+
+
+def test_plan_is_topological_and_covers_the_domain():
+    shape, W, K, n = (13, 11, 9), (4, 3, 5), 3, 8
+    tickets, ranges, ticket_of = emu.plan(shape, W, K, n)
+    for i, (band, a, b, c) in enumerate(tickets):
+        for d in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]:
+            j = ticket_of.get((band, a + d[0], b + d[1], c + d[2]))
+            assert j is None or j < i
+        if band > 0:
+            j = ticket_of.get((band - 1, a, b, c))
+            assert j is None or j < i
+    # at every step of every band, the tiles' B boxes cover each domain cell once
+    for band, rg in enumerate(ranges):
+        for tau in range(band * K + 1, min(n, (band + 1) * K) + 1):
+            cover = np.zeros(shape, int)
+            for a in range(rg[0][0], rg[0][1] + 1):
+                for b in range(rg[1][0], rg[1][1] + 1):
+                    for c in range(rg[2][0], rg[2][1] + 1):
+                        lo = [a * W[0] + tau, b * W[1] + tau, c * W[2] + tau]
+                        sl = tuple(slice(max(0, l), max(0, min(s, l + w)))
+                                   for l, s, w in zip(lo, shape, W))
+                        cover[sl] += 1
+            assert np.all(cover == 1)
+
+
+@pytest.mark.parametrize("shape,W,K,nsteps,seed", [
+    ((10, 9, 11), (3, 4, 3), 3, 7, 1),
+    ((16, 12, 14), (5, 4, 6), 4, 9, 2),
+    ((7, 13, 6), (2, 2, 3), 2, 5, 3),
+    ((12, 12, 12), (15, 15, 15), 6, 11, 4),   # one tile larger than the grid
+])
+def test_emulated_schedule_bitwise(shape, W, K, nsteps, seed):
+    w = wl.small_case(shape, (PEC, PEC, PEC), seed=seed, nsteps=nsteps,
+                      dipoles=[tuple(s // 2 for s in shape), (1, 1, 1)])
+    ref = _oracle(w, nsteps)
+    cE, cH = _coeffs(w)
+    for resident, sched_seed in [(1, 0), (3, 1), (50, 2)]:
+        m = emu.Machine(w.fields, cE, cH, shape, W, K, nsteps, sources=w.sources)
+        got = m.run(resident=resident, seed=sched_seed)
+        for c in range(6):
+            np.testing.assert_array_equal(got[c].view(np.uint32), ref[c].view(np.uint32),
+                                          err_msg="component %d resident %d" % (c, resident))
+
+
+def test_emulator_detects_a_missing_wait(monkeypatch):
+    """Sanity of the harness: dropping the wait before the forward-E load
+    makes some interleaving read stale data."""
+    shape, W, K, n = (10, 10, 10), (3, 3, 3), 3, 6
+    w = wl.small_case(shape, (PEC, PEC, PEC), seed=5, nsteps=n)
+    ref = _oracle(w, n)
+    cE, cH = _coeffs(w)
+    orig = emu.Machine.wait
+
+    def no_wait(self, tile, target):
+        if target % 2 == 1:      # the E-level waits
+            return
+        yield from orig(self, tile, target)
+    monkeypatch.setattr(emu.Machine, "wait", no_wait)
+    differs = False
+    for seed in range(6):
+        m = emu.Machine(w.fields, cE, cH, shape, W, K, n)
+        got = m.run(resident=60, seed=seed)
+        if any(not np.array_equal(np.nan_to_num(got[c]), ref[c]) for c in range(6)):
+            differs = True
+            break
+    assert differs

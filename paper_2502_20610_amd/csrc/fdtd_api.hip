@@ -263,7 +263,7 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
     ctx->scheme = cfg->scheme;
     ctx->band_steps = 0;  // 0 = choose per call
     ctx->workgroups = 0;
-    ctx->spin_limit = int64_t(1) << 26;
+    ctx->spin_limit = int64_t(1) << 22;
     ctx->profile = false;
     ctx->cH = (float)(cfg->dt / cfg->dx);
     ctx->err = "no error";

@@ -1,0 +1,94 @@
+"""GPU parity of the systolic scheme: bit-identical to the FP32 oracle.
+
+The systolic scheme performs exactly the update equations of the plain
+scheme, in an order that respects every dependency, so its FP32 result must
+be the same value bit for bit (the paper's claim that the scheme does the
+exact same update).  Cases cover several tiles per axis with ragged tails,
+band lengths from 1 to more than the step count, sources on tile edges and
+corners, grids smaller than one tile, fewer persistent workgroups than
+tiles (schedule stress), calls split across bands, scheme switches on a live
+context, and the refusal of configurations the scheme does not cover.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_20610_amd import fdtd
+from paper_2502_20610_amd import workloads as wl
+from tests import yee_math as ym
+from tests.test_gpu_parity import assert_bitwise, oracle_f32
+
+pytestmark = pytest.mark.gpu
+PEC, PER = 0, 1
+
+
+def run_sys(w, nsteps=None, **opts):
+    o = {}
+    if "band" in opts:
+        o[fdtd.OPT_BAND_STEPS] = opts["band"]
+    if "wg" in opts:
+        o[fdtd.OPT_WORKGROUPS] = opts["wg"]
+    return fdtd.run_workload(w, "systolic", nsteps=nsteps, options=o)
+
+
+@pytest.mark.parametrize("shape,nsteps,band,seed", [
+    ((16, 16, 16), 5, 16, 1),
+    ((40, 36, 34), 20, 16, 2),
+    ((31, 47, 29), 23, 7, 3),
+    ((64, 20, 50), 17, 1, 4),
+    ((9, 5, 13), 11, 4, 5),          # grid smaller than one tile
+    ((1, 30, 30), 6, 3, 6),          # one-cell-thick axis
+    ((45, 45, 45), 33, 10, 7),
+])
+def test_systolic_bitwise_small(shape, nsteps, band, seed):
+    dips = [tuple(s // 2 for s in shape)]
+    # sources on tile edges and corners of the initial tiling
+    for p in [(15, 15, 15), (14, 1, 29), (1, 16, 1)]:
+        if all(1 <= p[a] < shape[a] for a in range(3)):
+            dips.append(p)
+    dips = [d for d in dips if d[0] >= 1 and d[1] >= 1]
+    w = wl.small_case(shape, (PEC, PEC, PEC), seed=seed, nsteps=nsteps, dipoles=dips)
+    assert_bitwise(run_sys(w, band=band), oracle_f32(w), "systolic %s" % (shape,))
+
+
+@pytest.mark.parametrize("wg", [1, 2, 7, 64])
+def test_systolic_few_workgroups(wg):
+    w = wl.small_case((50, 40, 45), (PEC, PEC, PEC), seed=11, nsteps=19, dipoles=[(25, 20, 22)])
+    assert_bitwise(run_sys(w, band=6, wg=wg), oracle_f32(w), "systolic wg=%d" % wg)
+
+
+def test_systolic_c1_bitwise_and_fp64_bound():
+    w = wl.c1_cavity_pulse()
+    gpu = run_sys(w)
+    assert_bitwise(gpu, oracle_f32(w), "systolic C1")
+    f64 = oracle.run(w.fields, w.eps3(), w.bc, w.dt, w.dx, w.nsteps, dtype=np.float64)
+    assert ym.rel_l2(gpu, f64) < 1e-5
+
+
+def test_systolic_split_calls_and_scheme_switch():
+    w = wl.small_case((48, 44, 40), (PEC, PEC, PEC), seed=13, nsteps=41, dipoles=[(20, 21, 22)])
+    ref = oracle_f32(w)
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic")
+    sim.set_materials(w.eps)
+    sim.set_fields(w.fields)
+    for s in w.sources:
+        sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+    sim.step(9)
+    sim.set_option(fdtd.OPT_SCHEME, fdtd.SCHEME_PLAIN)
+    sim.step(5)
+    sim.set_option(fdtd.OPT_SCHEME, fdtd.SCHEME_SYSTOLIC)
+    sim.set_option(fdtd.OPT_BAND_STEPS, 4)
+    sim.step(13)
+    sim.step(14)
+    assert sim.current_step == 41
+    assert_bitwise(sim.read_fields(), ref, "systolic split")
+    sim.close()
+
+
+def test_systolic_refuses_periodic_without_fallback():
+    sim = fdtd.Simulation((16, 16, 16), 0.5, 1.0, (PER, PEC, PEC), scheme="systolic")
+    with pytest.raises(fdtd.FdtdError) as e:
+        sim.step(1)
+    assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+    assert sim.current_step == 0
+    sim.close()

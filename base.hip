@@ -1,0 +1,923 @@
+// Systolic scheme: one persistent launch per fdtd_step() call.
+//
+// Method (paper, Sections 3 and 4): the grid is covered by subdomain tiles
+// that stay resident on chip for a band of K steps.  Every step a tile moves
+// one cell along the x-y-z-t diagonal, so every dependency between tiles
+// points one way (upwind = +x, +y, +z); a tile only exchanges the faces of its
+// subdomain with its neighbours, through device memory, and waits on its
+// seven upwind neighbours' progress counters instead of a grid-wide barrier.
+// E is updated before H in every step (caption of Fig. 7), and the update
+// equations are exactly those of the plain scheme, so the result is the same
+// FP32 value bit for bit.
+//
+// MI355X mapping (one workgroup = one tile):
+//   * z: 16 slots on the 16 lanes of a DPP row; the +-1 z neighbour is a
+//     row_ror:1 / row_ror:15 operand modifier of the consuming VALU op;
+//   * y: 4 rows per wavefront x NW wavefronts = 4*NW slots; the +-1 y
+//     neighbour goes through LDS;
+//   * x: 16 slots in registers per lane; moving the tile one cell along x is
+//     a compile-time renaming (results of register j are written to j-1), so
+//     the x neighbour is a plain register operand.
+//   Each axis holds W+1 slots for W updated cells: the extra slot is the
+//   layer below the tile (H needed by the E half-step), then receives the
+//   layer above it from the upwind neighbours (E needed by the H half-step,
+//   then the state of the cells that enter the tile).  Slots are addressed
+//   modulo 16 on y and z, so cells never move between lanes.
+//
+// Faces: after each half-step a tile publishes the first layer of its
+// subdomain.  The x and y faces go straight into the field arrays at their
+// own coordinates (z-contiguous runs); the z face, which would be a strided
+// column in [x][y][z] memory, goes into a ring of per-ticket face buffers.
+// Published values stay where they are until the consumer has taken them,
+// because the next writer of a cell is its consumer.
+//
+// Schedule: tickets (band, tile) in topological order (bands in order; in a
+// band, tiles by depth below the most upwind corner).  Workgroups take
+// tickets from an atomic counter; every wait targets an earlier ticket, so
+// the schedule cannot deadlock however many workgroups are resident.  Waits
+// are bounded: on expiry the kernel raises the error word and drains.
+//
+// All axes must be PEC: cells outside the grid are ghosts that read as +0,
+// which reproduces the closed box of the periodic-index definition.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <type_traits>
+#include <vector>
+
+#include "fdtd_internal.h"
+
+namespace fdtd {
+
+namespace {
+
+constexpr int PX = 16, PZ = 16;         // slots along x (registers) and z (lanes)
+constexpr int WX = PX - 1, WZ = PZ - 1; // updated cells along x and z
+constexpr unsigned kOOB = 0xFFFFFFF0u;  // buffer offset that reads 0 / drops stores
+
+struct SysArgs {
+    float* f[6];
+    const float* cE[3];
+    float cH;
+    int nx, ny, nz;
+    unsigned fbytes;  // bytes of one field array
+    const int4* tickets;
+    int nt;
+    const int* tix;    // ticket index of (band, tile)
+    const int* band;   // per band: alo ahi blo bhi clo chi tix_off pad
+    unsigned* progress;
+    int amin, bmin, cmin, NA, NB, NC;
+    float* ring;
+    unsigned ring_bytes;
+    int R, K;
+    int nsteps;
+    long long step0;
+    const DevSource* src;
+    int nsrc;
+    unsigned* counter;
+    int* error;
+    long long spin_limit;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// Cache policy of the accesses to data shared between workgroups (field
+// arrays, face ring): with kDev = 16 (the "sc1" bit, device scope) every load
+// and store is coherent across the XCDs by itself, so publishing only has to
+// wait for the stores to complete and waiting only has to observe the flag.
+// With 0 the accesses are cached normally and the flag store/load carry
+// agent-scope release/acquire fences (L2 write-back / invalidate).
+template <int POL>
+__device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, POL));
+}
+
+template <int POL>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, POL);
+}
+
+// Value of the lane (zs - 1) mod 16 / (zs + 1) mod 16 of the same DPP row.
+__device__ __forceinline__ float from_zm(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x121, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_zp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x12F, 0xF, 0xF, false));
+}
+
+template <typename T>
+__device__ __forceinline__ unsigned lds_offset(T* p)
+{
+    return (unsigned)(unsigned long long)(__attribute__((address_space(3))) T*)(p);
+}
+
+// Asynchronous load of one dword per lane from a buffer straight into LDS at
+// lds + 4 * lane (out-of-range offsets write 0).  Issued as inline assembly
+// so that the compiler does not hold later LDS accesses of unrelated arrays
+// behind it; the kernel itself waits (vmcnt(0) and a barrier) before it reads
+// the destination.  M0 carries the LDS address; nothing else in this kernel
+// uses M0, and every such load sets it first.
+template <bool DEV>
+__device__ __forceinline__ void dma_dword(__amdgpu_buffer_rsrc_t desc, unsigned lds, unsigned voff)
+{
+    lds = __builtin_amdgcn_readfirstlane(lds);
+    if (DEV)
+        asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, 0 offen sc1 lds"
+                     :: "s"(lds), "v"(voff), "s"(desc) : "memory");
+    else
+        asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, 0 offen lds"
+                     :: "s"(lds), "v"(voff), "s"(desc) : "memory");
+}
+
+// Workgroup barrier for LDS traffic only: waits for this wavefront's LDS
+// operations, not for its outstanding global loads (__syncthreads() would
+// also drain those, which would stall on the prefetched faces).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ int band_has(const int* bi, int a, int b, int c)
+{
+    return a >= bi[0] && a <= bi[1] && b >= bi[2] && b <= bi[3] && c >= bi[4] && c <= bi[5];
+}
+
+__device__ __forceinline__ int prog_index(const SysArgs& A, int a, int b, int c)
+{
+    return ((a - A.amin) * A.NB + (b - A.bmin)) * A.NC + (c - A.cmin);
+}
+
+// Make this workgroup's global stores visible at device scope, then set the
+// tile's progress counter (release).
+template <bool DEV>
+__device__ __forceinline__ void publish(const SysArgs& A, int me, unsigned v)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (!DEV) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(A.progress + me, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Wait until every listed tile's counter is >= target (acquire).  Lanes
+// 0..n-1 of the first wavefront poll one counter each.  Returns false (on
+// every thread) if a wait expired or another workgroup raised the error.
+template <bool DEV>
+__device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8], int n,
+                                           unsigned target, int* s_abort, unsigned* s_min)
+{
+    const int tid = threadIdx.x;
+    if (s_min) {
+        // every wavefront has finished reading *s_min before it is reset
+        __syncthreads();
+        if (tid == 0 && n) *s_min = 0xFFFFFFFFu;
+        __syncthreads();
+    }
+    if (tid < n) {
+        int my = idx[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k)
+            if (tid == k) my = idx[k];
+        unsigned* p = A.progress + my;
+        long long it = 0;
+        unsigned v;
+        while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
+            if (++it > A.spin_limit) {
+                atomicOr(A.error, 2);
+                *s_abort = 1;
+                break;
+            }
+            if ((it & 255) == 0 && __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                *s_abort = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        // the lowest progress seen bounds every later wait of this ticket
+        if (s_min) atomicMin(s_min, v);
+        if (!DEV) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return *s_abort == 0;
+}
+
+template <int NW, bool DEV>
+__global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
+{
+    constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
+    constexpr int PY = 4 * NW;
+    constexpr int WY = PY - 1;
+    static_assert(PY == 16, "face staging assumes 16 slots on every axis");
+    // y-neighbour exchange, two components per half-step
+    __shared__ float xch[2][WX][PY][PZ];
+    // incoming faces of the next box: y face [comp][x][z], z face [comp][y][x]
+    __shared__ float yst[9][PX][PZ];
+    __shared__ __attribute__((aligned(16))) float zst[9][PY][PX];
+    // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
+    __shared__ float ytr[6][PX][PZ];
+    __shared__ __attribute__((aligned(16))) float ztr[9][PY][PX];
+    __shared__ int s_ticket;
+    __shared__ int s_abort;
+    __shared__ unsigned s_up;  // lower bound of the upwind neighbours' progress
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;         // wavefront
+    const int r = (tid >> 4) & 3;   // row within the wavefront
+    const int ys = tid >> 4;        // y slot: 4 rows per wavefront, NW wavefronts
+    const int zs = tid & 15;        // z slot: lane within the DPP row
+    if (tid == 0) s_abort = 0;
+
+    __amdgpu_buffer_rsrc_t rf[6], rc[3];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) rf[c] = make_rsrc(A.f[c], A.fbytes);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rc[c] = make_rsrc(A.cE[c], A.fbytes);
+    const __amdgpu_buffer_rsrc_t rring = make_rsrc(A.ring, A.ring_bytes);
+    const unsigned plane = (unsigned)A.ny * (unsigned)A.nz;
+    const float cH = A.cH;
+    constexpr unsigned ring_step = 9u * PY * PX;  // floats per (slot, local step)
+    constexpr unsigned ring_comp = PY * PX;       // floats per component
+
+    float E[3][PX], H[3][PX], C[3][PX];
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            // a raised error word (another workgroup timed out) drains the grid
+            const int err = __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = err ? A.nt : (int)atomicAdd(A.counter, 1u);
+        }
+        __syncthreads();
+        const int t = s_ticket;
+        if (t >= A.nt || s_abort) break;
+
+        const int4 tk = A.tickets[t];
+        const int bnd = tk.x, a = tk.y, b = tk.z, c = tk.w;
+        const int t0 = bnd * A.K;
+        const int t1 = min(A.nsteps, t0 + A.K);
+        const int* bi = A.band + 8 * bnd;
+        const int me = prog_index(A, a, b, c);
+        const int ox = a * WX, oy = b * WY, oz = c * WZ;
+
+        // upwind neighbours that exist in this band
+        int ups[8];
+        int nup = 0;
+#pragma unroll
+        for (int d = 1; d < 8; ++d) {
+            const int ua = a + (d & 1), ub = b + ((d >> 1) & 1), uc = c + ((d >> 2) & 1);
+            if (band_has(bi, ua, ub, uc)) {
+                const int pi = prog_index(A, ua, ub, uc);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k == nup) ups[k] = pi;
+                ++nup;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k >= nup) ups[k] = me;
+
+        // band start: this tile and its upwind neighbours finished the previous band
+        if (bnd > 0) {
+            const int* bp = A.band + 8 * (bnd - 1);
+            int wl[8];
+            int nw = 0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const int ua = a + (d & 1), ub = b + ((d >> 1) & 1), uc = c + ((d >> 2) & 1);
+                if (band_has(bp, ua, ub, uc)) {
+                    const int pi = prog_index(A, ua, ub, uc);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (k == nw) wl[k] = pi;
+                    ++nw;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k >= nw) wl[k] = me;
+            if (!wait_tiles<DEV>(A, wl, nw, 2u * (unsigned)t0, &s_abort, nullptr)) break;
+        }
+        // ring slot reuse: the previous occupant has finished writing it and
+        // its consumer (the -z neighbour) has finished reading it
+        const int slot = t % A.R;
+        if (t >= A.R) {
+            const int4 pk = A.tickets[t - A.R];
+            const int* pb = A.band + 8 * pk.x;
+            const unsigned pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * A.K);
+            int wl[8];
+            wl[0] = prog_index(A, pk.y, pk.z, pk.w);
+            int nw = 1;
+            if (band_has(pb, pk.y, pk.z, pk.w - 1)) {
+                wl[1] = prog_index(A, pk.y, pk.z, pk.w - 1);
+                nw = 2;
+            } else {
+                wl[1] = wl[0];
+            }
+#pragma unroll
+            for (int k = 2; k < 8; ++k) wl[k] = wl[0];
+            if (!wait_tiles<DEV>(A, wl, nw, pend, &s_abort, nullptr)) break;
+        }
+        const int has_consumer = band_has(bi, a, b, c - 1);
+        const int has_zup = band_has(bi, a, b, c + 1);
+        const int slot_zup = has_zup ? A.tix[bi[6] + ((a - bi[0]) * (bi[3] - bi[2] + 1) + (b - bi[2])) *
+                                                      (bi[5] - bi[4] + 1) + (c + 1 - bi[4])] % A.R
+                                     : 0;
+
+        // ---- load the slot box of step t0 + 1 (lower corner o + t0) and
+        //      read the upwind progress once
+        if (tid == 0) s_up = nup ? 0u : 0xFFFFFFFFu;
+        {
+            const int by = oy + t0, bz = oz + t0;
+            const int y = by + ((ys - by) & (PY - 1));
+            const int z = bz + ((zs - bz) & (PZ - 1));
+            const bool okyz = (unsigned)y < (unsigned)A.ny && (unsigned)z < (unsigned)A.nz;
+            const unsigned yz = (unsigned)y * (unsigned)A.nz + (unsigned)z;
+#pragma unroll
+            for (int j = 0; j < PX; ++j) {
+                const int x = ox + t0 + j;
+                const unsigned off = (okyz && (unsigned)x < (unsigned)A.nx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    E[q][j] = bld<SP>(rf[q], off);
+                    H[q][j] = bld<SP>(rf[3 + q], off);
+                    C[q][j] = bld<0>(rc[q], off);
+                }
+            }
+        }
+        if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up)) break;
+
+        float tx[3], th[6];  // x face of the next box, prefetched into registers
+        bool aborted = false;
+        for (int tau = t0 + 1; tau <= t1; ++tau) {
+            const int ls = tau - t0 - 1;
+            const int by = oy + tau - 1, bz = oz + tau - 1;
+            const int dy = (ys - by) & (PY - 1);  // 0: layer below the tile; 1..WY: inside
+            const int dz = (zs - bz) & (PZ - 1);
+            const int y = by + dy, z = bz + dz;
+            const bool inB = dy >= 1 && dz >= 1;
+            const bool okyz = (unsigned)y < (unsigned)A.ny && (unsigned)z < (unsigned)A.nz;
+            const unsigned yz = (unsigned)y * (unsigned)A.nz + (unsigned)z;
+            auto off_at = [&](int x) -> unsigned {
+                return (okyz && (unsigned)x < (unsigned)A.nx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
+            };
+            // coordinates of this lane in the next box (after the one-cell move)
+            const int dy1 = (dy - 1) & (PY - 1), dz1 = (dz - 1) & (PZ - 1);
+            const int y1 = by + 1 + dy1, z1 = bz + 1 + dz1;
+            const bool okyz1 = (unsigned)y1 < (unsigned)A.ny && (unsigned)z1 < (unsigned)A.nz;
+            const unsigned yz1 = (unsigned)y1 * (unsigned)A.nz + (unsigned)z1;
+            const unsigned ring_base = ((unsigned)slot * (unsigned)A.K + (unsigned)ls) * ring_step;
+            const unsigned ring_zup = ((unsigned)slot_zup * (unsigned)A.K + (unsigned)ls) * ring_step;
+            // the forward y and z planes of the next box
+            const int yf = oy + tau + WY, zf = oz + tau + WZ;
+            // z of DPP lane zs in the next box, for the y-face loads
+            const int zl = oz + tau + ((zs - oz - tau) & (PZ - 1));
+            const bool okz_l = (unsigned)zl < (unsigned)A.nz;
+            const bool oky_f = (unsigned)yf < (unsigned)A.ny;
+            const bool okz_f = (unsigned)zf < (unsigned)A.nz;
+
+            // Issue the loads of the next box's forward shell for components
+            // [q0, q0 + nq) (0..2 = E, 3..5 = H, 6..8 = cE): the x face into
+            // registers, the y and z faces straight into LDS.
+            auto prefetch = [&](int q0, int nq) {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                if (q0 == 0) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) tx[q] = bld<SP>(rf[q], ox1);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        th[q] = bld<SP>(rf[3 + q], ox1);
+                        th[3 + q] = bld<0>(rc[q], ox1);
+                    }
+                }
+                for (int i = w; i < 4 * nq; i += NW) {
+                    const int q = q0 + (i >> 2), blk = i & 3;
+                    // y face: rows of the wavefront are x, lanes are z
+                    const int j = 4 * blk + r;
+                    const int x = ox + tau + j;
+                    const unsigned oy_ = (oky_f && okz_l && (unsigned)x < (unsigned)A.nx)
+                                             ? (((unsigned)x * (unsigned)A.ny + (unsigned)yf) * (unsigned)A.nz + (unsigned)zl) * 4u
+                                             : kOOB;
+                    if (q < 6)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rf[q], &yst[q][4 * blk][0], 4, (int)oy_, 0, 0, SP);
+                    else
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rc[q - 6], &yst[q][4 * blk][0], 4, (int)oy_, 0, 0, 0);
+                    // z face: rows are y, lanes are x, from the +z neighbour's ring slot
+                    const int yy = 4 * blk + r;  // y index within the face
+                    const bool okz = has_zup && okz_f && zs < WX && yy < WY &&
+                                     (unsigned)(ox + tau + zs) < (unsigned)A.nx &&
+                                     (unsigned)(oy + tau + yy) < (unsigned)A.ny;
+                    const unsigned oz_ = okz ? (ring_zup + (unsigned)q * ring_comp + (unsigned)yy * PX + (unsigned)zs) * 4u : kOOB;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rring, &zst[q][4 * blk][0], 4, (int)oz_, 0, 0, SP);
+                }
+            };
+            // Write the staged first-layer faces for components [q0, q0+nq)
+            // to memory (after a barrier that makes the LDS writes visible).
+            auto store_faces = [&](int q0, int nq, int nqz) {
+                __syncthreads();
+                for (int i = w; i < 4 * nq; i += NW) {
+                    const int q = q0 + (i >> 2), blk = i & 3;
+                    const int j = 4 * blk + r;
+                    // y face at y = oy + tau: cells inside the tile only
+                    const int zz = oz + tau - 1 + ((zs - oz - tau + 1) & (PZ - 1));
+                    const bool in = j < WX && ((zs - oz - tau + 1) & (PZ - 1)) >= 1 &&
+                                    (unsigned)(ox + tau + j) < (unsigned)A.nx &&
+                                    (unsigned)(oy + tau) < (unsigned)A.ny && (unsigned)zz < (unsigned)A.nz;
+                    const unsigned o = in ? ((((unsigned)(ox + tau + j)) * (unsigned)A.ny + (unsigned)(oy + tau)) *
+                                             (unsigned)A.nz + (unsigned)zz) * 4u : kOOB;
+                    bst<SP>(rf[q], o, ytr[q][j][zs]);
+                }
+                if (has_consumer) {
+                    for (int i = w; i < 4 * nqz; i += NW) {
+                        const int q = q0 + (i >> 2), blk = i & 3;
+                        const int yy = 4 * blk + r;
+                        bst<SP>(rring, (ring_base + (unsigned)q * ring_comp + (unsigned)yy * PX + (unsigned)zs) * 4u,
+                                ztr[q][yy][zs]);
+                    }
+                }
+            };
+            auto ensure_up = [&](unsigned level) -> bool {
+                if (s_up >= level) return true;
+                return wait_tiles<DEV>(A, ups, nup, level, &s_abort, &s_up);
+            };
+
+            // ================= E half-step (H frame: register j <-> x = ox+tau-1+j)
+            const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
+            if (earlyE) prefetch(0, 3);
+#pragma unroll
+            for (int j = 1; j < PX; ++j) {
+                xch[0][j - 1][ys][zs] = H[2][j];
+                xch[1][j - 1][ys][zs] = H[0][j];
+            }
+            __syncthreads();
+            {
+                const int ysm = (ys - 1) & (PY - 1);
+#pragma unroll
+                for (int j = 1; j < PX; ++j) {
+                    const float hz_ym = xch[0][j - 1][ysm][zs];
+                    const float hx_ym = xch[1][j - 1][ysm][zs];
+                    const float hy_zm = from_zm(H[1][j]);
+                    const float hx_zm = from_zm(H[0][j]);
+                    const float ex = (E[0][j] + C[0][j] * (H[2][j] - hz_ym)) - C[0][j] * (H[1][j] - hy_zm);
+                    const float ey = (E[1][j] + C[1][j] * (H[0][j] - hx_zm)) - C[1][j] * (H[2][j] - H[2][j - 1]);
+                    const float ez = (E[2][j] + C[2][j] * (H[1][j] - H[1][j - 1])) - C[2][j] * (H[0][j] - hx_ym);
+                    E[0][j - 1] = ex;
+                    E[1][j - 1] = ey;
+                    E[2][j - 1] = ez;
+                    C[0][j - 1] = C[0][j];
+                    C[1][j - 1] = C[1][j];
+                    C[2][j - 1] = C[2][j];
+                }
+            }
+            // now E and C registers j <-> x = ox+tau+j (j = 0..14); j = 15 stale
+
+            // point sources of this step on cells of the tile
+            {
+                const long long s = A.step0 + tau - 1;
+                for (int q = 0; q < A.nsrc; ++q) {
+                    const DevSource sq = A.src[q];
+                    const long long m = s - sq.first;
+                    if (m < 0 || m >= sq.len) continue;
+                    const int px = sq.i - (ox + tau), py = sq.j - (oy + tau), pz = sq.k - (oz + tau);
+                    if ((unsigned)px >= (unsigned)WX || (unsigned)py >= (unsigned)WY || (unsigned)pz >= (unsigned)WZ)
+                        continue;
+                    const float wv = sq.wave[m];
+                    if (dy == py + 1 && dz == pz + 1) {
+#pragma unroll
+                        for (int j = 0; j < WX; ++j) {
+                            if (j == px) {
+                                if (sq.comp == 0) E[0][j] = E[0][j] + wv;
+                                if (sq.comp == 1) E[1][j] = E[1][j] + wv;
+                                if (sq.comp == 2) E[2][j] = E[2][j] + wv;
+                            }
+                        }
+                    }
+                }
+            }
+
+            // publish E of the first layer of the tile
+            if (inB) {
+                const unsigned o = off_at(ox + tau);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) bst<SP>(rf[q], o, E[q][0]);
+            }
+            if (dy == 1) {
+#pragma unroll
+                for (int j = 0; j < WX; ++j)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) ytr[q][j][zs] = E[q][j];
+            }
+            if (dz == 1) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) ztr[q][dy1][j] = E[q][j];
+            }
+            store_faces(0, 3, 3);
+            if (!earlyE) {
+                if (!ensure_up(2u * (unsigned)tau - 1u)) {
+                    aborted = true;
+                    break;
+                }
+                prefetch(0, 3);
+            }
+            publish<DEV>(A, me, 2u * (unsigned)tau - 1u);  // also completes the prefetch
+
+            // forward shell's E^tau into the registers
+#pragma unroll
+            for (int q = 0; q < 3; ++q) E[q][WX] = tx[q];
+            if (dy == 0) {
+#pragma unroll
+                for (int j = 0; j < WX; ++j)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) E[q][j] = yst[q][j][zs];
+            } else if (dz == 0) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) E[q][j] = zst[q][dy1][j];
+            }
+
+            // ================= H half-step (E frame: register j <-> x = ox+tau+j)
+            const bool earlyH = tau < t1 && s_up >= 2u * (unsigned)tau;
+            if (earlyH) prefetch(3, 6);
+#pragma unroll
+            for (int j = 0; j < WX; ++j) {
+                xch[0][j][ys][zs] = E[2][j];
+                xch[1][j][ys][zs] = E[0][j];
+            }
+            __syncthreads();
+            {
+                const int ysp = (ys + 1) & (PY - 1);
+#pragma unroll
+                for (int j = 0; j < WX; ++j) {
+                    const float ez_yp = xch[0][j][ysp][zs];
+                    const float ex_yp = xch[1][j][ysp][zs];
+                    const float ey_zp = from_zp(E[1][j]);
+                    const float ex_zp = from_zp(E[0][j]);
+                    const float hx = (H[0][j + 1] - cH * (ez_yp - E[2][j])) + cH * (ey_zp - E[1][j]);
+                    const float hy = (H[1][j + 1] - cH * (ex_zp - E[0][j])) + cH * (E[2][j + 1] - E[2][j]);
+                    const float hz = (H[2][j + 1] - cH * (E[1][j + 1] - E[1][j])) + cH * (ex_yp - E[0][j]);
+                    H[0][j] = hx;
+                    H[1][j] = hy;
+                    H[2][j] = hz;
+                }
+            }
+            // now H registers j <-> x = ox+tau+j as well
+
+            // publish H (and, on the z face, the coefficients) of the first layer
+            if (inB) {
+                const unsigned o = off_at(ox + tau);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) bst<SP>(rf[3 + q], o, H[q][0]);
+            }
+            if (dy == 1) {
+#pragma unroll
+                for (int j = 0; j < WX; ++j)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) ytr[3 + q][j][zs] = H[q][j];
+            }
+            if (dz == 1) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) {
+                        ztr[3 + q][dy1][j] = H[q][j];
+                        ztr[6 + q][dy1][j] = C[q][j];
+                    }
+            }
+            store_faces(3, 3, 6);
+            if (tau == t1 && inB) {
+                // band end: the whole subdomain goes back to the field arrays
+#pragma unroll
+                for (int j = 0; j < WX; ++j) {
+                    const unsigned o = off_at(ox + tau + j);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        bst<SP>(rf[q], o, E[q][j]);
+                        bst<SP>(rf[3 + q], o, H[q][j]);
+                    }
+                }
+            }
+            if (tau < t1 && !earlyH) {
+                if (!ensure_up(2u * (unsigned)tau)) {
+                    aborted = true;
+                    break;
+                }
+                prefetch(3, 6);
+            }
+            publish<DEV>(A, me, 2u * (unsigned)tau);  // also completes the prefetch
+            if (tau == t1) break;
+
+            // forward shell's H^(tau+1/2) and coefficients into the registers
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                H[q][WX] = th[q];
+                C[q][WX] = th[3 + q];
+            }
+            if (dy == 0) {
+#pragma unroll
+                for (int j = 0; j < WX; ++j)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        H[q][j] = yst[3 + q][j][zs];
+                        C[q][j] = yst[6 + q][j][zs];
+                    }
+            } else if (dz == 0) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) {
+                        H[q][j] = zst[3 + q][dy1][j];
+                        C[q][j] = zst[6 + q][dy1][j];
+                    }
+            }
+        }
+        if (aborted) break;
+    }
+}
+
+__global__ void fill_u32(unsigned* p, unsigned v, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+constexpr int kNW = 4;  // wavefronts per tile: tile = 15 x 15 x 15 updated cells
+
+}  // namespace
+
+// Host-side plan of one call: tickets, per-band tile ranges, ring sizing.
+struct SystolicState {
+    int nsteps = -1, K = -1;
+    int nt = 0, R = 0, D = 1, nbands = 0;
+    int amin = 0, bmin = 0, cmin = 0, NA = 0, NB = 0, NC = 0;
+    int4* d_tickets = nullptr;
+    int* d_tix = nullptr;
+    int* d_band = nullptr;
+    unsigned* d_progress = nullptr;
+    float* d_ring = nullptr;
+    unsigned* d_counter = nullptr;
+    size_t ring_bytes = 0;
+    int capacity = 0;
+};
+
+namespace {
+
+void free_plan(SystolicState* s)
+{
+    if (s->d_tickets) (void)hipFree(s->d_tickets);
+    if (s->d_tix) (void)hipFree(s->d_tix);
+    if (s->d_band) (void)hipFree(s->d_band);
+    if (s->d_progress) (void)hipFree(s->d_progress);
+    if (s->d_ring) (void)hipFree(s->d_ring);
+    if (s->d_counter) (void)hipFree(s->d_counter);
+    s->d_tickets = nullptr;
+    s->d_tix = nullptr;
+    s->d_band = nullptr;
+    s->d_progress = nullptr;
+    s->d_ring = nullptr;
+    s->d_counter = nullptr;
+    s->nsteps = s->K = -1;
+}
+
+int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
+{
+    constexpr int WY = 4 * kNW - 1;
+    const int W[3] = {WX, WY, WZ};
+    const int N[3] = {ctx->nx, ctx->ny, ctx->nz};
+    const int nb = (nsteps + K - 1) / K;
+    std::vector<int> band(8 * (size_t)nb);
+    int lo_all[3] = {1 << 30, 1 << 30, 1 << 30}, hi_all[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    size_t ntot = 0;
+    for (int bb = 0; bb < nb; ++bb) {
+        const int t0 = bb * K, t1 = std::min(nsteps, t0 + K);
+        size_t cnt = 1;
+        for (int d = 0; d < 3; ++d) {
+            // tiles whose subdomain meets the grid at some step of the band
+            const int lo = -floordiv(W[d] - 1 + t1, W[d]);
+            const int hi = floordiv(N[d] - 2 - t0, W[d]);
+            band[8 * bb + 2 * d] = lo;
+            band[8 * bb + 2 * d + 1] = hi;
+            lo_all[d] = std::min(lo_all[d], lo);
+            hi_all[d] = std::max(hi_all[d], hi);
+            cnt *= (size_t)(hi - lo + 1);
+        }
+        band[8 * bb + 6] = (int)ntot;
+        ntot += cnt;
+    }
+    if (ntot > (size_t)1 << 30) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: too many tickets");
+    std::vector<int4> tickets(ntot);
+    std::vector<int> tix(ntot);
+    size_t pos = 0;
+    for (int bb = 0; bb < nb; ++bb) {
+        const int* bi = &band[8 * bb];
+        const int na = bi[1] - bi[0] + 1, nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
+        const int maxd = na + nbb + nc - 3;
+        // counting sort by depth below the most upwind corner (upwind first)
+        std::vector<int> count(maxd + 2, 0);
+        for (int ia = 0; ia < na; ++ia)
+            for (int ib = 0; ib < nbb; ++ib)
+                for (int ic = 0; ic < nc; ++ic) count[(na - 1 - ia) + (nbb - 1 - ib) + (nc - 1 - ic) + 1]++;
+        for (int d = 1; d <= maxd + 1; ++d) count[d] += count[d - 1];
+        for (int ia = 0; ia < na; ++ia)
+            for (int ib = 0; ib < nbb; ++ib)
+                for (int ic = 0; ic < nc; ++ic) {
+                    const int d = (na - 1 - ia) + (nbb - 1 - ib) + (nc - 1 - ic);
+                    const size_t tix_i = pos + (size_t)count[d]++;
+                    tickets[tix_i] = make_int4(bb, bi[0] + ia, bi[2] + ib, bi[4] + ic);
+                    tix[(size_t)bi[6] + ((size_t)ia * nbb + ib) * nc + ic] = (int)tix_i;
+                }
+        pos += (size_t)na * nbb * nc;
+    }
+    // largest distance (in tickets) from a face producer to its -z consumer
+    int R = 1;
+    for (size_t t = 0; t < ntot; ++t) {
+        const int4 tk = tickets[t];
+        const int* bi = &band[8 * tk.x];
+        if (tk.w - 1 < bi[4]) continue;
+        const int nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
+        const int j = tix[(size_t)bi[6] + ((size_t)(tk.y - bi[0]) * nbb + (tk.z - bi[2])) * nc + (tk.w - 1 - bi[4])];
+        R = std::max(R, (int)(j - (int)t + 1));
+    }
+    free_plan(s);
+    s->nsteps = nsteps;
+    s->K = K;
+    s->nt = (int)ntot;
+    s->nbands = nb;
+    s->D = R;
+    s->amin = lo_all[0];
+    s->bmin = lo_all[1];
+    s->cmin = lo_all[2];
+    s->NA = hi_all[0] - lo_all[0] + 1;
+    s->NB = hi_all[1] - lo_all[1] + 1;
+    s->NC = hi_all[2] - lo_all[2] + 1;
+    hipError_t e;
+    size_t nprog = (size_t)s->NA * s->NB * s->NC;
+    if ((e = hipMalloc(&s->d_tickets, ntot * sizeof(int4))) != hipSuccess ||
+        (e = hipMalloc(&s->d_tix, ntot * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&s->d_band, band.size() * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&s->d_progress, nprog * sizeof(unsigned))) != hipSuccess ||
+        (e = hipMalloc(&s->d_counter, sizeof(unsigned))) != hipSuccess) {
+        free_plan(s);
+        return fail(ctx, FDTD_ENOMEM, std::string("systolic plan allocation: ") + hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(s->d_tickets, tickets.data(), ntot * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(s->d_tix, tix.data(), ntot * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(s->d_band, band.data(), band.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) {
+        free_plan(s);
+        return hip_fail(ctx, e, "systolic plan upload");
+    }
+    return FDTD_OK;
+}
+
+int default_band(const fdtd_ctx* ctx, int64_t nsteps)
+{
+    if (ctx->band_steps > 0) return (int)std::min<int64_t>(ctx->band_steps, nsteps);
+    return (int)std::min<int64_t>(16, nsteps);
+}
+
+}  // namespace
+
+int systolic_supported(const fdtd_ctx* ctx, std::string* why)
+{
+    for (int a = 0; a < 3; ++a)
+        if (ctx->cfg.bc[a] != FDTD_BC_PEC) {
+            *why = "periodic axes are not supported by the systolic scheme in this build";
+            return 0;
+        }
+    if ((uint64_t)ctx->ncell * 4u > 0xFFFFFF00ull) {
+        *why = "field arrays above 4 GiB are not supported by the systolic scheme";
+        return 0;
+    }
+    return 1;
+}
+
+int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
+{
+    if (nsteps > (int64_t(1) << 24)) return fail(ctx, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
+    if (!ctx->sys) {
+        ctx->sys = new (std::nothrow) SystolicState();
+        if (!ctx->sys) return fail(ctx, FDTD_ENOMEM, "systolic: host allocation failed");
+    }
+    SystolicState* s = ctx->sys;
+    const int K = default_band(ctx, nsteps);
+    if (s->nsteps != (int)nsteps || s->K != K) {
+        int rc = build_plan(ctx, s, (int)nsteps, K);
+        if (rc) return rc;
+    }
+    // synchronisation variant: device-scope accesses (default) or cached
+    // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
+    const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
+    const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
+    auto kern = dev ? systolic_kernel<kNW, true> : systolic_kernel<kNW, false>;
+    if (s->capacity == 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kNW, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, ctx->device);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDeviceProperties");
+        s->capacity = std::max(1, per_cu) * prop.multiProcessorCount;
+    }
+    int grid = ctx->workgroups > 0 ? ctx->workgroups : s->capacity;
+    grid = std::max(1, std::min(grid, s->nt));
+    // Face ring: a slot is reused R tickets later, after its previous
+    // occupant and that occupant's consumer have finished.  R = D + 2 * grid
+    // keeps those two long finished by the time the slot comes round again,
+    // so the reuse wait never holds a workgroup in steady state.
+    const int R = std::max(1, std::min(s->D + 2 * grid, s->nt));
+    const size_t ring_bytes = (size_t)R * s->K * 9 * (4 * kNW) * 16 * sizeof(float);
+    if (ring_bytes >= ((size_t)1 << 32)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: face ring too large");
+    if (R != s->R || !s->d_ring) {
+        if (s->d_ring) (void)hipFree(s->d_ring);
+        s->d_ring = nullptr;
+        s->R = 0;
+        hipError_t e0 = hipMalloc(&s->d_ring, ring_bytes);
+        if (e0 != hipSuccess) return fail(ctx, FDTD_ENOMEM, std::string("systolic face ring: ") + hipGetErrorString(e0));
+        s->R = R;
+        s->ring_bytes = ring_bytes;
+    }
+    ctx->sys_grid = grid;
+    ctx->sys_ring_slots = R;
+    ctx->sys_band = s->K;
+    ctx->sys_tickets = s->nt;
+    const size_t nprog = (size_t)s->NA * s->NB * s->NC;
+    hipLaunchKernelGGL(fill_u32, dim3(256), dim3(256), 0, ctx->stream, s->d_progress, 0u, (long long)nprog);
+    hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, ctx->stream, s->d_counter, 0u, 1LL);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "systolic reset");
+
+    SysArgs A;
+    memset(&A, 0, sizeof(A));
+    for (int c = 0; c < 6; ++c) A.f[c] = ctx->field[c];
+    for (int c = 0; c < 3; ++c) A.cE[c] = ctx->coef[c];
+    A.cH = ctx->cH;
+    A.nx = ctx->nx;
+    A.ny = ctx->ny;
+    A.nz = ctx->nz;
+    A.fbytes = (unsigned)((uint64_t)ctx->ncell * 4u);
+    A.tickets = s->d_tickets;
+    A.nt = s->nt;
+    A.tix = s->d_tix;
+    A.band = s->d_band;
+    A.progress = s->d_progress;
+    A.amin = s->amin;
+    A.bmin = s->bmin;
+    A.cmin = s->cmin;
+    A.NA = s->NA;
+    A.NB = s->NB;
+    A.NC = s->NC;
+    A.ring = s->d_ring;
+    A.ring_bytes = (unsigned)s->ring_bytes;
+    A.R = s->R;
+    A.K = s->K;
+    A.nsteps = (int)nsteps;
+    A.step0 = ctx->step_count;
+    A.src = ctx->dev_sources;
+    A.nsrc = ctx->dev_sources_n;
+    A.counter = s->d_counter;
+    A.error = ctx->dev_error;
+    A.spin_limit = ctx->spin_limit;
+    PendingTiming t;
+    timing_begin(ctx, FDTD_KERNEL_SYSTOLIC, &t);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kNW), 0, ctx->stream, A);
+    timing_end(ctx, &t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch(systolic)");
+    ctx->step_count += nsteps;
+    return FDTD_OK;
+}
+
+void systolic_tile(int* wx, int* wy, int* wz)
+{
+    *wx = WX;
+    *wy = 4 * kNW - 1;
+    *wz = WZ;
+}
+
+void systolic_release(fdtd_ctx* ctx)
+{
+    if (!ctx->sys) return;
+    free_plan(ctx->sys);
+    delete ctx->sys;
+    ctx->sys = nullptr;
+}
+
+}  // namespace fdtd

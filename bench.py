@@ -51,12 +51,14 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %r" % name)
 
 
-def run_scheme(w, scheme: str, steps: int, warmup: int):
+def run_scheme(w, scheme: str, steps: int, warmup: int, options=None):
     import torch
     from paper_2502_20610_amd import fdtd
     stream = torch.cuda.current_stream()
     sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, stream=stream.cuda_stream)
     try:
+        for k, v in (options or {}).items():
+            sim.set_option(k, v)
         dev = torch.device("cuda:0")
         sim.set_materials(torch.from_numpy(w.eps).to(dev))
         if w.fields is not None:
@@ -77,6 +79,13 @@ def run_scheme(w, scheme: str, steps: int, warmup: int):
         t = time.perf_counter() - t0
         stats = {k: sim.kernel_stats(k) for k in (fdtd.KERNEL_PLAIN_E, fdtd.KERNEL_PLAIN_H,
                                                    fdtd.KERNEL_SOURCES, fdtd.KERNEL_SYSTOLIC)}
+        if scheme == "systolic":
+            stats["info"] = {"grid": sim.info(fdtd.INFO_SYSTOLIC_GRID),
+                             "band_steps": sim.info(fdtd.INFO_SYSTOLIC_BAND),
+                             "tickets": sim.info(fdtd.INFO_SYSTOLIC_TICKETS),
+                             "ring_slots": sim.info(fdtd.INFO_RING_SLOTS),
+                             "tile": [sim.info(fdtd.INFO_TILE_X), sim.info(fdtd.INFO_TILE_Y),
+                                      sim.info(fdtd.INFO_TILE_Z)]}
         log("%s: %d steps in %.3f s" % (scheme, steps, t))
         return t, stats
     finally:
@@ -118,6 +127,8 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--schemes", default="systolic,plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--band", type=int, default=0, help="systolic band length (0 = default)")
+    ap.add_argument("--workgroups", type=int, default=0, help="systolic grid size (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,7 +146,13 @@ def main():
     results = {}
     for scheme in args.schemes.split(","):
         try:
-            t, stats = run_scheme(w, scheme, args.steps, args.warmup)
+            opts = {}
+            if scheme == "systolic":
+                if args.band:
+                    opts[fdtd.OPT_BAND_STEPS] = args.band
+                if args.workgroups:
+                    opts[fdtd.OPT_WORKGROUPS] = args.workgroups
+            t, stats = run_scheme(w, scheme, args.steps, args.warmup, opts)
         except fdtd.FdtdError as e:
             if e.code == fdtd.FDTD_EUNSUPPORTED:
                 log("%s unavailable: %s" % (scheme, e))
@@ -176,6 +193,8 @@ def main():
     for scheme, (ts, st) in results.items():
         c = cells * args.steps / ts
         entry = {"cups": c, "ms_per_step": ts / args.steps * 1e3}
+        if scheme == "systolic":
+            entry.update(st["info"])
         if scheme == "plain":
             ne, mse = st[fdtd.KERNEL_PLAIN_E]
             nh, msh = st[fdtd.KERNEL_PLAIN_H]

@@ -175,6 +175,20 @@ enum {
  * Synchronises the stream.  FDTD_OPT_PROFILE = 1 also resets the counters. */
 int fdtd_kernel_stats(fdtd_ctx* ctx, int kernel, int64_t* launches, double* total_ms);
 
+enum {
+    FDTD_INFO_SYSTOLIC_GRID = 0,   /* persistent workgroups of the last systolic launch */
+    FDTD_INFO_SYSTOLIC_BAND = 1,   /* steps per band of the last systolic launch         */
+    FDTD_INFO_SYSTOLIC_TICKETS = 2,/* (band, tile) tickets of the last systolic launch    */
+    FDTD_INFO_RING_SLOTS = 3,      /* face-ring slots of the last systolic launch        */
+    FDTD_INFO_TILE_X = 4,          /* updated cells per systolic tile along x, y, z      */
+    FDTD_INFO_TILE_Y = 5,
+    FDTD_INFO_TILE_Z = 6
+};
+
+/* Read a piece of launch information (FDTD_INFO_*) into *value; 0 before the
+ * first systolic launch.  FDTD_EINVAL for unknown keys or NULL arguments. */
+int fdtd_get_info(const fdtd_ctx* ctx, int key, int64_t* value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -590,4 +590,21 @@ int fdtd_kernel_stats(fdtd_ctx* ctx, int kernel, int64_t* launches, double* tota
     return FDTD_OK;
 }
 
+int fdtd_get_info(const fdtd_ctx* ctx, int key, int64_t* value)
+{
+    if (!ctx || !value) return FDTD_EINVAL;
+    int wx, wy, wz;
+    systolic_tile(&wx, &wy, &wz);
+    switch (key) {
+    case FDTD_INFO_SYSTOLIC_GRID: *value = ctx->sys_grid; return FDTD_OK;
+    case FDTD_INFO_SYSTOLIC_BAND: *value = ctx->sys_band; return FDTD_OK;
+    case FDTD_INFO_SYSTOLIC_TICKETS: *value = ctx->sys_tickets; return FDTD_OK;
+    case FDTD_INFO_RING_SLOTS: *value = ctx->sys_ring_slots; return FDTD_OK;
+    case FDTD_INFO_TILE_X: *value = wx; return FDTD_OK;
+    case FDTD_INFO_TILE_Y: *value = wy; return FDTD_OK;
+    case FDTD_INFO_TILE_Z: *value = wz; return FDTD_OK;
+    default: return FDTD_EINVAL;
+    }
+}
+
 }  // extern "C"

@@ -75,6 +75,10 @@ struct fdtd_ctx {
     int* dev_error;  // device error word: bit 0 bad eps, bit 1 watchdog timeout
 
     fdtd::SystolicState* sys;
+    int sys_grid;        // persistent workgroups of the last systolic launch
+    int sys_ring_slots;  // face-ring slots of the last systolic launch
+    int sys_band;        // steps per band of the last systolic launch
+    int sys_tickets;     // tickets of the last systolic launch
 };
 
 namespace fdtd {
@@ -94,6 +98,7 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps);
 int systolic_supported(const fdtd_ctx* ctx, std::string* why);
 int systolic_step(fdtd_ctx* ctx, int64_t nsteps);
 void systolic_release(fdtd_ctx* ctx);
+void systolic_tile(int* wx, int* wy, int* wz);
 
 // Launch the source-injection kernel for the step that starts at step count s.
 int launch_sources(fdtd_ctx* ctx, int64_t s);

@@ -39,9 +39,11 @@
 //
 // All axes must be PEC: cells outside the grid are ghosts that read as +0,
 // which reproduces the closed box of the periodic-index definition.
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "fdtd_internal.h"
@@ -83,14 +85,22 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsig
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
+// Cache policy of the accesses to data shared between workgroups (field
+// arrays, face ring): with kDev = 16 (the "sc1" bit, device scope) every load
+// and store is coherent across the XCDs by itself, so publishing only has to
+// wait for the stores to complete and waiting only has to observe the flag.
+// With 0 the accesses are cached normally and the flag store/load carry
+// agent-scope release/acquire fences (L2 write-back / invalidate).
+template <int POL>
 __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, unsigned off)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, POL));
 }
 
+template <int POL>
 __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, POL);
 }
 
 // Value of the lane (zs - 1) mod 16 / (zs + 1) mod 16 of the same DPP row.
@@ -105,6 +115,38 @@ __device__ __forceinline__ float from_zp(float v)
                                                                  0x12F, 0xF, 0xF, false));
 }
 
+template <typename T>
+__device__ __forceinline__ unsigned lds_offset(T* p)
+{
+    return (unsigned)(unsigned long long)(__attribute__((address_space(3))) T*)(p);
+}
+
+// Asynchronous load of one dword per lane from a buffer straight into LDS at
+// lds + 4 * lane (out-of-range offsets write 0).  Issued as inline assembly
+// so that the compiler does not hold later LDS accesses of unrelated arrays
+// behind it; the kernel itself waits (vmcnt(0) and a barrier) before it reads
+// the destination.  M0 carries the LDS address; nothing else in this kernel
+// uses M0, and every such load sets it first.
+template <bool DEV>
+__device__ __forceinline__ void dma_dword(__amdgpu_buffer_rsrc_t desc, unsigned lds, unsigned voff)
+{
+    lds = __builtin_amdgcn_readfirstlane(lds);
+    if (DEV)
+        asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, 0 offen sc1 lds"
+                     :: "s"(lds), "v"(voff), "s"(desc) : "memory");
+    else
+        asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, 0 offen lds"
+                     :: "s"(lds), "v"(voff), "s"(desc) : "memory");
+}
+
+// Workgroup barrier for LDS traffic only: waits for this wavefront's LDS
+// operations, not for its outstanding global loads (__syncthreads() would
+// also drain those, which would stall on the prefetched faces).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ int band_has(const int* bi, int a, int b, int c)
 {
     return a >= bi[0] && a <= bi[1] && b >= bi[2] && b <= bi[3] && c >= bi[4] && c <= bi[5];
@@ -117,12 +159,13 @@ __device__ __forceinline__ int prog_index(const SysArgs& A, int a, int b, int c)
 
 // Make this workgroup's global stores visible at device scope, then set the
 // tile's progress counter (release).
+template <bool DEV>
 __device__ __forceinline__ void publish(const SysArgs& A, int me, unsigned v)
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (!DEV) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(A.progress + me, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -130,10 +173,17 @@ __device__ __forceinline__ void publish(const SysArgs& A, int me, unsigned v)
 // Wait until every listed tile's counter is >= target (acquire).  Lanes
 // 0..n-1 of the first wavefront poll one counter each.  Returns false (on
 // every thread) if a wait expired or another workgroup raised the error.
+template <bool DEV>
 __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8], int n,
-                                           unsigned target, int* s_abort)
+                                           unsigned target, int* s_abort, unsigned* s_min)
 {
     const int tid = threadIdx.x;
+    if (s_min) {
+        // every wavefront has finished reading *s_min before it is reset
+        __syncthreads();
+        if (tid == 0 && n) *s_min = 0xFFFFFFFFu;
+        __syncthreads();
+    }
     if (tid < n) {
         int my = idx[0];
 #pragma unroll
@@ -141,7 +191,8 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
             if (tid == k) my = idx[k];
         unsigned* p = A.progress + my;
         long long it = 0;
-        while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        unsigned v;
+        while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
             if (++it > A.spin_limit) {
                 atomicOr(A.error, 2);
                 *s_abort = 1;
@@ -153,24 +204,38 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // the lowest progress seen bounds every later wait of this ticket
+        if (s_min) atomicMin(s_min, v);
+        if (!DEV) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     return *s_abort == 0;
 }
 
-template <int NW>
+template <int NW, bool DEV>
 __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
 {
+    constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
     constexpr int PY = 4 * NW;
     constexpr int WY = PY - 1;
-    __shared__ float xch[2][WX][PY][PZ];  // y-neighbour exchange, two components
+    static_assert(PY == 16, "face staging assumes 16 slots on every axis");
+    // y-neighbour exchange, two components per half-step
+    __shared__ float xch[2][WX][PY][PZ];
+    // incoming faces of the next box: y face [comp][x][z], z face [comp][y][x]
+    __shared__ float yst[9][PX][PZ];
+    __shared__ __attribute__((aligned(16))) float zst[9][PY][PX];
+    // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
+    __shared__ float ytr[6][PX][PZ];
+    __shared__ __attribute__((aligned(16))) float ztr[9][PY][PX];
     __shared__ int s_ticket;
     __shared__ int s_abort;
+    __shared__ unsigned s_up;  // lower bound of the upwind neighbours' progress
 
     const int tid = threadIdx.x;
-    const int ys = tid >> 4;        // 4 rows per wavefront, NW wavefronts
-    const int zs = tid & 15;
+    const int w = tid >> 6;         // wavefront
+    const int r = (tid >> 4) & 3;   // row within the wavefront
+    const int ys = tid >> 4;        // y slot: 4 rows per wavefront, NW wavefronts
+    const int zs = tid & 15;        // z slot: lane within the DPP row
     if (tid == 0) s_abort = 0;
 
     __amdgpu_buffer_rsrc_t rf[6], rc[3];
@@ -181,8 +246,8 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
     const __amdgpu_buffer_rsrc_t rring = make_rsrc(A.ring, A.ring_bytes);
     const unsigned plane = (unsigned)A.ny * (unsigned)A.nz;
     const float cH = A.cH;
-    constexpr unsigned ring_step = 9u * PY * 16u;      // floats per (slot, local step)
-    constexpr unsigned ring_comp = PY * 16u;            // floats per component
+    constexpr unsigned ring_step = 9u * PY * PX;  // floats per (slot, local step)
+    constexpr unsigned ring_comp = PY * PX;       // floats per component
 
     float E[3][PX], H[3][PX], C[3][PX];
 
@@ -226,7 +291,7 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
         // band start: this tile and its upwind neighbours finished the previous band
         if (bnd > 0) {
             const int* bp = A.band + 8 * (bnd - 1);
-            int w[8];
+            int wl[8];
             int nw = 0;
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
@@ -235,14 +300,14 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                     const int pi = prog_index(A, ua, ub, uc);
 #pragma unroll
                     for (int k = 0; k < 8; ++k)
-                        if (k == nw) w[k] = pi;
+                        if (k == nw) wl[k] = pi;
                     ++nw;
                 }
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (k >= nw) w[k] = me;
-            if (!wait_tiles(A, w, nw, 2u * (unsigned)t0, &s_abort)) break;
+                if (k >= nw) wl[k] = me;
+            if (!wait_tiles<DEV>(A, wl, nw, 2u * (unsigned)t0, &s_abort, nullptr)) break;
         }
         // ring slot reuse: the previous occupant has finished writing it and
         // its consumer (the -z neighbour) has finished reading it
@@ -251,18 +316,18 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             const int4 pk = A.tickets[t - A.R];
             const int* pb = A.band + 8 * pk.x;
             const unsigned pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * A.K);
-            int w[8];
-            w[0] = prog_index(A, pk.y, pk.z, pk.w);
+            int wl[8];
+            wl[0] = prog_index(A, pk.y, pk.z, pk.w);
             int nw = 1;
             if (band_has(pb, pk.y, pk.z, pk.w - 1)) {
-                w[1] = prog_index(A, pk.y, pk.z, pk.w - 1);
+                wl[1] = prog_index(A, pk.y, pk.z, pk.w - 1);
                 nw = 2;
             } else {
-                w[1] = w[0];
+                wl[1] = wl[0];
             }
 #pragma unroll
-            for (int k = 2; k < 8; ++k) w[k] = w[0];
-            if (!wait_tiles(A, w, nw, pend, &s_abort)) break;
+            for (int k = 2; k < 8; ++k) wl[k] = wl[0];
+            if (!wait_tiles<DEV>(A, wl, nw, pend, &s_abort, nullptr)) break;
         }
         const int has_consumer = band_has(bi, a, b, c - 1);
         const int has_zup = band_has(bi, a, b, c + 1);
@@ -270,7 +335,9 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                                                       (bi[5] - bi[4] + 1) + (c + 1 - bi[4])] % A.R
                                      : 0;
 
-        // ---- load the slot box of step t0 + 1: lower corner o + t0
+        // ---- load the slot box of step t0 + 1 (lower corner o + t0) and
+        //      read the upwind progress once
+        if (tid == 0) s_up = nup ? 0u : 0xFFFFFFFFu;
         {
             const int by = oy + t0, bz = oz + t0;
             const int y = by + ((ys - by) & (PY - 1));
@@ -283,13 +350,15 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                 const unsigned off = (okyz && (unsigned)x < (unsigned)A.nx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    E[q][j] = bld(rf[q], off);
-                    H[q][j] = bld(rf[3 + q], off);
-                    C[q][j] = bld(rc[q], off);
+                    E[q][j] = bld<SP>(rf[q], off);
+                    H[q][j] = bld<SP>(rf[3 + q], off);
+                    C[q][j] = bld<0>(rc[q], off);
                 }
             }
         }
+        if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up)) break;
 
+        float tx[3], th[6];  // x face of the next box, prefetched into registers
         bool aborted = false;
         for (int tau = t0 + 1; tau <= t1; ++tau) {
             const int ls = tau - t0 - 1;
@@ -308,13 +377,86 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             const int y1 = by + 1 + dy1, z1 = bz + 1 + dz1;
             const bool okyz1 = (unsigned)y1 < (unsigned)A.ny && (unsigned)z1 < (unsigned)A.nz;
             const unsigned yz1 = (unsigned)y1 * (unsigned)A.nz + (unsigned)z1;
-            auto off1_at = [&](int x) -> unsigned {
-                return (okyz1 && (unsigned)x < (unsigned)A.nx) ? ((unsigned)x * plane + yz1) * 4u : kOOB;
-            };
             const unsigned ring_base = ((unsigned)slot * (unsigned)A.K + (unsigned)ls) * ring_step;
             const unsigned ring_zup = ((unsigned)slot_zup * (unsigned)A.K + (unsigned)ls) * ring_step;
+            // the forward y and z planes of the next box
+            const int yf = oy + tau + WY, zf = oz + tau + WZ;
+            // z of DPP lane zs in the next box, for the y-face loads
+            const int zl = oz + tau + ((zs - oz - tau) & (PZ - 1));
+            const bool okz_l = (unsigned)zl < (unsigned)A.nz;
+            const bool oky_f = (unsigned)yf < (unsigned)A.ny;
+            const bool okz_f = (unsigned)zf < (unsigned)A.nz;
+
+            // Issue the loads of the next box's forward shell for components
+            // [q0, q0 + nq) (0..2 = E, 3..5 = H, 6..8 = cE): the x face into
+            // registers, the y and z faces straight into LDS.
+            auto prefetch = [&](int q0, int nq) {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                if (q0 == 0) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) tx[q] = bld<SP>(rf[q], ox1);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        th[q] = bld<SP>(rf[3 + q], ox1);
+                        th[3 + q] = bld<0>(rc[q], ox1);
+                    }
+                }
+                for (int i = w; i < 4 * nq; i += NW) {
+                    const int q = q0 + (i >> 2), blk = i & 3;
+                    // y face: rows of the wavefront are x, lanes are z
+                    const int j = 4 * blk + r;
+                    const int x = ox + tau + j;
+                    const unsigned oy_ = (oky_f && okz_l && (unsigned)x < (unsigned)A.nx)
+                                             ? (((unsigned)x * (unsigned)A.ny + (unsigned)yf) * (unsigned)A.nz + (unsigned)zl) * 4u
+                                             : kOOB;
+                    if (q < 6)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rf[q], &yst[q][4 * blk][0], 4, (int)oy_, 0, 0, SP);
+                    else
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rc[q - 6], &yst[q][4 * blk][0], 4, (int)oy_, 0, 0, 0);
+                    // z face: rows are y, lanes are x, from the +z neighbour's ring slot
+                    const int yy = 4 * blk + r;  // y index within the face
+                    const bool okz = has_zup && okz_f && zs < WX && yy < WY &&
+                                     (unsigned)(ox + tau + zs) < (unsigned)A.nx &&
+                                     (unsigned)(oy + tau + yy) < (unsigned)A.ny;
+                    const unsigned oz_ = okz ? (ring_zup + (unsigned)q * ring_comp + (unsigned)yy * PX + (unsigned)zs) * 4u : kOOB;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rring, &zst[q][4 * blk][0], 4, (int)oz_, 0, 0, SP);
+                }
+            };
+            // Write the staged first-layer faces for components [q0, q0+nq)
+            // to memory (after a barrier that makes the LDS writes visible).
+            auto store_faces = [&](int q0, int nq, int nqz) {
+                __syncthreads();
+                for (int i = w; i < 4 * nq; i += NW) {
+                    const int q = q0 + (i >> 2), blk = i & 3;
+                    const int j = 4 * blk + r;
+                    // y face at y = oy + tau: cells inside the tile only
+                    const int zz = oz + tau - 1 + ((zs - oz - tau + 1) & (PZ - 1));
+                    const bool in = j < WX && ((zs - oz - tau + 1) & (PZ - 1)) >= 1 &&
+                                    (unsigned)(ox + tau + j) < (unsigned)A.nx &&
+                                    (unsigned)(oy + tau) < (unsigned)A.ny && (unsigned)zz < (unsigned)A.nz;
+                    const unsigned o = in ? ((((unsigned)(ox + tau + j)) * (unsigned)A.ny + (unsigned)(oy + tau)) *
+                                             (unsigned)A.nz + (unsigned)zz) * 4u : kOOB;
+                    bst<SP>(rf[q], o, ytr[q][j][zs]);
+                }
+                if (has_consumer) {
+                    for (int i = w; i < 4 * nqz; i += NW) {
+                        const int q = q0 + (i >> 2), blk = i & 3;
+                        const int yy = 4 * blk + r;
+                        bst<SP>(rring, (ring_base + (unsigned)q * ring_comp + (unsigned)yy * PX + (unsigned)zs) * 4u,
+                                ztr[q][yy][zs]);
+                    }
+                }
+            };
+            auto ensure_up = [&](unsigned level) -> bool {
+                if (s_up >= level) return true;
+                return wait_tiles<DEV>(A, ups, nup, level, &s_abort, &s_up);
+            };
 
             // ================= E half-step (H frame: register j <-> x = ox+tau-1+j)
+            const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
+            if (earlyE) prefetch(0, 3);
 #pragma unroll
             for (int j = 1; j < PX; ++j) {
                 xch[0][j - 1][ys][zs] = H[2][j];
@@ -370,55 +512,48 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             if (inB) {
                 const unsigned o = off_at(ox + tau);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) bst(rf[q], o, E[q][0]);
+                for (int q = 0; q < 3; ++q) bst<SP>(rf[q], o, E[q][0]);
             }
-            if (dy == 1 && dz >= 1) {
+            if (dy == 1) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
-                    const unsigned o = off_at(ox + tau + j);
+                for (int j = 0; j < WX; ++j)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) bst(rf[q], o, E[q][j]);
-                }
+                    for (int q = 0; q < 3; ++q) ytr[q][j][zs] = E[q][j];
             }
-            if (has_consumer && dz == 1 && dy >= 1) {
-                const unsigned o = (ring_base + (unsigned)(dy - 1) * 16u) * 4u;
+            if (dz == 1) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int j = 0; j < WX; ++j) bst(rring, o + (q * ring_comp + j) * 4u, E[q][j]);
+                    for (int j = 0; j < WX; ++j) ztr[q][dy1][j] = E[q][j];
             }
-            publish(A, me, 2u * (unsigned)tau - 1u);
-            if (!wait_tiles(A, ups, nup, 2u * (unsigned)tau - 1u, &s_abort)) {
-                aborted = true;
-                break;
+            store_faces(0, 3, 3);
+            if (!earlyE) {
+                if (!ensure_up(2u * (unsigned)tau - 1u)) {
+                    aborted = true;
+                    break;
+                }
+                prefetch(0, 3);
             }
+            publish<DEV>(A, me, 2u * (unsigned)tau - 1u);  // also completes the prefetch
 
-            // forward layer's E (E^tau of the upwind neighbours' first layers)
-            {
-                const unsigned o = off1_at(ox + tau + WX);
+            // forward shell's E^tau into the registers
 #pragma unroll
-                for (int q = 0; q < 3; ++q) E[q][WX] = bld(rf[q], o);
-            }
+            for (int q = 0; q < 3; ++q) E[q][WX] = tx[q];
             if (dy == 0) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
-                    const unsigned o = off1_at(ox + tau + j);
+                for (int j = 0; j < WX; ++j)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) E[q][j] = bld(rf[q], o);
-                }
+                    for (int q = 0; q < 3; ++q) E[q][j] = yst[q][j][zs];
             } else if (dz == 0) {
-                const bool ok = has_zup && (unsigned)y1 < (unsigned)A.ny && (unsigned)z1 < (unsigned)A.nz;
-                const unsigned o = (ring_zup + (unsigned)dy1 * 16u) * 4u;
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
-                    const bool okx = ok && (unsigned)(ox + tau + j) < (unsigned)A.nx;
+                for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q)
-                        E[q][j] = bld(rring, okx ? o + (q * ring_comp + j) * 4u : kOOB);
-                }
+                    for (int j = 0; j < WX; ++j) E[q][j] = zst[q][dy1][j];
             }
 
             // ================= H half-step (E frame: register j <-> x = ox+tau+j)
+            const bool earlyH = tau < t1 && s_up >= 2u * (unsigned)tau;
+            if (earlyH) prefetch(3, 6);
 #pragma unroll
             for (int j = 0; j < WX; ++j) {
                 xch[0][j][ys][zs] = E[2][j];
@@ -447,26 +582,24 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             if (inB) {
                 const unsigned o = off_at(ox + tau);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) bst(rf[3 + q], o, H[q][0]);
+                for (int q = 0; q < 3; ++q) bst<SP>(rf[3 + q], o, H[q][0]);
             }
-            if (dy == 1 && dz >= 1) {
+            if (dy == 1) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
-                    const unsigned o = off_at(ox + tau + j);
+                for (int j = 0; j < WX; ++j)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) bst(rf[3 + q], o, H[q][j]);
-                }
+                    for (int q = 0; q < 3; ++q) ytr[3 + q][j][zs] = H[q][j];
             }
-            if (has_consumer && dz == 1 && dy >= 1) {
-                const unsigned o = (ring_base + (unsigned)(dy - 1) * 16u) * 4u;
+            if (dz == 1) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
                     for (int j = 0; j < WX; ++j) {
-                        bst(rring, o + ((3 + q) * ring_comp + j) * 4u, H[q][j]);
-                        bst(rring, o + ((6 + q) * ring_comp + j) * 4u, C[q][j]);
+                        ztr[3 + q][dy1][j] = H[q][j];
+                        ztr[6 + q][dy1][j] = C[q][j];
                     }
             }
+            store_faces(3, 3, 6);
             if (tau == t1 && inB) {
                 // band end: the whole subdomain goes back to the field arrays
 #pragma unroll
@@ -474,49 +607,43 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                     const unsigned o = off_at(ox + tau + j);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        bst(rf[q], o, E[q][j]);
-                        bst(rf[3 + q], o, H[q][j]);
+                        bst<SP>(rf[q], o, E[q][j]);
+                        bst<SP>(rf[3 + q], o, H[q][j]);
                     }
                 }
             }
-            publish(A, me, 2u * (unsigned)tau);
-            if (tau == t1) break;
-            if (!wait_tiles(A, ups, nup, 2u * (unsigned)tau, &s_abort)) {
-                aborted = true;
-                break;
-            }
-
-            // forward layer's H^(tau+1/2) and coefficients
-            {
-                const unsigned o = off1_at(ox + tau + WX);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    H[q][WX] = bld(rf[3 + q], o);
-                    C[q][WX] = bld(rc[q], o);
+            if (tau < t1 && !earlyH) {
+                if (!ensure_up(2u * (unsigned)tau)) {
+                    aborted = true;
+                    break;
                 }
+                prefetch(3, 6);
+            }
+            publish<DEV>(A, me, 2u * (unsigned)tau);  // also completes the prefetch
+            if (tau == t1) break;
+
+            // forward shell's H^(tau+1/2) and coefficients into the registers
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                H[q][WX] = th[q];
+                C[q][WX] = th[3 + q];
             }
             if (dy == 0) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
-                    const unsigned o = off1_at(ox + tau + j);
+                for (int j = 0; j < WX; ++j)
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        H[q][j] = bld(rf[3 + q], o);
-                        C[q][j] = bld(rc[q], o);
+                        H[q][j] = yst[3 + q][j][zs];
+                        C[q][j] = yst[6 + q][j][zs];
                     }
-                }
             } else if (dz == 0) {
-                const bool ok = has_zup && (unsigned)y1 < (unsigned)A.ny && (unsigned)z1 < (unsigned)A.nz;
-                const unsigned o = (ring_zup + (unsigned)dy1 * 16u) * 4u;
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
-                    const bool okx = ok && (unsigned)(ox + tau + j) < (unsigned)A.nx;
+                for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        H[q][j] = bld(rring, okx ? o + ((3 + q) * ring_comp + j) * 4u : kOOB);
-                        C[q][j] = bld(rring, okx ? o + ((6 + q) * ring_comp + j) * 4u : kOOB);
+                    for (int j = 0; j < WX; ++j) {
+                        H[q][j] = zst[3 + q][dy1][j];
+                        C[q][j] = zst[6 + q][dy1][j];
                     }
-                }
             }
         }
         if (aborted) break;
@@ -537,7 +664,7 @@ constexpr int kNW = 4;  // wavefronts per tile: tile = 15 x 15 x 15 updated cell
 // Host-side plan of one call: tickets, per-band tile ranges, ring sizing.
 struct SystolicState {
     int nsteps = -1, K = -1;
-    int nt = 0, R = 1, nbands = 0;
+    int nt = 0, R = 0, D = 1, nbands = 0;
     int amin = 0, bmin = 0, cmin = 0, NA = 0, NB = 0, NC = 0;
     int4* d_tickets = nullptr;
     int* d_tix = nullptr;
@@ -619,7 +746,7 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
                 }
         pos += (size_t)na * nbb * nc;
     }
-    // ring depth: the -z consumer of ticket t must have index < t + R
+    // largest distance (in tickets) from a face producer to its -z consumer
     int R = 1;
     for (size_t t = 0; t < ntot; ++t) {
         const int4 tk = tickets[t];
@@ -634,22 +761,19 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     s->K = K;
     s->nt = (int)ntot;
     s->nbands = nb;
-    s->R = R;
+    s->D = R;
     s->amin = lo_all[0];
     s->bmin = lo_all[1];
     s->cmin = lo_all[2];
     s->NA = hi_all[0] - lo_all[0] + 1;
     s->NB = hi_all[1] - lo_all[1] + 1;
     s->NC = hi_all[2] - lo_all[2] + 1;
-    s->ring_bytes = (size_t)R * K * 9 * (4 * kNW) * 16 * sizeof(float);
-    if (s->ring_bytes >= ((size_t)1 << 32)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: face ring too large");
     hipError_t e;
     size_t nprog = (size_t)s->NA * s->NB * s->NC;
     if ((e = hipMalloc(&s->d_tickets, ntot * sizeof(int4))) != hipSuccess ||
         (e = hipMalloc(&s->d_tix, ntot * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&s->d_band, band.size() * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&s->d_progress, nprog * sizeof(unsigned))) != hipSuccess ||
-        (e = hipMalloc(&s->d_ring, s->ring_bytes)) != hipSuccess ||
         (e = hipMalloc(&s->d_counter, sizeof(unsigned))) != hipSuccess) {
         free_plan(s);
         return fail(ctx, FDTD_ENOMEM, std::string("systolic plan allocation: ") + hipGetErrorString(e));
@@ -698,15 +822,42 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
         int rc = build_plan(ctx, s, (int)nsteps, K);
         if (rc) return rc;
     }
+    // synchronisation variant: device-scope accesses (default) or cached
+    // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
+    const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
+    const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
+    auto kern = dev ? systolic_kernel<kNW, true> : systolic_kernel<kNW, false>;
     if (s->capacity == 0) {
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, systolic_kernel<kNW>, 64 * kNW, 0);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kNW, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
         hipDeviceProp_t prop;
         e = hipGetDeviceProperties(&prop, ctx->device);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDeviceProperties");
         s->capacity = std::max(1, per_cu) * prop.multiProcessorCount;
     }
+    int grid = ctx->workgroups > 0 ? ctx->workgroups : s->capacity;
+    grid = std::max(1, std::min(grid, s->nt));
+    // Face ring: a slot is reused R tickets later, after its previous
+    // occupant and that occupant's consumer have finished.  R = D + 2 * grid
+    // keeps those two long finished by the time the slot comes round again,
+    // so the reuse wait never holds a workgroup in steady state.
+    const int R = std::max(1, std::min(s->D + 2 * grid, s->nt));
+    const size_t ring_bytes = (size_t)R * s->K * 9 * (4 * kNW) * 16 * sizeof(float);
+    if (ring_bytes >= ((size_t)1 << 32)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: face ring too large");
+    if (R != s->R || !s->d_ring) {
+        if (s->d_ring) (void)hipFree(s->d_ring);
+        s->d_ring = nullptr;
+        s->R = 0;
+        hipError_t e0 = hipMalloc(&s->d_ring, ring_bytes);
+        if (e0 != hipSuccess) return fail(ctx, FDTD_ENOMEM, std::string("systolic face ring: ") + hipGetErrorString(e0));
+        s->R = R;
+        s->ring_bytes = ring_bytes;
+    }
+    ctx->sys_grid = grid;
+    ctx->sys_ring_slots = R;
+    ctx->sys_band = s->K;
+    ctx->sys_tickets = s->nt;
     const size_t nprog = (size_t)s->NA * s->NB * s->NC;
     hipLaunchKernelGGL(fill_u32, dim3(256), dim3(256), 0, ctx->stream, s->d_progress, 0u, (long long)nprog);
     hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, ctx->stream, s->d_counter, 0u, 1LL);
@@ -744,16 +895,21 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
     A.counter = s->d_counter;
     A.error = ctx->dev_error;
     A.spin_limit = ctx->spin_limit;
-    int grid = ctx->workgroups > 0 ? ctx->workgroups : s->capacity;
-    grid = std::max(1, std::min(grid, s->nt));
     PendingTiming t;
     timing_begin(ctx, FDTD_KERNEL_SYSTOLIC, &t);
-    hipLaunchKernelGGL(systolic_kernel<kNW>, dim3(grid), dim3(64 * kNW), 0, ctx->stream, A);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kNW), 0, ctx->stream, A);
     timing_end(ctx, &t);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "launch(systolic)");
     ctx->step_count += nsteps;
     return FDTD_OK;
+}
+
+void systolic_tile(int* wx, int* wy, int* wz)
+{
+    *wx = WX;
+    *wy = 4 * kNW - 1;
+    *wz = WZ;
 }
 
 void systolic_release(fdtd_ctx* ctx)

@@ -29,13 +29,15 @@ FP32, FP16_STORAGE = 0, 1
 HOST, DEVICE = 0, 1
 OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE = range(5)
 KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC = range(4)
+(INFO_SYSTOLIC_GRID, INFO_SYSTOLIC_BAND, INFO_SYSTOLIC_TICKETS, INFO_RING_SLOTS, INFO_TILE_X,
+ INFO_TILE_Y, INFO_TILE_Z) = range(7)
 SCHEMES = {"plain": SCHEME_PLAIN, "systolic": SCHEME_SYSTOLIC}
 
 # every symbol the header declares
 EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_fields",
            "fdtd_add_source", "fdtd_step", "fdtd_read_fields", "fdtd_synchronize",
            "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
-           "fdtd_kernel_stats")
+           "fdtd_kernel_stats", "fdtd_get_info")
 
 
 class FdtdError(RuntimeError):
@@ -81,6 +83,7 @@ def load_library():
         "fdtd_set_option": ([vp, ctypes.c_int, i64], ctypes.c_int),
         "fdtd_kernel_stats": ([vp, ctypes.c_int, ctypes.POINTER(i64),
                                ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "fdtd_get_info": ([vp, ctypes.c_int, ctypes.POINTER(i64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -232,6 +235,11 @@ class Simulation:
         self._check(self._lib.fdtd_kernel_stats(self._h, int(kernel), ctypes.byref(n),
                                                 ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+    def info(self, key: int) -> int:
+        v = ctypes.c_int64()
+        self._check(self._lib.fdtd_get_info(self._h, int(key), ctypes.byref(v)))
+        return int(v.value)
 
     def adjoint(self):
         self._check(self._lib.fdtd_adjoint(self._h, None, None, HOST))

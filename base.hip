@@ -230,6 +230,10 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
     __shared__ int s_ticket;
     __shared__ int s_abort;
     __shared__ unsigned s_up;  // lower bound of the upwind neighbours' progress
+    constexpr int kLdsSrc = 16;  // point sources kept in LDS (more are read from memory)
+    __shared__ int s_src[kLdsSrc][4];        // comp, i, j, k
+    __shared__ long long s_srcw[kLdsSrc][2]; // first, len
+    __shared__ const float* s_srcp[kLdsSrc];
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;         // wavefront
@@ -237,6 +241,16 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
     const int ys = tid >> 4;        // y slot: 4 rows per wavefront, NW wavefronts
     const int zs = tid & 15;        // z slot: lane within the DPP row
     if (tid == 0) s_abort = 0;
+    if (tid < min(A.nsrc, kLdsSrc)) {
+        const DevSource sq = A.src[tid];
+        s_src[tid][0] = sq.comp;
+        s_src[tid][1] = sq.i;
+        s_src[tid][2] = sq.j;
+        s_src[tid][3] = sq.k;
+        s_srcw[tid][0] = sq.first;
+        s_srcw[tid][1] = sq.len;
+        s_srcp[tid] = sq.wave;
+    }
 
     __amdgpu_buffer_rsrc_t rf[6], rc[3];
 #pragma unroll
@@ -358,7 +372,8 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
         }
         if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up)) break;
 
-        float tx[3], th[6];  // x face of the next box, prefetched into registers
+        float tx0 = 0.f, tx1 = 0.f, tx2 = 0.f;  // x face of the next box, prefetched
+        float th0 = 0.f, th1 = 0.f, th2 = 0.f, th3 = 0.f, th4 = 0.f, th5 = 0.f;
         bool aborted = false;
         for (int tau = t0 + 1; tau <= t1; ++tau) {
             const int ls = tau - t0 - 1;
@@ -388,65 +403,56 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             const bool okz_f = (unsigned)zf < (unsigned)A.nz;
 
             // Issue the loads of the next box's forward shell for components
-            // [q0, q0 + nq) (0..2 = E, 3..5 = H, 6..8 = cE): the x face into
-            // registers, the y and z faces straight into LDS.
-            auto prefetch = [&](int q0, int nq) {
-                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
-                if (q0 == 0) {
+            // [Q0, Q0 + NQ) (0..2 = E, 3..5 = H, 6..8 = cE): the x face into
+            // registers, the y and z faces straight into LDS.  Wavefront w
+            // loads rows 4w..4w+3 of every component of both faces.
+            auto prefetch = [&](auto q0c, auto nqc) {
+                constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
+                // y face: rows of the wavefront are x, lanes are z
+                const int j = 4 * w + r;
+                const int x = ox + tau + j;
+                const unsigned oyf = (oky_f && okz_l && (unsigned)x < (unsigned)A.nx)
+                                         ? (((unsigned)x * (unsigned)A.ny + (unsigned)yf) * (unsigned)A.nz + (unsigned)zl) * 4u
+                                         : kOOB;
+                // z face: rows are y, lanes are x, from the +z neighbour's ring slot
+                const int yy = 4 * w + r;
+                const bool okz = has_zup && okz_f && zs < WX && yy < WY &&
+                                 (unsigned)(ox + tau + zs) < (unsigned)A.nx &&
+                                 (unsigned)(oy + tau + yy) < (unsigned)A.ny;
+                const unsigned ozf = (ring_zup + (unsigned)yy * PX + (unsigned)zs) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) tx[q] = bld<SP>(rf[q], ox1);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        th[q] = bld<SP>(rf[3 + q], ox1);
-                        th[3 + q] = bld<0>(rc[q], ox1);
-                    }
-                }
-                for (int i = w; i < 4 * nq; i += NW) {
-                    const int q = q0 + (i >> 2), blk = i & 3;
-                    // y face: rows of the wavefront are x, lanes are z
-                    const int j = 4 * blk + r;
-                    const int x = ox + tau + j;
-                    const unsigned oy_ = (oky_f && okz_l && (unsigned)x < (unsigned)A.nx)
-                                             ? (((unsigned)x * (unsigned)A.ny + (unsigned)yf) * (unsigned)A.nz + (unsigned)zl) * 4u
-                                             : kOOB;
+                for (int q = Q0; q < Q0 + NQ; ++q) {
+                    const unsigned ly = lds_offset(&yst[q][4 * w][0]);
                     if (q < 6)
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rf[q], &yst[q][4 * blk][0], 4, (int)oy_, 0, 0, SP);
+                        dma_dword<DEV>(rf[q], ly, oyf);
                     else
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rc[q - 6], &yst[q][4 * blk][0], 4, (int)oy_, 0, 0, 0);
-                    // z face: rows are y, lanes are x, from the +z neighbour's ring slot
-                    const int yy = 4 * blk + r;  // y index within the face
-                    const bool okz = has_zup && okz_f && zs < WX && yy < WY &&
-                                     (unsigned)(ox + tau + zs) < (unsigned)A.nx &&
-                                     (unsigned)(oy + tau + yy) < (unsigned)A.ny;
-                    const unsigned oz_ = okz ? (ring_zup + (unsigned)q * ring_comp + (unsigned)yy * PX + (unsigned)zs) * 4u : kOOB;
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rring, &zst[q][4 * blk][0], 4, (int)oz_, 0, 0, SP);
+                        dma_dword<false>(rc[q - 6], ly, oyf);
+                    dma_dword<DEV>(rring, lds_offset(&zst[q][4 * w][0]),
+                                   okz ? ozf + (unsigned)q * ring_comp * 4u : kOOB);
                 }
             };
-            // Write the staged first-layer faces for components [q0, q0+nq)
-            // to memory (after a barrier that makes the LDS writes visible).
-            auto store_faces = [&](int q0, int nq, int nqz) {
-                __syncthreads();
-                for (int i = w; i < 4 * nq; i += NW) {
-                    const int q = q0 + (i >> 2), blk = i & 3;
-                    const int j = 4 * blk + r;
-                    // y face at y = oy + tau: cells inside the tile only
-                    const int zz = oz + tau - 1 + ((zs - oz - tau + 1) & (PZ - 1));
-                    const bool in = j < WX && ((zs - oz - tau + 1) & (PZ - 1)) >= 1 &&
-                                    (unsigned)(ox + tau + j) < (unsigned)A.nx &&
-                                    (unsigned)(oy + tau) < (unsigned)A.ny && (unsigned)zz < (unsigned)A.nz;
-                    const unsigned o = in ? ((((unsigned)(ox + tau + j)) * (unsigned)A.ny + (unsigned)(oy + tau)) *
-                                             (unsigned)A.nz + (unsigned)zz) * 4u : kOOB;
-                    bst<SP>(rf[q], o, ytr[q][j][zs]);
-                }
+            // Write the staged first-layer faces for components [Q0, Q0+NQ)
+            // (z face: [Q0, Q0+NQZ)) to memory, after a barrier that makes the
+            // LDS writes visible.  Wavefront w writes rows 4w..4w+3.
+            auto store_faces = [&](auto q0c, auto nqc, auto nqzc) {
+                constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
+                constexpr int NQZ = decltype(nqzc)::value;
+                lds_barrier();
+                const int j = 4 * w + r;
+                // y face at y = oy + tau: cells inside the tile only
+                const int dzl = (zs - oz - tau + 1) & (PZ - 1);
+                const int zz = oz + tau - 1 + dzl;
+                const bool in = j < WX && dzl >= 1 && (unsigned)(ox + tau + j) < (unsigned)A.nx &&
+                                (unsigned)(oy + tau) < (unsigned)A.ny && (unsigned)zz < (unsigned)A.nz;
+                const unsigned o = in ? ((((unsigned)(ox + tau + j)) * (unsigned)A.ny + (unsigned)(oy + tau)) *
+                                         (unsigned)A.nz + (unsigned)zz) * 4u : kOOB;
+#pragma unroll
+                for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rf[q], o, ytr[q][j][zs]);
                 if (has_consumer) {
-                    for (int i = w; i < 4 * nqz; i += NW) {
-                        const int q = q0 + (i >> 2), blk = i & 3;
-                        const int yy = 4 * blk + r;
-                        bst<SP>(rring, (ring_base + (unsigned)q * ring_comp + (unsigned)yy * PX + (unsigned)zs) * 4u,
-                                ztr[q][yy][zs]);
-                    }
+                    const unsigned oz_ = (ring_base + (unsigned)j * PX + (unsigned)zs) * 4u;
+#pragma unroll
+                    for (int q = Q0; q < Q0 + NQZ; ++q)
+                        bst<SP>(rring, oz_ + (unsigned)q * ring_comp * 4u, ztr[q][j][zs]);
                 }
             };
             auto ensure_up = [&](unsigned level) -> bool {
@@ -456,13 +462,29 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
 
             // ================= E half-step (H frame: register j <-> x = ox+tau-1+j)
             const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
-            if (earlyE) prefetch(0, 3);
+            if (earlyE) {
+                prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
+                {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                tx0 = bld<SP>(rf[0], ox1);
+                tx1 = bld<SP>(rf[1], ox1);
+                tx2 = bld<SP>(rf[2], ox1);
+            }
+                {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                tx0 = bld<SP>(rf[0], ox1);
+                tx1 = bld<SP>(rf[1], ox1);
+                tx2 = bld<SP>(rf[2], ox1);
+            }
+            }
 #pragma unroll
             for (int j = 1; j < PX; ++j) {
                 xch[0][j - 1][ys][zs] = H[2][j];
                 xch[1][j - 1][ys][zs] = H[0][j];
             }
-            __syncthreads();
+            lds_barrier();
             {
                 const int ysm = (ys - 1) & (PY - 1);
 #pragma unroll
@@ -484,27 +506,47 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             }
             // now E and C registers j <-> x = ox+tau+j (j = 0..14); j = 15 stale
 
-            // point sources of this step on cells of the tile
-            {
-                const long long s = A.step0 + tau - 1;
-                for (int q = 0; q < A.nsrc; ++q) {
-                    const DevSource sq = A.src[q];
-                    const long long m = s - sq.first;
-                    if (m < 0 || m >= sq.len) continue;
-                    const int px = sq.i - (ox + tau), py = sq.j - (oy + tau), pz = sq.k - (oz + tau);
-                    if ((unsigned)px >= (unsigned)WX || (unsigned)py >= (unsigned)WY || (unsigned)pz >= (unsigned)WZ)
-                        continue;
-                    const float wv = sq.wave[m];
-                    if (dy == py + 1 && dz == pz + 1) {
+            // point sources of this step on cells of the tile (registers are
+            // only ever indexed with compile-time constants, so they stay in
+            // VGPRs)
+            for (int q = 0; q < A.nsrc; ++q) {
+                int comp, si, sj, sk;
+                long long first, len;
+                const float* wave;
+                if (q < kLdsSrc) {
+                    comp = s_src[q][0];
+                    si = s_src[q][1];
+                    sj = s_src[q][2];
+                    sk = s_src[q][3];
+                    first = s_srcw[q][0];
+                    len = s_srcw[q][1];
+                    wave = s_srcp[q];
+                } else {
+                    comp = A.src[q].comp;
+                    si = A.src[q].i;
+                    sj = A.src[q].j;
+                    sk = A.src[q].k;
+                    first = A.src[q].first;
+                    len = A.src[q].len;
+                    wave = A.src[q].wave;
+                }
+                const long long m = A.step0 + tau - 1 - first;
+                const int px = si - (ox + tau), py = sj - (oy + tau), pz = sk - (oz + tau);
+                if (m < 0 || m >= len || (unsigned)px >= (unsigned)WX || (unsigned)py >= (unsigned)WY ||
+                    (unsigned)pz >= (unsigned)WZ)
+                    continue;
+                const float wv = wave[m];
+                // the source's register index on its lane, -1 on every other lane
+                const int lx = (dy == py + 1 && dz == pz + 1) ? px : -1;
+                if (comp == 0) {
 #pragma unroll
-                        for (int j = 0; j < WX; ++j) {
-                            if (j == px) {
-                                if (sq.comp == 0) E[0][j] = E[0][j] + wv;
-                                if (sq.comp == 1) E[1][j] = E[1][j] + wv;
-                                if (sq.comp == 2) E[2][j] = E[2][j] + wv;
-                            }
-                        }
-                    }
+                    for (int j = 0; j < WX; ++j) E[0][j] = lx == j ? E[0][j] + wv : E[0][j];
+                } else if (comp == 1) {
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) E[1][j] = lx == j ? E[1][j] + wv : E[1][j];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) E[2][j] = lx == j ? E[2][j] + wv : E[2][j];
                 }
             }
 
@@ -526,19 +568,27 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
 #pragma unroll
                     for (int j = 0; j < WX; ++j) ztr[q][dy1][j] = E[q][j];
             }
-            store_faces(0, 3, 3);
+            store_faces(std::integral_constant<int, 0>(), std::integral_constant<int, 3>(), std::integral_constant<int, 3>());
             if (!earlyE) {
                 if (!ensure_up(2u * (unsigned)tau - 1u)) {
                     aborted = true;
                     break;
                 }
-                prefetch(0, 3);
+                prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
+                {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                tx0 = bld<SP>(rf[0], ox1);
+                tx1 = bld<SP>(rf[1], ox1);
+                tx2 = bld<SP>(rf[2], ox1);
+            }
             }
             publish<DEV>(A, me, 2u * (unsigned)tau - 1u);  // also completes the prefetch
 
             // forward shell's E^tau into the registers
-#pragma unroll
-            for (int q = 0; q < 3; ++q) E[q][WX] = tx[q];
+            E[0][WX] = tx0;
+            E[1][WX] = tx1;
+            E[2][WX] = tx2;
             if (dy == 0) {
 #pragma unroll
                 for (int j = 0; j < WX; ++j)
@@ -553,13 +603,35 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
 
             // ================= H half-step (E frame: register j <-> x = ox+tau+j)
             const bool earlyH = tau < t1 && s_up >= 2u * (unsigned)tau;
-            if (earlyH) prefetch(3, 6);
+            if (earlyH) {
+                prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
+                {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                th0 = bld<SP>(rf[3], ox1);
+                th1 = bld<SP>(rf[4], ox1);
+                th2 = bld<SP>(rf[5], ox1);
+                th3 = bld<0>(rc[0], ox1);
+                th4 = bld<0>(rc[1], ox1);
+                th5 = bld<0>(rc[2], ox1);
+            }
+                {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                th0 = bld<SP>(rf[3], ox1);
+                th1 = bld<SP>(rf[4], ox1);
+                th2 = bld<SP>(rf[5], ox1);
+                th3 = bld<0>(rc[0], ox1);
+                th4 = bld<0>(rc[1], ox1);
+                th5 = bld<0>(rc[2], ox1);
+            }
+            }
 #pragma unroll
             for (int j = 0; j < WX; ++j) {
                 xch[0][j][ys][zs] = E[2][j];
                 xch[1][j][ys][zs] = E[0][j];
             }
-            __syncthreads();
+            lds_barrier();
             {
                 const int ysp = (ys + 1) & (PY - 1);
 #pragma unroll
@@ -599,7 +671,7 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                         ztr[6 + q][dy1][j] = C[q][j];
                     }
             }
-            store_faces(3, 3, 6);
+            store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
             if (tau == t1 && inB) {
                 // band end: the whole subdomain goes back to the field arrays
 #pragma unroll
@@ -617,17 +689,28 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                     aborted = true;
                     break;
                 }
-                prefetch(3, 6);
+                prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
+                {
+                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                th0 = bld<SP>(rf[3], ox1);
+                th1 = bld<SP>(rf[4], ox1);
+                th2 = bld<SP>(rf[5], ox1);
+                th3 = bld<0>(rc[0], ox1);
+                th4 = bld<0>(rc[1], ox1);
+                th5 = bld<0>(rc[2], ox1);
+            }
             }
             publish<DEV>(A, me, 2u * (unsigned)tau);  // also completes the prefetch
             if (tau == t1) break;
 
             // forward shell's H^(tau+1/2) and coefficients into the registers
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                H[q][WX] = th[q];
-                C[q][WX] = th[3 + q];
-            }
+            H[0][WX] = th0;
+            H[1][WX] = th1;
+            H[2][WX] = th2;
+            C[0][WX] = th3;
+            C[1][WX] = th4;
+            C[2][WX] = th5;
             if (dy == 0) {
 #pragma unroll
                 for (int j = 0; j < WX; ++j)

@@ -34,6 +34,25 @@ FLOPS_PER_CELL = 36            # 6 components x 6 flops (Section 2)
 PLAIN_E_BYTES, PLAIN_H_BYTES = 48, 36   # algorithmic bytes per cell, per half-step kernel
 
 
+def counter_traffic(kernel: str, source: str, launch: dict):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/hbm_traffic.json), or None when the summary was taken on another
+    version of the kernel's source or another launch configuration."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        tr = json.load(open(path))
+        have = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()[:16]
+        cells = launch["cells"]
+        key = {k: v for k, v in launch.items() if k != "cells"}
+        if tr["_sources"].get(source) != have or tr[kernel]["launch"] != key:
+            return None
+        k = tr[kernel]
+        return (k["fetch_bytes_per_update"] + k["write_bytes_per_update"]) * cells * launch["steps"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -129,6 +148,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--band", type=int, default=0, help="systolic band length (0 = default)")
     ap.add_argument("--workgroups", type=int, default=0, help="systolic grid size (0 = auto)")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (read + write), the "
+                         "reference dispatch for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -138,6 +160,15 @@ def main():
     import torch
     from paper_2502_20610_amd import fdtd
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mb:
+        n = args.calibrate_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # reads and writes exactly n*4 bytes each
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.calibrate_copy_mb, args.calibrate_copy_mb))
+        del src, dst
     log("building workload %s" % args.workload)
     w = make_workload(args.workload)
     cells = w.cells
@@ -170,15 +201,22 @@ def main():
         avg_s = ms / 1e3 / max(n, 1)
         steps_per_launch = args.steps / max(n, 1)
         achieved = FLOPS_PER_CELL * cells * steps_per_launch / avg_s / 1e12
+        launch = {"workload": w.name, "steps": int(round(steps_per_launch)),
+                  "band": stats["info"]["band_steps"]}
+        traffic = counter_traffic("systolic_kernel", "paper_2502_20610_amd/csrc/systolic.hip",
+                                  dict(launch, cells=cells))
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": None,
-                "kernel": "systolic_kernel", "launches": n, "avg_launch_ms": avg_s * 1e3}
+                "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": "systolic_kernel", "launches": n, "avg_launch_ms": avg_s * 1e3,
+                "traffic_GBps": None if traffic is None else traffic / avg_s / 1e9}
     else:
         n, ms = stats[fdtd.KERNEL_PLAIN_E]
         avg_s = ms / 1e3 / max(n, 1)
         achieved = PLAIN_E_BYTES * cells / avg_s / 1e9
+        traffic = counter_traffic("plain_E_kernel", "paper_2502_20610_amd/csrc/plain.hip",
+                                  {"workload": w.name, "steps": 1, "cells": cells})
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "plain_E_kernel",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "plain_E_kernel",
                 "launches": n, "avg_launch_ms": avg_s * 1e3}
 
     out = {

@@ -1,0 +1,98 @@
+"""Parity at the full 1024x1024x512 size, in the launch configuration of the
+benchmark, on sampled cells.
+
+After n steps a cell depends only on cells within n of it on each axis (one
+cell per axis per step), so each sample is recomputed by the FP32 oracle on a
+crop of half-width n+2 around it.  A crop that ends at the grid's upper wall
+gets an artificial PEC plane at its own lower end (its tangential E zeroed),
+so that its periodic wrap reproduces the wall; that plane is more than n
+cells from the sample and cannot reach it.  Crops that start at the lower
+wall keep the real wall; interior crops wrap periodically, again more than n
+cells from the sample.  Samples cover the interior, every wall, edges,
+corners and the three dipoles.  Values are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_20610_amd import fdtd
+from paper_2502_20610_amd import workloads as wl
+from tests.crop_oracle import crop_oracle as _crop_oracle
+
+pytestmark = pytest.mark.gpu
+PEC, PER = 0, 1
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+if not _gpu_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _samples(w, rng):
+    nx, ny, nz = w.shape
+    pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (0, ny - 1, nz // 2), (nx - 1, 0, 1),
+           (nx // 2, 0, nz - 1), (1, ny // 2, 0), (nx - 1, ny // 2, nz // 2),
+           (nx // 2, ny - 1, nz // 2), (nx // 2, ny // 2, nz - 1), (nx // 3, ny // 5, 7)]
+    for s in w.sources:
+        pts.append((s["i"], s["j"], s["k"]))
+        pts.append((s["i"] + 1, s["j"], s["k"] - 1))
+    for _ in range(8):
+        pts.append(tuple(int(rng.integers(0, n)) for n in w.shape))
+    # cells on tile edges of the systolic tiling at the first and last step
+    pts += [(15 * 20 - 1, 15 * 30, 15 * 10 + 3), (15 * 40 + 8, 15 * 50 - 1, 15 * 20 - 1)]
+    return pts
+
+
+@pytest.mark.parametrize("scheme,band", [("systolic", 4), ("systolic", 16), ("plain", 0)])
+def test_fullsize_sampled_bitwise(scheme, band):
+    import torch
+    w = wl.c3_large_dielectric(nsteps=8)
+    nsteps = 8 if scheme == "plain" else 2 * band
+    pts = _samples(w, np.random.default_rng(5))
+    # seeded noise in the dependency cone of every sample, so that no sampled
+    # value is trivially zero
+    rng = np.random.default_rng(77)
+    fields = [np.zeros(w.shape, np.float32) for _ in range(6)]
+    r = nsteps + 2
+    for p in pts:
+        sl = tuple(slice(max(0, p[a] - r), min(w.shape[a], p[a] + r + 1)) for a in range(3))
+        for f in fields:
+            f[sl] = rng.uniform(-1e-2, 1e-2, size=f[sl].shape).astype(np.float32)
+    wl.zero_pec(fields, w.bc)
+    w.fields = tuple(fields)
+    dev = torch.device("cuda:0")
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme)
+    try:
+        if band:
+            sim.set_option(fdtd.OPT_BAND_STEPS, band)
+        sim.set_materials(torch.from_numpy(w.eps).to(dev))
+        sim.set_fields([torch.from_numpy(f).to(dev) for f in w.fields])
+        for s in w.sources:
+            sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+        sim.step(nsteps)
+        idx = torch.tensor(pts, dtype=torch.long, device=dev)
+        got = []
+        for c in range(6):
+            buf = torch.empty(w.shape, dtype=torch.float32, device=dev)
+            sim.read_fields(mask=1 << c, out=[buf] * 6)
+            sim.synchronize()
+            got.append(buf[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy())
+            del buf
+        got = np.stack(got, axis=1)
+    finally:
+        sim.close()
+    bad = []
+    for n, p in enumerate(pts):
+        ref = _crop_oracle(w, p, nsteps)
+        if not np.array_equal(ref.view(np.uint32), got[n].view(np.uint32)):
+            bad.append((p, got[n], ref))
+    assert not bad, "%d/%d samples differ, first %s" % (len(bad), len(pts), bad[0])
+    # the check is not vacuous: most sampled cells are non-zero
+    assert np.count_nonzero(got) > got.size // 2

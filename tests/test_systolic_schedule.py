@@ -91,3 +91,19 @@ def test_emulator_detects_a_missing_wait(monkeypatch):
             differs = True
             break
     assert differs
+
+
+def test_crop_oracle_reproduces_full_runs():
+    """The sampled full-size parity check recomputes cells on crops; the crop
+    construction must give exactly the full-grid value (walls, edges, corners,
+    interior, sources)."""
+    from tests.crop_oracle import crop_oracle
+    w = wl.random_dielectric((40, 36, 44), (PEC, PEC, PEC), 10, 3, 6, side=(2, 10), noise=0.1,
+                             dipoles=[(20, 18, 22)])
+    full = oracle.run(w.fields, w.eps3(), w.bc, w.dt, w.dx, 6, sources=w.sources,
+                      dtype=np.float32)
+    for p in [(0, 0, 0), (39, 35, 43), (0, 35, 20), (39, 0, 1), (20, 0, 43), (1, 18, 0),
+              (39, 18, 22), (20, 35, 22), (20, 18, 43), (13, 7, 7), (20, 18, 22), (21, 18, 21)]:
+        ref = crop_oracle(w, p, 6)
+        val = np.array([f[p] for f in full], np.float32)
+        np.testing.assert_array_equal(ref.view(np.uint32), val.view(np.uint32), err_msg=str(p))

@@ -152,7 +152,8 @@ int fdtd_adjoint(fdtd_ctx* ctx, const void* objective, float* grad_eps, int wher
 
 enum {
     FDTD_OPT_SCHEME = 0,      /* switch scheme on a live context (state kept) */
-    FDTD_OPT_BAND_STEPS = 1,  /* systolic: steps each tile stays resident (>=1) */
+    FDTD_OPT_BAND_STEPS = 1,  /* systolic: steps each tile stays resident:
+                                 1..64, larger values act as 64; 0 = auto  */
     FDTD_OPT_WORKGROUPS = 2,  /* systolic: persistent grid size, 0 = auto       */
     FDTD_OPT_SPIN_LIMIT = 3,  /* systolic: polls before a wait times out        */
     FDTD_OPT_PROFILE = 4      /* 1 = time every kernel launch with HIP events    */

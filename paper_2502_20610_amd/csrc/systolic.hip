@@ -56,6 +56,9 @@ constexpr int PX = 16, PZ = 16;         // slots along x (registers) and z (lane
 constexpr int WX = PX - 1, WZ = PZ - 1; // updated cells along x and z
 constexpr unsigned kOOB = 0xFFFFFFF0u;  // buffer offset that reads 0 / drops stores
 
+// longest band: the per-band source samples are staged in LDS
+constexpr int kMaxBand = 64;
+
 struct SysArgs {
     float* f[6];
     const float* cE[3];
@@ -213,7 +216,7 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
 }
 
 template <int NW, bool DEV>
-__global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void systolic_kernel(SysArgs A)
 {
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
     constexpr int PY = 4 * NW;
@@ -222,6 +225,7 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
     // y-neighbour exchange, two components per half-step
     __shared__ float xch[2][WX][PY][PZ];
     // incoming faces of the next box: y face [comp][x][z], z face [comp][y][x]
+    __shared__ float xst[9][PY][PZ];   // x face [comp][y slot][z slot]
     __shared__ float yst[9][PX][PZ];
     __shared__ __attribute__((aligned(16))) float zst[9][PY][PX];
     // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
@@ -234,6 +238,7 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
     __shared__ int s_src[kLdsSrc][4];        // comp, i, j, k
     __shared__ long long s_srcw[kLdsSrc][2]; // first, len
     __shared__ const float* s_srcp[kLdsSrc];
+    __shared__ float s_wv[kLdsSrc][kMaxBand];  // their samples for the steps of the current band
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;         // wavefront
@@ -349,6 +354,16 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                                                       (bi[5] - bi[4] + 1) + (c + 1 - bi[4])] % A.R
                                      : 0;
 
+        // ---- the band's samples of the LDS-cached sources (step tau reads
+        //      sample step0 + tau - 1 - first; the range test is repeated at use)
+        {
+            const int nl = min(A.nsrc, kLdsSrc);
+            for (int i = tid; i < nl * kMaxBand; i += 64 * NW) {
+                const int q = i / kMaxBand, l = i % kMaxBand;
+                const long long m = A.step0 + t0 + l - s_srcw[q][0];
+                s_wv[q][l] = (l < t1 - t0 && m >= 0 && m < s_srcw[q][1]) ? s_srcp[q][m] : 0.f;
+            }
+        }
         // ---- load the slot box of step t0 + 1 (lower corner o + t0) and
         //      read the upwind progress once
         if (tid == 0) s_up = nup ? 0u : 0xFFFFFFFFu;
@@ -372,8 +387,6 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
         }
         if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up)) break;
 
-        float tx0 = 0.f, tx1 = 0.f, tx2 = 0.f;  // x face of the next box, prefetched
-        float th0 = 0.f, th1 = 0.f, th2 = 0.f, th3 = 0.f, th4 = 0.f, th5 = 0.f;
         bool aborted = false;
         for (int tau = t0 + 1; tau <= t1; ++tau) {
             const int ls = tau - t0 - 1;
@@ -408,6 +421,9 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             // loads rows 4w..4w+3 of every component of both faces.
             auto prefetch = [&](auto q0c, auto nqc) {
                 constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
+                // x face: rows of the wavefront are y slots, lanes are z slots
+                const unsigned oxf = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
+                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
                 // y face: rows of the wavefront are x, lanes are z
                 const int j = 4 * w + r;
                 const int x = ox + tau + j;
@@ -423,10 +439,14 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) {
                     const unsigned ly = lds_offset(&yst[q][4 * w][0]);
-                    if (q < 6)
+                    const unsigned lx = lds_offset(&xst[q][4 * w][0]);
+                    if (q < 6) {
+                        dma_dword<DEV>(rf[q], lx, oxf);
                         dma_dword<DEV>(rf[q], ly, oyf);
-                    else
+                    } else {
+                        dma_dword<false>(rc[q - 6], lx, oxf);
                         dma_dword<false>(rc[q - 6], ly, oyf);
+                    }
                     dma_dword<DEV>(rring, lds_offset(&zst[q][4 * w][0]),
                                    okz ? ozf + (unsigned)q * ring_comp * 4u : kOOB);
                 }
@@ -462,23 +482,7 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
 
             // ================= E half-step (H frame: register j <-> x = ox+tau-1+j)
             const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
-            if (earlyE) {
-                prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
-                {
-                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
-                tx0 = bld<SP>(rf[0], ox1);
-                tx1 = bld<SP>(rf[1], ox1);
-                tx2 = bld<SP>(rf[2], ox1);
-            }
-                {
-                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
-                tx0 = bld<SP>(rf[0], ox1);
-                tx1 = bld<SP>(rf[1], ox1);
-                tx2 = bld<SP>(rf[2], ox1);
-            }
-            }
+            if (earlyE) prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
 #pragma unroll
             for (int j = 1; j < PX; ++j) {
                 xch[0][j - 1][ys][zs] = H[2][j];
@@ -509,46 +513,35 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
             // point sources of this step on cells of the tile (registers are
             // only ever indexed with compile-time constants, so they stay in
             // VGPRs)
-            for (int q = 0; q < A.nsrc; ++q) {
-                int comp, si, sj, sk;
-                long long first, len;
-                const float* wave;
-                if (q < kLdsSrc) {
-                    comp = s_src[q][0];
-                    si = s_src[q][1];
-                    sj = s_src[q][2];
-                    sk = s_src[q][3];
-                    first = s_srcw[q][0];
-                    len = s_srcw[q][1];
-                    wave = s_srcp[q];
-                } else {
-                    comp = A.src[q].comp;
-                    si = A.src[q].i;
-                    sj = A.src[q].j;
-                    sk = A.src[q].k;
-                    first = A.src[q].first;
-                    len = A.src[q].len;
-                    wave = A.src[q].wave;
-                }
-                const long long m = A.step0 + tau - 1 - first;
-                const int px = si - (ox + tau), py = sj - (oy + tau), pz = sk - (oz + tau);
-                if (m < 0 || m >= len || (unsigned)px >= (unsigned)WX || (unsigned)py >= (unsigned)WY ||
-                    (unsigned)pz >= (unsigned)WZ)
-                    continue;
-                const float wv = wave[m];
-                // the source's register index on its lane, -1 on every other lane
-                const int lx = (dy == py + 1 && dz == pz + 1) ? px : -1;
-                if (comp == 0) {
-#pragma unroll
-                    for (int j = 0; j < WX; ++j) E[0][j] = lx == j ? E[0][j] + wv : E[0][j];
-                } else if (comp == 1) {
-#pragma unroll
-                    for (int j = 0; j < WX; ++j) E[1][j] = lx == j ? E[1][j] + wv : E[1][j];
-                } else {
-#pragma unroll
-                    for (int j = 0; j < WX; ++j) E[2][j] = lx == j ? E[2][j] + wv : E[2][j];
-                }
+            // (the LDS-cached and the remaining sources are read in separate loops
+            // so that neither becomes a generic-address load)
+#define FDTD_APPLY_SOURCE(comp, si, sj, sk, first, len, sample)                                        \
+    {                                                                                               \
+        const long long m = A.step0 + tau - 1 - (first);                                            \
+        const int px = (si) - (ox + tau), py = (sj) - (oy + tau), pz = (sk) - (oz + tau);           \
+        if (m >= 0 && m < (len) && (unsigned)px < (unsigned)WX && (unsigned)py < (unsigned)WY &&    \
+            (unsigned)pz < (unsigned)WZ) {                                                          \
+            const float wv = (sample);                                                              \
+            const int lx = (dy == py + 1 && dz == pz + 1) ? px : -1;                                \
+            if ((comp) == 0) {                                                                      \
+                _Pragma("unroll") for (int j = 0; j < WX; ++j) E[0][j] = lx == j ? E[0][j] + wv : E[0][j]; \
+            } else if ((comp) == 1) {                                                               \
+                _Pragma("unroll") for (int j = 0; j < WX; ++j) E[1][j] = lx == j ? E[1][j] + wv : E[1][j]; \
+            } else {                                                                                \
+                _Pragma("unroll") for (int j = 0; j < WX; ++j) E[2][j] = lx == j ? E[2][j] + wv : E[2][j]; \
+            }                                                                                       \
+        }                                                                                           \
+    }
+            {
+                const int nl = min(A.nsrc, kLdsSrc);
+                for (int q = 0; q < nl; ++q)
+                    FDTD_APPLY_SOURCE(s_src[q][0], s_src[q][1], s_src[q][2], s_src[q][3], s_srcw[q][0],
+                                      s_srcw[q][1], s_wv[q][ls]);
+                for (int q = kLdsSrc; q < A.nsrc; ++q)
+                    FDTD_APPLY_SOURCE(A.src[q].comp, A.src[q].i, A.src[q].j, A.src[q].k, A.src[q].first,
+                                      A.src[q].len, A.src[q].wave[m]);
             }
+#undef FDTD_APPLY_SOURCE
 
             // publish E of the first layer of the tile
             if (inB) {
@@ -575,20 +568,12 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                     break;
                 }
                 prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
-                {
-                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
-                tx0 = bld<SP>(rf[0], ox1);
-                tx1 = bld<SP>(rf[1], ox1);
-                tx2 = bld<SP>(rf[2], ox1);
-            }
             }
             publish<DEV>(A, me, 2u * (unsigned)tau - 1u);  // also completes the prefetch
 
             // forward shell's E^tau into the registers
-            E[0][WX] = tx0;
-            E[1][WX] = tx1;
-            E[2][WX] = tx2;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) E[q][WX] = xst[q][ys][zs];
             if (dy == 0) {
 #pragma unroll
                 for (int j = 0; j < WX; ++j)
@@ -603,29 +588,7 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
 
             // ================= H half-step (E frame: register j <-> x = ox+tau+j)
             const bool earlyH = tau < t1 && s_up >= 2u * (unsigned)tau;
-            if (earlyH) {
-                prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
-                {
-                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
-                th0 = bld<SP>(rf[3], ox1);
-                th1 = bld<SP>(rf[4], ox1);
-                th2 = bld<SP>(rf[5], ox1);
-                th3 = bld<0>(rc[0], ox1);
-                th4 = bld<0>(rc[1], ox1);
-                th5 = bld<0>(rc[2], ox1);
-            }
-                {
-                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
-                th0 = bld<SP>(rf[3], ox1);
-                th1 = bld<SP>(rf[4], ox1);
-                th2 = bld<SP>(rf[5], ox1);
-                th3 = bld<0>(rc[0], ox1);
-                th4 = bld<0>(rc[1], ox1);
-                th5 = bld<0>(rc[2], ox1);
-            }
-            }
+            if (earlyH) prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
 #pragma unroll
             for (int j = 0; j < WX; ++j) {
                 xch[0][j][ys][zs] = E[2][j];
@@ -690,27 +653,16 @@ __global__ __launch_bounds__(64 * NW) void systolic_kernel(SysArgs A)
                     break;
                 }
                 prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
-                {
-                const unsigned ox1 = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
-                th0 = bld<SP>(rf[3], ox1);
-                th1 = bld<SP>(rf[4], ox1);
-                th2 = bld<SP>(rf[5], ox1);
-                th3 = bld<0>(rc[0], ox1);
-                th4 = bld<0>(rc[1], ox1);
-                th5 = bld<0>(rc[2], ox1);
-            }
             }
             publish<DEV>(A, me, 2u * (unsigned)tau);  // also completes the prefetch
             if (tau == t1) break;
 
             // forward shell's H^(tau+1/2) and coefficients into the registers
-            H[0][WX] = th0;
-            H[1][WX] = th1;
-            H[2][WX] = th2;
-            C[0][WX] = th3;
-            C[1][WX] = th4;
-            C[2][WX] = th5;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                H[q][WX] = xst[3 + q][ys][zs];
+                C[q][WX] = xst[6 + q][ys][zs];
+            }
             if (dy == 0) {
 #pragma unroll
                 for (int j = 0; j < WX; ++j)
@@ -872,8 +824,8 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 
 int default_band(const fdtd_ctx* ctx, int64_t nsteps)
 {
-    if (ctx->band_steps > 0) return (int)std::min<int64_t>(ctx->band_steps, nsteps);
-    return (int)std::min<int64_t>(16, nsteps);
+    if (ctx->band_steps > 0) return (int)std::min<int64_t>(std::min(ctx->band_steps, kMaxBand), nsteps);
+    return (int)std::min<int64_t>(32, nsteps);
 }
 
 }  // namespace

@@ -81,6 +81,9 @@ struct SysArgs {
     unsigned* counter;
     int* error;
     long long spin_limit;
+    int per[3];  // periodic axis: tiles form a ring, positions wrap
+    int L[3];    // tiles of the ring on a periodic axis
+    int wr[3];   // updated cells of the ring's last (ragged) tile
 };
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes)
@@ -155,6 +158,31 @@ __device__ __forceinline__ int band_has(const int* bi, int a, int b, int c)
     return a >= bi[0] && a <= bi[1] && b >= bi[2] && b <= bi[3] && c >= bi[4] && c <= bi[5];
 }
 
+// Tile coordinate v + (-1, 0 or +1) on an axis: wrapped onto the ring of a
+// periodic axis.
+template <bool PER>
+__device__ __forceinline__ int wrap_tile(const SysArgs& A, int d, int v)
+{
+    if (!PER || !A.per[d]) return v;
+    return v >= A.L[d] ? v - A.L[d] : (v < 0 ? v + A.L[d] : v);
+}
+
+// Grid position (o + tau) + k on an axis, k in [-1, 16]: U = o + tau (tile
+// frame, unbounded), Uw = U mod n (kept only on periodic axes, n >= 16).
+// Returns false for ghost positions outside a PEC axis.
+template <bool PER>
+__device__ __forceinline__ bool axis_pos(int U, int Uw, int n, bool per, int k, int& p)
+{
+    if (PER && per) {
+        int q = Uw + k;
+        q = q >= n ? q - n : q;
+        p = q < 0 ? q + n : q;
+        return true;
+    }
+    p = U + k;
+    return (unsigned)p < (unsigned)n;
+}
+
 __device__ __forceinline__ int prog_index(const SysArgs& A, int a, int b, int c)
 {
     return ((a - A.amin) * A.NB + (b - A.bmin)) * A.NC + (c - A.cmin);
@@ -171,6 +199,14 @@ __device__ __forceinline__ void publish(const SysArgs& A, int me, unsigned v)
         if (!DEV) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(A.progress + me, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// Complete this workgroup's outstanding loads into LDS and make them visible
+// to every wavefront.
+__device__ __forceinline__ void complete_loads()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
 }
 
 // Wait until every listed tile's counter is >= target (acquire).  Lanes
@@ -215,7 +251,7 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     return *s_abort == 0;
 }
 
-template <int NW, bool DEV>
+template <int NW, bool DEV, bool PER>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void systolic_kernel(SysArgs A)
 {
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
@@ -265,6 +301,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const __amdgpu_buffer_rsrc_t rring = make_rsrc(A.ring, A.ring_bytes);
     const unsigned plane = (unsigned)A.ny * (unsigned)A.nz;
     const float cH = A.cH;
+    const bool perx = PER && A.per[0], pery = PER && A.per[1], perz = PER && A.per[2];
     constexpr unsigned ring_step = 9u * PY * PX;  // floats per (slot, local step)
     constexpr unsigned ring_comp = PY * PX;       // floats per component
 
@@ -294,7 +331,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         int nup = 0;
 #pragma unroll
         for (int d = 1; d < 8; ++d) {
-            const int ua = a + (d & 1), ub = b + ((d >> 1) & 1), uc = c + ((d >> 2) & 1);
+            const int ua = wrap_tile<PER>(A, 0, a + (d & 1)), ub = wrap_tile<PER>(A, 1, b + ((d >> 1) & 1)),
+                      uc = wrap_tile<PER>(A, 2, c + ((d >> 2) & 1));
             if (band_has(bi, ua, ub, uc)) {
                 const int pi = prog_index(A, ua, ub, uc);
 #pragma unroll
@@ -314,7 +352,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             int nw = 0;
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
-                const int ua = a + (d & 1), ub = b + ((d >> 1) & 1), uc = c + ((d >> 2) & 1);
+                const int ua = wrap_tile<PER>(A, 0, a + (d & 1)), ub = wrap_tile<PER>(A, 1, b + ((d >> 1) & 1)),
+                          uc = wrap_tile<PER>(A, 2, c + ((d >> 2) & 1));
                 if (band_has(bp, ua, ub, uc)) {
                     const int pi = prog_index(A, ua, ub, uc);
 #pragma unroll
@@ -338,8 +377,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             int wl[8];
             wl[0] = prog_index(A, pk.y, pk.z, pk.w);
             int nw = 1;
-            if (band_has(pb, pk.y, pk.z, pk.w - 1)) {
-                wl[1] = prog_index(A, pk.y, pk.z, pk.w - 1);
+            const int pcm = wrap_tile<PER>(A, 2, pk.w - 1);
+            if (band_has(pb, pk.y, pk.z, pcm)) {
+                wl[1] = prog_index(A, pk.y, pk.z, pcm);
                 nw = 2;
             } else {
                 wl[1] = wl[0];
@@ -348,11 +388,23 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             for (int k = 2; k < 8; ++k) wl[k] = wl[0];
             if (!wait_tiles<DEV>(A, wl, nw, pend, &s_abort, nullptr)) break;
         }
-        const int has_consumer = band_has(bi, a, b, c - 1);
-        const int has_zup = band_has(bi, a, b, c + 1);
+        const int has_consumer = band_has(bi, a, b, wrap_tile<PER>(A, 2, c - 1));
+        const int czup = wrap_tile<PER>(A, 2, c + 1);
+        const int has_zup = band_has(bi, a, b, czup);
         const int slot_zup = has_zup ? A.tix[bi[6] + ((a - bi[0]) * (bi[3] - bi[2] + 1) + (b - bi[2])) *
-                                                      (bi[5] - bi[4] + 1) + (c + 1 - bi[4])] % A.R
+                                                      (bi[5] - bi[4] + 1) + (czup - bi[4])] % A.R
                                      : 0;
+        // updated cells per axis (the last tile of a periodic ring is ragged),
+        // the lanes that take the forward y and z faces, and the tile frame
+        // origin modulo n on periodic axes
+        const int wxr = (perx && a == A.L[0] - 1) ? A.wr[0] : WX;
+        const int wyr = (pery && b == A.L[1] - 1) ? A.wr[1] : WY;
+        const int wzr = (perz && c == A.L[2] - 1) ? A.wr[2] : WZ;
+        const int fy = (wyr + 1) & (PY - 1), fz = (wzr + 1) & (PZ - 1);
+        int Xw = 0, Yw = 0, Zw = 0;
+        if (perx) Xw = (ox + t0 + 1) % A.nx;
+        if (pery) Yw = (oy + t0 + 1) % A.ny;
+        if (perz) Zw = (oz + t0 + 1) % A.nz;
 
         // ---- the band's samples of the LDS-cached sources (step tau reads
         //      sample step0 + tau - 1 - first; the range test is repeated at use)
@@ -369,14 +421,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         if (tid == 0) s_up = nup ? 0u : 0xFFFFFFFFu;
         {
             const int by = oy + t0, bz = oz + t0;
-            const int y = by + ((ys - by) & (PY - 1));
-            const int z = bz + ((zs - bz) & (PZ - 1));
-            const bool okyz = (unsigned)y < (unsigned)A.ny && (unsigned)z < (unsigned)A.nz;
+            int y, z;
+            const bool oky = axis_pos<PER>(by + 1, Yw, A.ny, pery, ((ys - by) & (PY - 1)) - 1, y);
+            const bool okz = axis_pos<PER>(bz + 1, Zw, A.nz, perz, ((zs - bz) & (PZ - 1)) - 1, z);
+            const bool okyz = oky && okz;
             const unsigned yz = (unsigned)y * (unsigned)A.nz + (unsigned)z;
 #pragma unroll
             for (int j = 0; j < PX; ++j) {
-                const int x = ox + t0 + j;
-                const unsigned off = (okyz && (unsigned)x < (unsigned)A.nx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
+                int x;
+                const bool okx = axis_pos<PER>(ox + t0 + 1, Xw, A.nx, perx, j - 1, x);
+                const unsigned off = (okyz && okx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     E[q][j] = bld<SP>(rf[q], off);
@@ -393,27 +447,35 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const int by = oy + tau - 1, bz = oz + tau - 1;
             const int dy = (ys - by) & (PY - 1);  // 0: layer below the tile; 1..WY: inside
             const int dz = (zs - bz) & (PZ - 1);
-            const int y = by + dy, z = bz + dz;
-            const bool inB = dy >= 1 && dz >= 1;
-            const bool okyz = (unsigned)y < (unsigned)A.ny && (unsigned)z < (unsigned)A.nz;
+            const int Ux = ox + tau, Uy = oy + tau, Uz = oz + tau;  // frame origin of B_tau
+            int y, z;
+            const bool oky = axis_pos<PER>(Uy, Yw, A.ny, pery, dy - 1, y);
+            const bool okz0 = axis_pos<PER>(Uz, Zw, A.nz, perz, dz - 1, z);
+            const bool inB = dy >= 1 && dz >= 1 && dy <= wyr && dz <= wzr;
+            const bool okyz = oky && okz0;
             const unsigned yz = (unsigned)y * (unsigned)A.nz + (unsigned)z;
-            auto off_at = [&](int x) -> unsigned {
-                return (okyz && (unsigned)x < (unsigned)A.nx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
+            // offset of this lane's cell at x = Ux + k
+            auto off_at = [&](int k) -> unsigned {
+                int x;
+                const bool okx = axis_pos<PER>(Ux, Xw, A.nx, perx, k, x);
+                return (okyz && okx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
             };
             // coordinates of this lane in the next box (after the one-cell move)
             const int dy1 = (dy - 1) & (PY - 1), dz1 = (dz - 1) & (PZ - 1);
-            const int y1 = by + 1 + dy1, z1 = bz + 1 + dz1;
-            const bool okyz1 = (unsigned)y1 < (unsigned)A.ny && (unsigned)z1 < (unsigned)A.nz;
+            int y1, z1;
+            const bool oky1 = axis_pos<PER>(Uy, Yw, A.ny, pery, dy1, y1);
+            const bool okz1 = axis_pos<PER>(Uz, Zw, A.nz, perz, dz1, z1);
+            const bool okyz1 = oky1 && okz1;
             const unsigned yz1 = (unsigned)y1 * (unsigned)A.nz + (unsigned)z1;
             const unsigned ring_base = ((unsigned)slot * (unsigned)A.K + (unsigned)ls) * ring_step;
             const unsigned ring_zup = ((unsigned)slot_zup * (unsigned)A.K + (unsigned)ls) * ring_step;
             // the forward y and z planes of the next box
-            const int yf = oy + tau + WY, zf = oz + tau + WZ;
+            int yf, zf, zl;
+            const bool oky_f = axis_pos<PER>(Uy, Yw, A.ny, pery, wyr, yf);
+            const bool okz_f = axis_pos<PER>(Uz, Zw, A.nz, perz, wzr, zf);
             // z of DPP lane zs in the next box, for the y-face loads
-            const int zl = oz + tau + ((zs - oz - tau) & (PZ - 1));
-            const bool okz_l = (unsigned)zl < (unsigned)A.nz;
-            const bool oky_f = (unsigned)yf < (unsigned)A.ny;
-            const bool okz_f = (unsigned)zf < (unsigned)A.nz;
+            const bool okz_l = axis_pos<PER>(Uz, Zw, A.nz, perz, (zs - oz - tau) & (PZ - 1), zl);
+            (void)zf;
 
             // Issue the loads of the next box's forward shell for components
             // [Q0, Q0 + NQ) (0..2 = E, 3..5 = H, 6..8 = cE): the x face into
@@ -422,19 +484,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             auto prefetch = [&](auto q0c, auto nqc) {
                 constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
                 // x face: rows of the wavefront are y slots, lanes are z slots
-                const unsigned oxf = (okyz1 && (unsigned)(ox + tau + WX) < (unsigned)A.nx)
-                                         ? ((unsigned)(ox + tau + WX) * plane + yz1) * 4u : kOOB;
+                int xf;
+                const bool okxf = axis_pos<PER>(Ux, Xw, A.nx, perx, wxr, xf);
+                const unsigned oxf = (okyz1 && okxf) ? ((unsigned)xf * plane + yz1) * 4u : kOOB;
                 // y face: rows of the wavefront are x, lanes are z
                 const int j = 4 * w + r;
-                const int x = ox + tau + j;
-                const unsigned oyf = (oky_f && okz_l && (unsigned)x < (unsigned)A.nx)
+                int x;
+                const bool okx = axis_pos<PER>(Ux, Xw, A.nx, perx, j, x);
+                const unsigned oyf = (oky_f && okz_l && okx)
                                          ? (((unsigned)x * (unsigned)A.ny + (unsigned)yf) * (unsigned)A.nz + (unsigned)zl) * 4u
                                          : kOOB;
                 // z face: rows are y, lanes are x, from the +z neighbour's ring slot
                 const int yy = 4 * w + r;
+                int xr, yr;
                 const bool okz = has_zup && okz_f && zs < WX && yy < WY &&
-                                 (unsigned)(ox + tau + zs) < (unsigned)A.nx &&
-                                 (unsigned)(oy + tau + yy) < (unsigned)A.ny;
+                                 axis_pos<PER>(Ux, Xw, A.nx, perx, zs, xr) &&
+                                 axis_pos<PER>(Uy, Yw, A.ny, pery, yy, yr);
                 const unsigned ozf = (ring_zup + (unsigned)yy * PX + (unsigned)zs) * 4u;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) {
@@ -461,10 +526,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const int j = 4 * w + r;
                 // y face at y = oy + tau: cells inside the tile only
                 const int dzl = (zs - oz - tau + 1) & (PZ - 1);
-                const int zz = oz + tau - 1 + dzl;
-                const bool in = j < WX && dzl >= 1 && (unsigned)(ox + tau + j) < (unsigned)A.nx &&
-                                (unsigned)(oy + tau) < (unsigned)A.ny && (unsigned)zz < (unsigned)A.nz;
-                const unsigned o = in ? ((((unsigned)(ox + tau + j)) * (unsigned)A.ny + (unsigned)(oy + tau)) *
+                int xs_, ys_, zz;
+                const bool in = j < wxr && dzl >= 1 && dzl <= wzr &&
+                                axis_pos<PER>(Ux, Xw, A.nx, perx, j, xs_) &&
+                                axis_pos<PER>(Uy, Yw, A.ny, pery, 0, ys_) &&
+                                axis_pos<PER>(Uz, Zw, A.nz, perz, dzl - 1, zz);
+                const unsigned o = in ? ((((unsigned)xs_) * (unsigned)A.ny + (unsigned)ys_) *
                                          (unsigned)A.nz + (unsigned)zz) * 4u : kOOB;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rf[q], o, ytr[q][j][zs]);
@@ -518,9 +585,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #define FDTD_APPLY_SOURCE(comp, si, sj, sk, first, len, sample)                                        \
     {                                                                                               \
         const long long m = A.step0 + tau - 1 - (first);                                            \
-        const int px = (si) - (ox + tau), py = (sj) - (oy + tau), pz = (sk) - (oz + tau);           \
-        if (m >= 0 && m < (len) && (unsigned)px < (unsigned)WX && (unsigned)py < (unsigned)WY &&    \
-            (unsigned)pz < (unsigned)WZ) {                                                          \
+        int px = (si) - (perx ? Xw : Ux), py = (sj) - (pery ? Yw : Uy), pz = (sk) - (perz ? Zw : Uz); \
+        px += (perx && px < 0) ? A.nx : 0;                                                          \
+        py += (pery && py < 0) ? A.ny : 0;                                                          \
+        pz += (perz && pz < 0) ? A.nz : 0;                                                          \
+        if (m >= 0 && m < (len) && (unsigned)px < (unsigned)wxr && (unsigned)py < (unsigned)wyr &&  \
+            (unsigned)pz < (unsigned)wzr) {                                                         \
             const float wv = (sample);                                                              \
             const int lx = (dy == py + 1 && dz == pz + 1) ? px : -1;                                \
             if ((comp) == 0) {                                                                      \
@@ -545,7 +615,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 
             // publish E of the first layer of the tile
             if (inB) {
-                const unsigned o = off_at(ox + tau);
+                const unsigned o = off_at(0);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) bst<SP>(rf[q], o, E[q][0]);
             }
@@ -562,28 +632,42 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     for (int j = 0; j < WX; ++j) ztr[q][dy1][j] = E[q][j];
             }
             store_faces(std::integral_constant<int, 0>(), std::integral_constant<int, 3>(), std::integral_constant<int, 3>());
+            // publish (which also completes an early prefetch); a late prefetch
+            // waits for the upwind neighbours only after this tile's own flag
+            // is out, since on a periodic ring they wait on it in turn
+            publish<DEV>(A, me, 2u * (unsigned)tau - 1u);
             if (!earlyE) {
                 if (!ensure_up(2u * (unsigned)tau - 1u)) {
                     aborted = true;
                     break;
                 }
                 prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
+                complete_loads();
             }
-            publish<DEV>(A, me, 2u * (unsigned)tau - 1u);  // also completes the prefetch
 
             // forward shell's E^tau into the registers
-#pragma unroll
-            for (int q = 0; q < 3; ++q) E[q][WX] = xst[q][ys][zs];
-            if (dy == 0) {
+            if (dy == fy) {
 #pragma unroll
                 for (int j = 0; j < WX; ++j)
 #pragma unroll
                     for (int q = 0; q < 3; ++q) E[q][j] = yst[q][j][zs];
-            } else if (dz == 0) {
+            } else if (dz == fz) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
                     for (int j = 0; j < WX; ++j) E[q][j] = zst[q][dy1][j];
+            }
+            if (!PER || wxr == WX) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) E[q][WX] = xst[q][ys][zs];
+            } else {
+                // ragged tile of a periodic ring: the x face enters at slot wxr
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const float v = xst[q][ys][zs];
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) E[q][j] = j == wxr ? v : E[q][j];
+                }
             }
 
             // ================= H half-step (E frame: register j <-> x = ox+tau+j)
@@ -615,7 +699,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 
             // publish H (and, on the z face, the coefficients) of the first layer
             if (inB) {
-                const unsigned o = off_at(ox + tau);
+                const unsigned o = off_at(0);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) bst<SP>(rf[3 + q], o, H[q][0]);
             }
@@ -639,7 +723,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 // band end: the whole subdomain goes back to the field arrays
 #pragma unroll
                 for (int j = 0; j < WX; ++j) {
-                    const unsigned o = off_at(ox + tau + j);
+                    const unsigned o = j < wxr ? off_at(j) : kOOB;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         bst<SP>(rf[q], o, E[q][j]);
@@ -647,23 +731,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     }
                 }
             }
-            if (tau < t1 && !earlyH) {
+            publish<DEV>(A, me, 2u * (unsigned)tau);
+            if (tau == t1) break;
+            if (!earlyH) {
                 if (!ensure_up(2u * (unsigned)tau)) {
                     aborted = true;
                     break;
                 }
                 prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
+                complete_loads();
             }
-            publish<DEV>(A, me, 2u * (unsigned)tau);  // also completes the prefetch
-            if (tau == t1) break;
 
             // forward shell's H^(tau+1/2) and coefficients into the registers
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                H[q][WX] = xst[3 + q][ys][zs];
-                C[q][WX] = xst[6 + q][ys][zs];
-            }
-            if (dy == 0) {
+            if (dy == fy) {
 #pragma unroll
                 for (int j = 0; j < WX; ++j)
 #pragma unroll
@@ -671,7 +751,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         H[q][j] = yst[3 + q][j][zs];
                         C[q][j] = yst[6 + q][j][zs];
                     }
-            } else if (dz == 0) {
+            } else if (dz == fz) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
@@ -679,6 +759,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         H[q][j] = zst[3 + q][dy1][j];
                         C[q][j] = zst[6 + q][dy1][j];
                     }
+            }
+            if (!PER || wxr == WX) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    H[q][WX] = xst[3 + q][ys][zs];
+                    C[q][WX] = xst[6 + q][ys][zs];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const float vh = xst[3 + q][ys][zs], vc = xst[6 + q][ys][zs];
+#pragma unroll
+                    for (int j = 0; j < WX; ++j) {
+                        H[q][j] = j == wxr ? vh : H[q][j];
+                        C[q][j] = j == wxr ? vc : C[q][j];
+                    }
+                }
+            }
+            if (PER) {
+                Xw = (perx && Xw == A.nx - 1) ? 0 : Xw + 1;
+                Yw = (pery && Yw == A.ny - 1) ? 0 : Yw + 1;
+                Zw = (perz && Zw == A.nz - 1) ? 0 : Zw + 1;
             }
         }
         if (aborted) break;
@@ -708,7 +810,10 @@ struct SystolicState {
     float* d_ring = nullptr;
     unsigned* d_counter = nullptr;
     size_t ring_bytes = 0;
-    int capacity = 0;
+    int per[3] = {0, 0, 0};  // periodic axes of the plan
+    int L[3] = {0, 0, 0};    // ring tiles on periodic axes
+    int group = 1;           // tiles of one ring group (must be co-resident)
+    int sm_count = 0;
 };
 
 namespace {
@@ -737,6 +842,14 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     constexpr int WY = 4 * kNW - 1;
     const int W[3] = {WX, WY, WZ};
     const int N[3] = {ctx->nx, ctx->ny, ctx->nz};
+    int per[3], L[3], group = 1;
+    for (int d = 0; d < 3; ++d) {
+        per[d] = ctx->cfg.bc[d] == FDTD_BC_PERIODIC;
+        L[d] = per[d] ? (N[d] + W[d] - 1) / W[d] : 0;
+        if (per[d]) group *= L[d];
+    }
+    // wrap a tile coordinate onto the ring of a periodic axis
+    auto wrap = [&](int d, int v) { return per[d] ? ((v % L[d]) + L[d]) % L[d] : v; };
     const int nb = (nsteps + K - 1) / K;
     std::vector<int> band(8 * (size_t)nb);
     int lo_all[3] = {1 << 30, 1 << 30, 1 << 30}, hi_all[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
@@ -746,8 +859,9 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
         size_t cnt = 1;
         for (int d = 0; d < 3; ++d) {
             // tiles whose subdomain meets the grid at some step of the band
-            const int lo = -floordiv(W[d] - 1 + t1, W[d]);
-            const int hi = floordiv(N[d] - 2 - t0, W[d]);
+            // (a periodic axis always holds its whole ring)
+            const int lo = per[d] ? 0 : -floordiv(W[d] - 1 + t1, W[d]);
+            const int hi = per[d] ? L[d] - 1 : floordiv(N[d] - 2 - t0, W[d]);
             band[8 * bb + 2 * d] = lo;
             band[8 * bb + 2 * d + 1] = hi;
             lo_all[d] = std::min(lo_all[d], lo);
@@ -763,32 +877,49 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     size_t pos = 0;
     for (int bb = 0; bb < nb; ++bb) {
         const int* bi = &band[8 * bb];
-        const int na = bi[1] - bi[0] + 1, nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
-        const int maxd = na + nbb + nc - 3;
-        // counting sort by depth below the most upwind corner (upwind first)
+        const int n3[3] = {bi[1] - bi[0] + 1, bi[3] - bi[2] + 1, bi[5] - bi[4] + 1};
+        // depth below the most upwind corner, along the PEC axes only
+        int maxd = 0;
+        for (int d = 0; d < 3; ++d)
+            if (!per[d]) maxd += n3[d] - 1;
+        // loop order: PEC axes outside, periodic axes inside, so that the
+        // tiles of one ring group are enumerated (and so stored) together
+        int ax[3], k = 0;
+        for (int d = 0; d < 3; ++d)
+            if (!per[d]) ax[k++] = d;
+        for (int d = 0; d < 3; ++d)
+            if (per[d]) ax[k++] = d;
+        auto depth = [&](const int* i3) {
+            int dd = 0;
+            for (int d = 0; d < 3; ++d)
+                if (!per[d]) dd += n3[d] - 1 - i3[d];
+            return dd;
+        };
+        // counting sort by depth (upwind first), stable in the loop order
         std::vector<int> count(maxd + 2, 0);
-        for (int ia = 0; ia < na; ++ia)
-            for (int ib = 0; ib < nbb; ++ib)
-                for (int ic = 0; ic < nc; ++ic) count[(na - 1 - ia) + (nbb - 1 - ib) + (nc - 1 - ic) + 1]++;
+        int i3[3];
+        for (i3[ax[0]] = 0; i3[ax[0]] < n3[ax[0]]; ++i3[ax[0]])
+            for (i3[ax[1]] = 0; i3[ax[1]] < n3[ax[1]]; ++i3[ax[1]])
+                for (i3[ax[2]] = 0; i3[ax[2]] < n3[ax[2]]; ++i3[ax[2]]) count[depth(i3) + 1]++;
         for (int d = 1; d <= maxd + 1; ++d) count[d] += count[d - 1];
-        for (int ia = 0; ia < na; ++ia)
-            for (int ib = 0; ib < nbb; ++ib)
-                for (int ic = 0; ic < nc; ++ic) {
-                    const int d = (na - 1 - ia) + (nbb - 1 - ib) + (nc - 1 - ic);
-                    const size_t tix_i = pos + (size_t)count[d]++;
-                    tickets[tix_i] = make_int4(bb, bi[0] + ia, bi[2] + ib, bi[4] + ic);
-                    tix[(size_t)bi[6] + ((size_t)ia * nbb + ib) * nc + ic] = (int)tix_i;
+        for (i3[ax[0]] = 0; i3[ax[0]] < n3[ax[0]]; ++i3[ax[0]])
+            for (i3[ax[1]] = 0; i3[ax[1]] < n3[ax[1]]; ++i3[ax[1]])
+                for (i3[ax[2]] = 0; i3[ax[2]] < n3[ax[2]]; ++i3[ax[2]]) {
+                    const size_t tix_i = pos + (size_t)count[depth(i3)]++;
+                    tickets[tix_i] = make_int4(bb, bi[0] + i3[0], bi[2] + i3[1], bi[4] + i3[2]);
+                    tix[(size_t)bi[6] + ((size_t)i3[0] * n3[1] + i3[1]) * n3[2] + i3[2]] = (int)tix_i;
                 }
-        pos += (size_t)na * nbb * nc;
+        pos += (size_t)n3[0] * n3[1] * n3[2];
     }
     // largest distance (in tickets) from a face producer to its -z consumer
     int R = 1;
     for (size_t t = 0; t < ntot; ++t) {
         const int4 tk = tickets[t];
         const int* bi = &band[8 * tk.x];
-        if (tk.w - 1 < bi[4]) continue;
+        const int cm = wrap(2, tk.w - 1);
+        if (cm < bi[4]) continue;
         const int nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
-        const int j = tix[(size_t)bi[6] + ((size_t)(tk.y - bi[0]) * nbb + (tk.z - bi[2])) * nc + (tk.w - 1 - bi[4])];
+        const int j = tix[(size_t)bi[6] + ((size_t)(tk.y - bi[0]) * nbb + (tk.z - bi[2])) * nc + (cm - bi[4])];
         R = std::max(R, (int)(j - (int)t + 1));
     }
     free_plan(s);
@@ -803,6 +934,11 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     s->NA = hi_all[0] - lo_all[0] + 1;
     s->NB = hi_all[1] - lo_all[1] + 1;
     s->NC = hi_all[2] - lo_all[2] + 1;
+    for (int d = 0; d < 3; ++d) {
+        s->per[d] = per[d];
+        s->L[d] = L[d];
+    }
+    s->group = group;
     hipError_t e;
     size_t nprog = (size_t)s->NA * s->NB * s->NC;
     if ((e = hipMalloc(&s->d_tickets, ntot * sizeof(int4))) != hipSuccess ||
@@ -832,9 +968,10 @@ int default_band(const fdtd_ctx* ctx, int64_t nsteps)
 
 int systolic_supported(const fdtd_ctx* ctx, std::string* why)
 {
+    const int n[3] = {ctx->nx, ctx->ny, ctx->nz};
     for (int a = 0; a < 3; ++a)
-        if (ctx->cfg.bc[a] != FDTD_BC_PEC) {
-            *why = "periodic axes are not supported by the systolic scheme in this build";
+        if (ctx->cfg.bc[a] == FDTD_BC_PERIODIC && n[a] < 16) {
+            *why = "the systolic scheme needs at least 16 cells on a periodic axis";
             return 0;
         }
     if ((uint64_t)ctx->ncell * 4u > 0xFFFFFF00ull) {
@@ -861,22 +998,33 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
     // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
     const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
     const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
-    auto kern = dev ? systolic_kernel<kNW, true> : systolic_kernel<kNW, false>;
-    if (s->capacity == 0) {
-        int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kNW, 0);
-        if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+    const bool anyper = s->per[0] || s->per[1] || s->per[2];
+    auto kern = dev ? (anyper ? systolic_kernel<kNW, true, true> : systolic_kernel<kNW, true, false>)
+                    : (anyper ? systolic_kernel<kNW, false, true> : systolic_kernel<kNW, false, false>);
+    if (s->sm_count == 0) {
         hipDeviceProp_t prop;
-        e = hipGetDeviceProperties(&prop, ctx->device);
+        hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDeviceProperties");
-        s->capacity = std::max(1, per_cu) * prop.multiProcessorCount;
+        s->sm_count = prop.multiProcessorCount;
     }
-    int grid = ctx->workgroups > 0 ? ctx->workgroups : s->capacity;
+    int per_cu = 0;
+    hipError_t eo = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kNW, 0);
+    if (eo != hipSuccess) return hip_fail(ctx, eo, "occupancy query");
+    // every workgroup of the persistent grid must be resident at once
+    const int capacity = std::max(1, per_cu) * s->sm_count;
+    int grid = ctx->workgroups > 0 ? std::min(ctx->workgroups, capacity) : capacity;
     grid = std::max(1, std::min(grid, s->nt));
+    // The tiles of a periodic ring wait on each other in a cycle that only
+    // time breaks, so a whole ring group must be resident together.
+    if (anyper && grid < s->group)
+        return fail(ctx, FDTD_EUNSUPPORTED,
+                    "systolic: a periodic ring group of " + std::to_string(s->group) +
+                        " tiles needs as many resident workgroups (grid " + std::to_string(grid) + ")");
     // Face ring: a slot is reused R tickets later, after its previous
     // occupant and that occupant's consumer have finished.  R = D + 2 * grid
     // keeps those two long finished by the time the slot comes round again,
-    // so the reuse wait never holds a workgroup in steady state.
+    // so the reuse wait never holds a workgroup in steady state; as grid is
+    // at least one ring group, both lie in groups before the reuser's own.
     const int R = std::max(1, std::min(s->D + 2 * grid, s->nt));
     const size_t ring_bytes = (size_t)R * s->K * 9 * (4 * kNW) * 16 * sizeof(float);
     if (ring_bytes >= ((size_t)1 << 32)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: face ring too large");
@@ -930,6 +1078,13 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
     A.counter = s->d_counter;
     A.error = ctx->dev_error;
     A.spin_limit = ctx->spin_limit;
+    for (int d = 0; d < 3; ++d) {
+        const int n = d == 0 ? ctx->nx : (d == 1 ? ctx->ny : ctx->nz);
+        const int W = d == 1 ? 4 * kNW - 1 : WX;
+        A.per[d] = s->per[d];
+        A.L[d] = s->L[d];
+        A.wr[d] = s->per[d] ? n - W * (s->L[d] - 1) : W;
+    }
     PendingTiming t;
     timing_begin(ctx, FDTD_KERNEL_SYSTOLIC, &t);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kNW), 0, ctx->stream, A);

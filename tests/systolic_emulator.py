@@ -12,9 +12,13 @@ kernel's atomic ticket counter).  A missing or misplaced wait shows up as a
 read of stale data, so the result stops matching the FP32 oracle.
 
 Skewed frame: during the tau-th step of a call (tau = 1..nsteps) the tile with
-index (a, b, c) updates B_tau = [a*Wx + tau, a*Wx + tau + Wx - 1] x ... and
-keeps the slot box R = B_tau plus one layer below on every axis.  All axes
-must be PEC: cells outside the domain are ghosts that read as zero.
+index (a, b, c) updates B_tau = [a*Wx + tau, a*Wx + tau + wx - 1] x ... and
+keeps the slot box R = B_tau plus one layer below on every axis.  On a PEC
+axis cells outside the domain are ghosts that read as zero and the tile range
+of each band covers the domain; on a periodic axis positions wrap modulo n,
+the L = ceil(n / W) tiles form a ring whose last tile is ragged (width
+n - W (L - 1)), and the tiles of a ring depend on each other in a cycle that
+only time breaks: they must be resident together and advance in lock-step.
 """
 from __future__ import annotations
 
@@ -23,20 +27,31 @@ import numpy as np
 F32 = np.float32
 
 
-def plan(shape, W, K, nsteps):
+def ring_tiles(shape, W, bc):
+    """Tiles per periodic axis (None on PEC axes)."""
+    return [-(-n // w) if p else None for n, w, p in zip(shape, W, bc)]
+
+
+def plan(shape, W, K, nsteps, bc=(0, 0, 0)):
     """Tickets in dequeue order and per-band tile ranges.
 
     Returns (tickets, ranges, ticket_of) with tickets = [(band, a, b, c)],
     ranges[band] = ((alo, ahi), (blo, bhi), (clo, chi)), and ticket_of a dict
     (band, a, b, c) -> ticket index.  Within a band, tiles are ordered by
-    depth below the most upwind corner (upwind first): every tile appears
-    after its seven upwind neighbours."""
+    depth below the most upwind corner along the PEC axes (upwind first), and
+    the tiles that differ only along periodic axes (one ring group) are
+    consecutive: every tile appears after its upwind neighbours outside its
+    group."""
     tickets, ranges = [], []
+    L = ring_tiles(shape, W, bc)
     nb = (nsteps + K - 1) // K
     for band in range(nb):
         t0, t1 = band * K, min(nsteps, (band + 1) * K)
         rg = []
-        for n, w in zip(shape, W):
+        for n, w, l in zip(shape, W, L):
+            if l is not None:
+                rg.append((0, l - 1))
+                continue
             lo = -((w - 1 + t1) // w)          # ceil((1 - w - t1) / w)
             hi = (n - 2 - t0) // w
             rg.append((lo, hi))
@@ -44,18 +59,28 @@ def plan(shape, W, K, nsteps):
         tiles = [(a, b, c) for a in range(rg[0][0], rg[0][1] + 1)
                  for b in range(rg[1][0], rg[1][1] + 1)
                  for c in range(rg[2][0], rg[2][1] + 1)]
-        tiles.sort(key=lambda p: ((rg[0][1] - p[0]) + (rg[1][1] - p[1]) + (rg[2][1] - p[2]), p))
+
+        def key(p):
+            pec = tuple(p[d] for d in range(3) if L[d] is None)
+            depth = sum(rg[d][1] - p[d] for d in range(3) if L[d] is None)
+            return (depth, pec, p)
+        tiles.sort(key=key)
         tickets += [(band,) + p for p in tiles]
     ticket_of = {t: i for i, t in enumerate(tickets)}
     return tickets, ranges, ticket_of
 
 
-def ring_depth(tickets, ticket_of):
+def wrap_tile(t, L):
+    """Tile coordinates with the periodic axes wrapped onto their rings."""
+    return tuple(x % l if l is not None else x for x, l in zip(t, L))
+
+
+def ring_depth(tickets, ticket_of, L=(None, None, None)):
     """Smallest ring size R such that the consumer of ticket t (its -z
     neighbour in the same band) has index < t + R."""
     R = 1
     for i, (band, a, b, c) in enumerate(tickets):
-        j = ticket_of.get((band, a, b, c - 1))
+        j = ticket_of.get((band,) + wrap_tile((a, b, c - 1), L))
         if j is not None:
             R = max(R, j - i + 1)
     return R
@@ -63,7 +88,7 @@ def ring_depth(tickets, ticket_of):
 
 class Machine:
     def __init__(self, fields, cE, cH, shape, W, K, nsteps, sources=(), step0=0,
-                 ring_slack=0):
+                 ring_slack=0, bc=(0, 0, 0)):
         self.f = [np.array(x, dtype=F32) for x in fields]
         self.cE = [np.asarray(x, dtype=F32) for x in cE]
         self.cH = F32(cH)
@@ -73,8 +98,17 @@ class Machine:
         self.nsteps = nsteps
         self.sources = list(sources)
         self.step0 = step0
-        self.tickets, self.ranges, self.ticket_of = plan(shape, W, K, nsteps)
-        self.R = ring_depth(self.tickets, self.ticket_of) + ring_slack
+        self.per = tuple(bool(p) for p in bc)
+        for n, w, p in zip(shape, W, self.per):
+            if p and n <= w:
+                raise ValueError("a periodic axis needs at least two tiles")
+        self.L = ring_tiles(shape, W, self.per)
+        self.tickets, self.ranges, self.ticket_of = plan(shape, W, K, nsteps, self.per)
+        # a slot is reused R tickets later, after its previous occupant and that
+        # occupant's consumer have finished their band; with R beyond the ring
+        # depth plus one ring group, both lie in groups before the reuser's own
+        self.group = int(np.prod([l for l in self.L if l is not None]))
+        self.R = ring_depth(self.tickets, self.ticket_of, self.L) + self.group - 1 + ring_slack
         Wx, Wy, Wz = W
         # ring: [slot][local step][9 values][Wx][Wy]; values: Ex Ey Ez Hx Hy Hz cEx cEy cEz
         self.ring = np.full((self.R, K, 9, Wx, Wy), np.nan, dtype=F32)
@@ -82,17 +116,31 @@ class Machine:
         self.reads_before_ready = 0
 
     # ---- geometry ---------------------------------------------------------
-    def exists(self, band, a, b, c):
+    def tile(self, band, a, b, c):
+        """The tile (a, b, c) wrapped onto the periodic rings, or None if the
+        band has no such tile."""
+        t = wrap_tile((a, b, c), self.L)
         rg = self.ranges[band]
-        return rg[0][0] <= a <= rg[0][1] and rg[1][0] <= b <= rg[1][1] and rg[2][0] <= c <= rg[2][1]
+        if all(rg[d][0] <= t[d] <= rg[d][1] for d in range(3)):
+            return t
+        return None
+
+    def exists(self, band, a, b, c):
+        return self.tile(band, a, b, c) is not None
+
+    def widths(self, tile):
+        """Updated cells per axis of a tile (the last tile of a ring is ragged)."""
+        return tuple(n - w * (l - 1) if l is not None and x == l - 1 else w
+                     for x, n, w, l in zip(tile, self.shape, self.W, self.L))
 
     def _box_index(self, lo, size):
         """Index arrays for a box with lower corner lo and given size, plus an
-        in-domain mask."""
+        in-domain mask (periodic axes wrap and are always in the domain)."""
         ax = [np.arange(l, l + s) for l, s in zip(lo, size)]
-        inb = [(x >= 0) & (x < n) for x, n in zip(ax, self.shape)]
+        inb = [np.ones(len(x), bool) if p else (x >= 0) & (x < n)
+               for x, n, p in zip(ax, self.shape, self.per)]
         mask = inb[0][:, None, None] & inb[1][None, :, None] & inb[2][None, None, :]
-        cl = [np.clip(x, 0, n - 1) for x, n in zip(ax, self.shape)]
+        cl = [x % n if p else np.clip(x, 0, n - 1) for x, n, p in zip(ax, self.shape, self.per)]
         return np.ix_(*cl), mask
 
     def load_box(self, arr, lo, size):
@@ -102,13 +150,18 @@ class Machine:
     def store_box(self, arr, lo, vals):
         """Store the in-domain part of a box; ghost cells are dropped."""
         dst, src = [], []
-        for l, s, n in zip(lo, vals.shape, self.shape):
+        for l, s, n, p in zip(lo, vals.shape, self.shape, self.per):
+            if p:
+                assert s <= n
+                dst.append(np.arange(l, l + s) % n)
+                src.append(np.arange(s))
+                continue
             a, b = max(l, 0), min(l + s, n)
             if a >= b:
                 return
-            dst.append(slice(a, b))
-            src.append(slice(a - l, b - l))
-        arr[tuple(dst)] = vals[tuple(src)]
+            dst.append(np.arange(a, b))
+            src.append(np.arange(a - l, b - l))
+        arr[np.ix_(*dst)] = vals[np.ix_(*src)]
 
     # ---- coroutine for one ticket ------------------------------------------
     def wait(self, tile, target):
@@ -122,10 +175,12 @@ class Machine:
         ups = [(a + dx, b + dy, c + dz) for dx in (0, 1) for dy in (0, 1) for dz in (0, 1)
                if (dx, dy, dz) != (0, 0, 0)]
         me = (a, b, c)
+        wx, wy, wz = self.widths(me)
         # band start: this tile and its upwind neighbours finished the previous band
         if band > 0:
             for u in [me] + ups:
-                if self.exists(band - 1, *u):
+                u = self.tile(band - 1, *u)
+                if u is not None:
                     yield from self.wait(u, 2 * t0)
         # ring slot reuse: the previous occupant of the slot has finished
         # writing it and its consumer (the -z neighbour) has finished reading it
@@ -134,13 +189,13 @@ class Machine:
             pb, pa, pbb, pc = self.tickets[t - self.R]
             pend = 2 * min(self.nsteps, (pb + 1) * K)
             yield from self.wait((pa, pbb, pc), pend)
-            cons = (pa, pbb, pc - 1)
-            if self.exists(pb, *cons):
+            cons = self.tile(pb, pa, pbb, pc - 1)
+            if cons is not None:
                 yield from self.wait(cons, pend)
         ox, oy, oz = a * Wx, b * Wy, c * Wz
         # slot box of step t0 + 1: lower corner (ox + t0, ...), size W + 1
         lo = (ox + t0, oy + t0, oz + t0)
-        P = (Wx + 1, Wy + 1, Wz + 1)
+        P = (wx + 1, wy + 1, wz + 1)
         S = [self.load_box(self.f[q], lo, P) for q in range(6)]
         C = [self.load_box(self.cE[q], lo, P) for q in range(3)]
         cH = self.cH
@@ -162,8 +217,9 @@ class Machine:
                 m = s - src["first_step"]
                 if m < 0 or m >= len(src["waveform"]):
                     continue
-                p = (src["i"] - blo[0], src["j"] - blo[1], src["k"] - blo[2])
-                if all(0 <= p[d] < self.W[d] for d in range(3)):
+                p = [src["i"] - blo[0], src["j"] - blo[1], src["k"] - blo[2]]
+                p = [x % n if per else x for x, n, per in zip(p, self.shape, self.per)]
+                if all(0 <= p[d] < (wx, wy, wz)[d] for d in range(3)):
                     arr = S[src["comp"]]
                     q = (p[0] + 1, p[1] + 1, p[2] + 1)
                     arr[q] = F32(arr[q] + F32(src["waveform"][m]))
@@ -173,7 +229,8 @@ class Machine:
             self.progress[me] = 2 * tau - 1
             yield "E"
             for u in ups:
-                if self.exists(band, *u):
+                u = self.tile(band, *u)
+                if u is not None:
                     yield from self.wait(u, 2 * tau - 1)
             # shift the box by one on every axis; load the forward shell's E
             S = [self._shift(x) for x in S]
@@ -196,7 +253,8 @@ class Machine:
             yield "H"
             if tau < t1:
                 for u in ups:
-                    if self.exists(band, *u):
+                    u = self.tile(band, *u)
+                    if u is not None:
                         yield from self.wait(u, 2 * tau)
                 self._load_forward(S, C, nlo, band, (a, b, c), tau - t0 - 1, comps=(3, 4, 5),
                                    coef=True)
@@ -216,7 +274,7 @@ class Machine:
             # y face: y = blo[1]
             self.store_box(self.f[q], blo, B[:, 0:1, :])
             # z face -> ring
-            self.ring[slot, ls, q] = B[:, :, 0]
+            self.ring[slot, ls, q, :B.shape[0], :B.shape[1]] = B[:, :, 0]
 
     def _publish_shifted(self, S, C, blo, slot, ls):
         """H of the first layer of B after the shift (box index 0 on each axis)."""
@@ -224,20 +282,21 @@ class Machine:
             B = S[q][:-1, :-1, :-1]
             self.store_box(self.f[q], blo, B[0:1, :, :])
             self.store_box(self.f[q], blo, B[:, 0:1, :])
-            self.ring[slot, ls, q] = B[:, :, 0]
+            self.ring[slot, ls, q, :B.shape[0], :B.shape[1]] = B[:, :, 0]
         for q in range(3):
-            self.ring[slot, ls, 6 + q] = C[q][:-1, :-1, 0]
+            cq = C[q][:-1, :-1, 0]
+            self.ring[slot, ls, 6 + q, :cq.shape[0], :cq.shape[1]] = cq
 
     def _load_forward(self, S, C, nlo, band, tile, ls, comps, coef=False):
         """Load the forward shell of the box whose lower corner is nlo."""
-        Wx, Wy, Wz = self.W
+        Wx, Wy, Wz = self.widths(tile)
         a, b, c = tile
         X, Y, Z = nlo[0] + Wx, nlo[1] + Wy, nlo[2] + Wz
         arrs = [(S[q], self.f[q], q) for q in comps]
         if coef:
             arrs += [(C[q], self.cE[q], 6 + q) for q in range(3)]
-        zt = (band, a, b, c + 1)
-        zslot = self.ticket_of[zt] % self.R if zt in self.ticket_of else None
+        zt = self.tile(band, a, b, c + 1)
+        zslot = self.ticket_of[(band,) + zt] % self.R if zt is not None else None
         for box, src, q in arrs:
             # x plane: all (y, z) of the box at x = X
             box[-1:, :, :] = self.load_box(src, (X, nlo[1], nlo[2]), (1, Wy + 1, Wz + 1))
@@ -247,7 +306,7 @@ class Machine:
             if zslot is None:
                 vals = np.zeros((Wx, Wy), F32)
             else:
-                vals = self.ring[zslot, ls, q]
+                vals = self.ring[zslot, ls, q, :Wx, :Wy]
             _, mask = self._box_index((nlo[0], nlo[1], Z), (Wx, Wy, 1))
             box[:-1, :-1, -1] = np.where(mask[:, :, 0], vals, F32(0))
 

@@ -7,7 +7,9 @@ exact same update).  Cases cover several tiles per axis with ragged tails,
 band lengths from 1 to more than the step count, sources on tile edges and
 corners, grids smaller than one tile, fewer persistent workgroups than
 tiles (schedule stress), calls split across bands, scheme switches on a live
-context, and the refusal of configurations the scheme does not cover.
+context, periodic axes (rings of tiles resident together, ragged last tiles,
+sources across the seams), and the refusal of configurations the scheme does
+not cover.
 """
 import numpy as np
 import pytest
@@ -85,8 +87,40 @@ def test_systolic_split_calls_and_scheme_switch():
     sim.close()
 
 
-def test_systolic_refuses_periodic_without_fallback():
-    sim = fdtd.Simulation((16, 16, 16), 0.5, 1.0, (PER, PEC, PEC), scheme="systolic")
+@pytest.mark.parametrize("shape,bc,nsteps,band,seed", [
+    ((31, 47, 29), (PER, PEC, PEC), 23, 7, 21),     # x ring of 3 tiles, ragged width 1
+    ((40, 36, 34), (PER, PER, PER), 20, 16, 22),    # every axis periodic: one group of 27
+    ((16, 20, 50), (PER, PEC, PER), 17, 5, 23),     # two-tile x ring, ragged z tile of width 5
+    ((45, 16, 46), (PEC, PER, PEC), 33, 10, 24),    # y ring with a width-1 tile
+    ((64, 64, 30), (PER, PER, PEC), 40, 6, 25),     # the boundary pattern of the C2 workload
+    ((30, 30, 30), (PER, PER, PER), 12, 1, 26),     # rings with no ragged tile, band of 1
+])
+def test_systolic_periodic_bitwise(shape, bc, nsteps, band, seed):
+    # dipoles at the interior, on tile edges and across the periodic seams
+    pts = [tuple(s // 2 for s in shape), (0, 15, 14), (shape[0] - 1, 1, shape[2] - 1), (15, 0, 0)]
+    dips = [p for p in pts if all(bc[a] == PER or p[a] >= 1 for a in (0, 1))
+            and all(p[a] < shape[a] for a in range(3))]
+    w = wl.small_case(shape, bc, seed=seed, nsteps=nsteps, dipoles=dips)
+    assert_bitwise(run_sys(w, band=band), oracle_f32(w), "systolic periodic %s %s" % (shape, bc))
+
+
+def test_systolic_periodic_ring_group_needs_resident_grid():
+    """A ring group (here 3 x 3 tiles of an x-y periodic grid) must be resident
+    at once: a smaller persistent grid is refused (never run, never a silent
+    fallback); a grid of exactly one group is bit-exact."""
+    w = wl.small_case((40, 40, 20), (PER, PER, PEC), seed=27, nsteps=9, dipoles=[(3, 38, 10)])
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic")
+    sim.set_option(fdtd.OPT_WORKGROUPS, 8)
+    with pytest.raises(fdtd.FdtdError) as e:
+        sim.step(1)
+    assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+    assert sim.current_step == 0
+    sim.close()
+    assert_bitwise(run_sys(w, band=4, wg=9), oracle_f32(w), "systolic periodic wg=9")
+
+
+def test_systolic_refuses_short_periodic_axis_without_fallback():
+    sim = fdtd.Simulation((15, 16, 16), 0.5, 1.0, (PER, PEC, PEC), scheme="systolic")
     with pytest.raises(fdtd.FdtdError) as e:
         sim.step(1)
     assert e.value.code == fdtd.FDTD_EUNSUPPORTED

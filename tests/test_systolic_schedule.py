@@ -69,6 +69,86 @@ def test_emulated_schedule_bitwise(shape, W, K, nsteps, seed):
                                           err_msg="component %d resident %d" % (c, resident))
 
 
+@pytest.mark.parametrize("shape,W,bc", [
+    ((10, 9, 11), (3, 4, 3), (1, 0, 0)),
+    ((10, 9, 11), (3, 4, 3), (0, 1, 1)),
+    ((8, 7, 9), (3, 3, 4), (1, 1, 1)),
+    ((9, 6, 12), (4, 5, 5), (1, 1, 0)),
+])
+def test_plan_periodic_groups(shape, W, bc):
+    """Periodic axes: every band holds the whole ring of each periodic axis,
+    the tiles of one ring group (same PEC coordinates) are consecutive, every
+    upwind neighbour outside the group comes earlier, and the boxes (wrapped)
+    cover each cell once at every step."""
+    K, n = 3, 7
+    tickets, ranges, ticket_of = emu.plan(shape, W, K, n, bc)
+    L = emu.ring_tiles(shape, W, bc)
+    pec = [d for d in range(3) if not bc[d]]
+    groups = {}
+    for i, (band, a, b, c) in enumerate(tickets):
+        g = (band,) + tuple((a, b, c)[d] for d in pec)
+        groups.setdefault(g, []).append(i)
+        for d in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]:
+            u = emu.wrap_tile((a + d[0], b + d[1], c + d[2]), L)
+            j = ticket_of.get((band,) + u)
+            if j is None:
+                continue
+            same = all(u[e] == (a, b, c)[e] for e in pec)
+            assert same or j < i
+    for g, idx in groups.items():
+        assert idx == list(range(idx[0], idx[0] + len(idx)))
+        assert len(idx) == int(np.prod([L[d] for d in range(3) if bc[d]]))
+    for band, rg in enumerate(ranges):
+        for tau in range(band * K + 1, min(n, (band + 1) * K) + 1):
+            cover = np.zeros(shape, int)
+            for a in range(rg[0][0], rg[0][1] + 1):
+                for b in range(rg[1][0], rg[1][1] + 1):
+                    for c in range(rg[2][0], rg[2][1] + 1):
+                        idx = []
+                        for d, t in enumerate((a, b, c)):
+                            w = W[d]
+                            if bc[d] and t == L[d] - 1:
+                                w = shape[d] - W[d] * (L[d] - 1)
+                            x = np.arange(t * W[d] + tau, t * W[d] + tau + w)
+                            idx.append(x % shape[d] if bc[d] else x[(x >= 0) & (x < shape[d])])
+                        cover[np.ix_(*idx)] += 1
+            assert np.all(cover == 1)
+
+
+@pytest.mark.parametrize("shape,W,K,nsteps,bc,seed", [
+    ((10, 9, 11), (3, 4, 3), 3, 7, (1, 0, 0), 11),
+    ((10, 9, 11), (3, 4, 3), 4, 9, (0, 1, 1), 12),
+    ((8, 7, 9), (3, 3, 4), 3, 8, (1, 1, 1), 13),
+    ((9, 6, 12), (4, 5, 5), 2, 7, (1, 1, 0), 14),
+    ((7, 8, 10), (6, 7, 3), 5, 9, (1, 1, 0), 15),   # two-tile rings, width-1 ragged tiles
+])
+def test_emulated_schedule_periodic_bitwise(shape, W, K, nsteps, bc, seed):
+    dips = [tuple(s // 2 for s in shape), (shape[0] - 1, 1, shape[2] - 1)]
+    dips = [d for d in dips if all(bc[a] or d[a] >= 1 for a in range(3))]
+    w = wl.small_case(shape, bc, seed=seed, nsteps=nsteps, dipoles=dips)
+    ref = _oracle(w, nsteps)
+    cE, cH = _coeffs(w)
+    L = emu.ring_tiles(shape, W, bc)
+    group = int(np.prod([L[d] for d in range(3) if bc[d]]))
+    for resident, sched_seed in [(group, 0), (group + 5, 1), (400, 2)]:
+        m = emu.Machine(w.fields, cE, cH, shape, W, K, nsteps, sources=w.sources, bc=bc)
+        got = m.run(resident=resident, seed=sched_seed)
+        for c in range(6):
+            np.testing.assert_array_equal(got[c].view(np.uint32), ref[c].view(np.uint32),
+                                          err_msg="component %d resident %d" % (c, resident))
+
+
+def test_emulated_periodic_ring_needs_coresidency():
+    """With fewer resident tickets than a ring group the schedule cannot
+    progress (the ring's tiles wait on each other in a cycle)."""
+    shape, W, bc = (9, 8, 8), (3, 4, 4), (1, 0, 0)
+    w = wl.small_case(shape, bc, seed=3, nsteps=4)
+    cE, cH = _coeffs(w)
+    m = emu.Machine(w.fields, cE, cH, shape, W, 2, 4, bc=bc)
+    with pytest.raises(RuntimeError, match="deadlocked"):
+        m.run(resident=2, seed=0)
+
+
 def test_emulator_detects_a_missing_wait(monkeypatch):
     """Sanity of the harness: dropping the wait before the forward-E load
     makes some interleaving read stale data."""

@@ -32,6 +32,19 @@ HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 VALU_FP32_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 FLOPS_PER_CELL = 36            # 6 components x 6 flops (Section 2)
 PLAIN_E_BYTES, PLAIN_H_BYTES = 48, 36   # algorithmic bytes per cell, per half-step kernel
+PLAIN_BYTES_PER_UPDATE = PLAIN_E_BYTES + PLAIN_H_BYTES
+
+
+def systolic_bytes_per_update(tile, band):
+    """Algorithmic HBM bytes per cell update of the systolic scheme (Section 4
+    accounting): every step a tile of V = Wx*Wy*Wz updated cells takes in its
+    leading faces (E, H and the coefficient: 36 B per cell) and puts out its
+    trailing faces (E and H: 24 B per cell), A = WyWz + WxWz + WxWy cells each;
+    once per band of K steps the whole state goes out and comes back in (60 B
+    per cell)."""
+    wx, wy, wz = tile
+    area = wy * wz + wx * wz + wx * wy
+    return (36 + 24) * area / (wx * wy * wz) + 60.0 / band
 
 
 def counter_traffic(kernel: str, source: str, launch: dict):
@@ -111,7 +124,7 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None):
         sim.close()
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
+def cpu_baseline(w, budget_s: float = 15.0):
     """The FP32 oracle, as it stands, on a bounded centre crop of the workload."""
     import oracle
     nx, ny, nz = w.shape
@@ -127,7 +140,7 @@ def cpu_baseline(w, budget_s: float = 12.0):
     t0 = time.perf_counter()
     oracle.step(cE, cH, f, 2, dtype=np.float32)
     per = (time.perf_counter() - t0) / 2
-    n = int(max(2, min(400, budget_s / max(per, 1e-6))))
+    n = int(max(2, min(5000, budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     oracle.step(cE, cH, f, n, step0=2, dtype=np.float32)
     t = time.perf_counter() - t0
@@ -200,15 +213,24 @@ def main():
         n, ms = stats[fdtd.KERNEL_SYSTOLIC]
         avg_s = ms / 1e3 / max(n, 1)
         steps_per_launch = args.steps / max(n, 1)
-        achieved = FLOPS_PER_CELL * cells * steps_per_launch / avg_s / 1e12
-        launch = {"workload": w.name, "steps": int(round(steps_per_launch)),
-                  "band": stats["info"]["band_steps"]}
+        band = stats["info"]["band_steps"]
+        b_alg = systolic_bytes_per_update(stats["info"]["tile"], band)
+        updates = cells * steps_per_launch
+        achieved = b_alg * updates / avg_s / 1e9
+        flops = FLOPS_PER_CELL * updates / avg_s / 1e12
+        launch = {"workload": w.name, "steps": int(round(steps_per_launch)), "band": band}
         traffic = counter_traffic("systolic_kernel", "paper_2502_20610_amd/csrc/systolic.hip",
                                   dict(launch, cells=cells))
-        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
+        # arithmetic intensity 36 / b_alg flop/B is below the machine balance
+        # (39.3 T op/s / 8 TB/s), so the roofline bound is HBM
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "systolic_kernel", "launches": n, "avg_launch_ms": avg_s * 1e3,
-                "traffic_GBps": None if traffic is None else traffic / avg_s / 1e9}
+                "alg_bytes_per_update": b_alg,
+                "traffic_bytes_per_update": None if traffic is None else traffic / updates,
+                "traffic_GBps": None if traffic is None else traffic / avg_s / 1e9,
+                "alu_achieved_TFLOPs": flops, "alu_peak_TFLOPs": VALU_FP32_PEAK_TFLOPS,
+                "alu_frac": flops / VALU_FP32_PEAK_TFLOPS}
     else:
         n, ms = stats[fdtd.KERNEL_PLAIN_E]
         avg_s = ms / 1e3 / max(n, 1)
@@ -233,12 +255,17 @@ def main():
         entry = {"cups": c, "ms_per_step": ts / args.steps * 1e3}
         if scheme == "systolic":
             entry.update(st["info"])
+            b = systolic_bytes_per_update(st["info"]["tile"], st["info"]["band_steps"])
+            entry["alg_bytes_per_update"] = b
+            entry["alg_roofline_frac"] = c * b / (HBM_PEAK_GBS * 1e9)
+            entry["effective_bw_frac_84B"] = c * PLAIN_BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9)
         if scheme == "plain":
             ne, mse = st[fdtd.KERNEL_PLAIN_E]
             nh, msh = st[fdtd.KERNEL_PLAIN_H]
             entry["E_avg_ms"] = mse / max(ne, 1)
             entry["H_avg_ms"] = msh / max(nh, 1)
-            entry["hbm_frac_84B"] = c * 84 / (HBM_PEAK_GBS * 1e9)
+            entry["alg_bytes_per_update"] = PLAIN_BYTES_PER_UPDATE
+            entry["alg_roofline_frac"] = c * PLAIN_BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9)
         out[scheme] = entry
     if "plain" in results and "systolic" in results:
         out["systolic_over_plain"] = out["systolic"]["cups"] / out["plain"]["cups"]

@@ -59,6 +59,7 @@ constexpr unsigned kOOB = 0xFFFFFFF0u;  // buffer offset that reads 0 / drops st
 // longest band: the per-band source samples are staged in LDS
 constexpr int kMaxBand = 64;
 
+
 struct SysArgs {
     float* f[6];
     const float* cE[3];
@@ -188,18 +189,27 @@ __device__ __forceinline__ int prog_index(const SysArgs& A, int a, int b, int c)
     return ((a - A.amin) * A.NB + (b - A.bmin)) * A.NC + (c - A.cmin);
 }
 
-// Make this workgroup's global stores visible at device scope, then set the
-// tile's progress counter (release).
+// Set the tile's progress counter (release): every wavefront has completed
+// the global stores the new level covers, and passed a barrier since.
 template <bool DEV>
-__device__ __forceinline__ void publish(const SysArgs& A, int me, unsigned v)
+__device__ __forceinline__ void set_flag(const SysArgs& A, int me, unsigned v)
 {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
     if (threadIdx.x == 0) {
         if (!DEV) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(A.progress + me, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
+
+// Make this workgroup's global stores visible at device scope, then set the
+// tile's progress counter.
+template <bool DEV>
+__device__ __forceinline__ void publish(const SysArgs& A, int me, unsigned v)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    set_flag<DEV>(A, me, v);
+}
+
 
 // Complete this workgroup's outstanding loads into LDS and make them visible
 // to every wavefront.
@@ -275,9 +285,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     __shared__ long long s_srcw[kLdsSrc][2]; // first, len
     __shared__ const float* s_srcp[kLdsSrc];
     __shared__ float s_wv[kLdsSrc][kMaxBand];  // their samples for the steps of the current band
+    __shared__ unsigned s_srcmask;             // LDS-cached sources this ticket may reach
 
     const int tid = threadIdx.x;
-    const int w = tid >> 6;         // wavefront
+    // wavefront index, wave-uniform (kept in a scalar register)
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = (tid >> 4) & 3;   // row within the wavefront
     const int ys = tid >> 4;        // y slot: 4 rows per wavefront, NW wavefronts
     const int zs = tid & 15;        // z slot: lane within the DPP row
@@ -415,6 +427,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const long long m = A.step0 + t0 + l - s_srcw[q][0];
                 s_wv[q][l] = (l < t1 - t0 && m >= 0 && m < s_srcw[q][1]) ? s_srcp[q][m] : 0.f;
             }
+            // Sources that can fall inside this tile during the band: on a PEC
+            // axis the cell is inside B_tau for tau in [p - o - w + 1, p - o];
+            // periodic axes are not narrowed.  The test at use stays exact.
+            if (tid == 0) s_srcmask = 0u;
+            __syncthreads();
+            if (tid < nl) {
+                int lo = t0 + 1, hi = t1;
+                const int p3[3] = {s_src[tid][1], s_src[tid][2], s_src[tid][3]};
+                const int o3[3] = {ox, oy, oz}, w3[3] = {wxr, wyr, wzr};
+                const bool per3[3] = {perx, pery, perz};
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (!per3[d]) {
+                        lo = max(lo, p3[d] - o3[d] - w3[d] + 1);
+                        hi = min(hi, p3[d] - o3[d]);
+                    }
+                // and the waveform covers some of those steps
+                const long long first = s_srcw[tid][0], len = s_srcw[tid][1];
+                lo = (int)max((long long)lo, first + 1 - A.step0);
+                hi = (int)min((long long)hi, first + len - A.step0);
+                if (lo <= hi) atomicOr(&s_srcmask, 1u << tid);
+            }
         }
         // ---- load the slot box of step t0 + 1 (lower corner o + t0) and
         //      read the upwind progress once
@@ -441,6 +475,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
         if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up)) break;
 
+        // (s_srcmask is complete: wait_tiles ends with a barrier)
+        const unsigned srcmask = __builtin_amdgcn_readfirstlane(s_srcmask);
         bool aborted = false;
         for (int tau = t0 + 1; tau <= t1; ++tau) {
             const int ls = tau - t0 - 1;
@@ -535,12 +571,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                                          (unsigned)A.nz + (unsigned)zz) * 4u : kOOB;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rf[q], o, ytr[q][j][zs]);
-                if (has_consumer) {
-                    const unsigned oz_ = (ring_base + (unsigned)j * PX + (unsigned)zs) * 4u;
+                // (dropped offsets when there is no consumer: no branch)
+                const unsigned oz_ = (ring_base + (unsigned)j * PX + (unsigned)zs) * 4u;
 #pragma unroll
-                    for (int q = Q0; q < Q0 + NQZ; ++q)
-                        bst<SP>(rring, oz_ + (unsigned)q * ring_comp * 4u, ztr[q][j][zs]);
-                }
+                for (int q = Q0; q < Q0 + NQZ; ++q)
+                    bst<SP>(rring, has_consumer ? oz_ + (unsigned)q * ring_comp * 4u : kOOB, ztr[q][j][zs]);
             };
             auto ensure_up = [&](unsigned level) -> bool {
                 if (s_up >= level) return true;
@@ -603,10 +638,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }                                                                                           \
     }
             {
-                const int nl = min(A.nsrc, kLdsSrc);
-                for (int q = 0; q < nl; ++q)
+                for (unsigned msk = srcmask; msk; msk &= msk - 1u) {
+                    const int q = __builtin_ctz(msk);
                     FDTD_APPLY_SOURCE(s_src[q][0], s_src[q][1], s_src[q][2], s_src[q][3], s_srcw[q][0],
                                       s_srcw[q][1], s_wv[q][ls]);
+                }
                 for (int q = kLdsSrc; q < A.nsrc; ++q)
                     FDTD_APPLY_SOURCE(A.src[q].comp, A.src[q].i, A.src[q].j, A.src[q].k, A.src[q].first,
                                       A.src[q].len, A.src[q].wave[m]);
@@ -614,8 +650,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #undef FDTD_APPLY_SOURCE
 
             // publish E of the first layer of the tile
-            if (inB) {
-                const unsigned o = off_at(0);
+            {
+                const unsigned o = inB ? off_at(0) : kOOB;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) bst<SP>(rf[q], o, E[q][0]);
             }
@@ -698,8 +734,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // now H registers j <-> x = ox+tau+j as well
 
             // publish H (and, on the z face, the coefficients) of the first layer
-            if (inB) {
-                const unsigned o = off_at(0);
+            {
+                const unsigned o = inB ? off_at(0) : kOOB;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) bst<SP>(rf[3 + q], o, H[q][0]);
             }

@@ -78,12 +78,15 @@ def zero_pec(fields, bc):
 
 
 def paint_boxes(shape, n_boxes: int, side_lo: int, side_hi, eps_bg: float, eps_box,
-                rng: np.random.Generator) -> np.ndarray:
+                rng: np.random.Generator, window=None) -> np.ndarray:
     """Background permittivity with ``n_boxes`` axis-aligned boxes painted in order.
 
     ``side_hi`` may be an int or a per-axis tuple; ``eps_box`` a float or a
-    callable ``rng -> float`` (per-box permittivity)."""
-    eps = np.full(shape, np.float32(eps_bg), dtype=np.float32)
+    callable ``rng -> float`` (per-box permittivity).  With ``window`` =
+    (lower corner, size) only that window of the map is returned (the same
+    random draws, boxes clipped to the window)."""
+    wlo, wsz = window if window is not None else ((0, 0, 0), tuple(shape))
+    eps = np.full(wsz, np.float32(eps_bg), dtype=np.float32)
     his = side_hi if isinstance(side_hi, (tuple, list)) else (side_hi,) * 3
     for _ in range(n_boxes):
         lo_corner, hi_corner = [], []
@@ -95,8 +98,9 @@ def paint_boxes(shape, n_boxes: int, side_lo: int, side_hi, eps_bg: float, eps_b
             lo_corner.append(c0)
             hi_corner.append(c0 + side)
         val = eps_box(rng) if callable(eps_box) else eps_box
-        eps[lo_corner[0]:hi_corner[0], lo_corner[1]:hi_corner[1], lo_corner[2]:hi_corner[2]] = \
-            np.float32(val)
+        sl = tuple(slice(max(lo_corner[a] - wlo[a], 0), max(min(hi_corner[a] - wlo[a], wsz[a]), 0))
+                   for a in range(3))
+        eps[sl] = np.float32(val)
     return eps
 
 
@@ -175,6 +179,21 @@ def c3_large_dielectric(shape=(1024, 1024, 512), nsteps: int = 500, seed: int = 
     dip = [tuple(int(rng.integers(16, s - 16)) for s in shape) for _ in range(3)]
     return random_dielectric(shape, (PEC, PEC, PEC), n_boxes, seed, nsteps, dipoles=dip,
                              name="c3_pec_dielectric_%dx%dx%d" % tuple(shape))
+
+
+def c3_centre_crop(n: int = 128, nsteps: int = 500, seed: int = 3) -> Workload:
+    """Accuracy rerun of the 1024x1024x512 workload: the central n^3 crop of its
+    permittivity map, PEC walls, zero fields, one Ez dipole at the crop centre."""
+    full_shape = (1024, 1024, 512)
+    o = tuple((s - n) // 2 for s in full_shape)
+    shape = (n, n, n)
+    # the draws of c3_large_dielectric's map, painted on the window only
+    eps = paint_boxes(full_shape, 2000, 8, 64, 2.08, 12.25, np.random.default_rng(seed),
+                      window=(o, shape))
+    fields = tuple(np.zeros(shape, np.float32) for _ in range(6))
+    wave = gaussian_sine(nsteps, 0.5)
+    return Workload("c3_centre_crop_%d" % n, shape, (PEC, PEC, PEC), 0.5, 1.0, nsteps, eps, fields,
+                    [dipole(EZ, n // 2, n // 2, n // 2, wave)])
 
 
 def bare_bones(n, seed: int = 6, nsteps: int = 100, shape=None) -> Workload:

@@ -1,0 +1,37 @@
+"""Host-side logic of bench.py: the algorithmic byte count, the counter-summary
+lookup and the single-GPU contract (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_systolic_bytes_per_update():
+    # Section 4 accounting: (36 in + 24 out) * A / V + 60 / K
+    assert bench.systolic_bytes_per_update((31, 15, 15), 64) == pytest.approx(10.873, abs=1e-3)
+    assert bench.systolic_bytes_per_update((15, 15, 15), 32) == pytest.approx(12.0 + 60 / 32)
+    # the plain two-launch scheme moves 84 B per update
+    assert bench.PLAIN_BYTES_PER_UPDATE == 84
+
+
+def test_counter_traffic_needs_matching_source_and_launch():
+    launch = {"workload": "c3_pec_dielectric_1024x1024x512", "steps": 128, "band": 32,
+              "cells": 1024 * 1024 * 512}
+    src = "paper_2502_20610_amd/csrc/systolic.hip"
+    t = bench.counter_traffic("systolic_kernel", src, launch)
+    if t is not None:   # the committed summary matches this source
+        assert t > 0
+    assert bench.counter_traffic("systolic_kernel", src, dict(launch, steps=7)) is None
+    assert bench.counter_traffic("systolic_kernel", src, dict(launch, band=16)) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

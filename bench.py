@@ -151,6 +151,31 @@ def cpu_baseline(w, budget_s: float = 15.0):
                       "%d steps (%.1f s)" % (cx, cy, cz, n, t)}
 
 
+def sweep(args):
+    """Fig. 1 analog: cell updates/s of both schemes against grid size, on the
+    bare-bones workload (random boxes, fields U(-1, 1), PEC walls, no sources).
+    Steps per point: the smallest multiple of the band above 100 that runs
+    about 0.3 s at the expected rate, so small grids are timed long enough."""
+    from paper_2502_20610_amd import fdtd
+    from paper_2502_20610_amd import workloads as wl
+    for n in [int(x) for x in args.sweep.split(",") if x]:
+        w = wl.bare_bones(n)
+        row = {"sweep": "bare_bones", "n": n, "cells": w.cells, "state_bytes_fp32": 24 * w.cells}
+        for scheme in args.schemes.split(","):
+            steps = max(128, int(0.3 * 5e10 / w.cells) // 32 * 32)
+            steps = min(steps, 20000)
+            try:
+                t, _ = run_scheme(w, scheme, steps, 32)
+            except fdtd.FdtdError as e:
+                row[scheme] = None
+                log("n=%d %s unavailable: %s" % (n, scheme, e))
+                continue
+            row[scheme] = {"cups": w.cells * steps / t, "steps": steps, "s": t}
+        if row.get("systolic") and row.get("plain"):
+            row["systolic_over_plain"] = row["systolic"]["cups"] / row["plain"]["cups"]
+        print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +186,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--band", type=int, default=0, help="systolic band length (0 = default)")
     ap.add_argument("--workgroups", type=int, default=0, help="systolic grid size (0 = auto)")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated n: instead of the headline line, one JSON line per "
+                         "bare-bones n^3 grid with both schemes (the Fig. 1 size sweep)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling HBM counters")
@@ -182,6 +210,9 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read + %d MiB written" % (args.calibrate_copy_mb, args.calibrate_copy_mb))
         del src, dst
+    if args.sweep:
+        sweep(args)
+        return
     log("building workload %s" % args.workload)
     w = make_workload(args.workload)
     cells = w.cells

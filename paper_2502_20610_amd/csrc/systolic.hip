@@ -70,8 +70,7 @@ struct SysArgs {
     int nt;
     const int* tix;    // ticket index of (band, tile)
     const int* band;   // per band: alo ahi blo bhi clo chi tix_off pad
-    unsigned* progress;
-    int amin, bmin, cmin, NA, NB, NC;
+    unsigned* progress;  // per ticket: last completed half-step level
     float* ring;
     unsigned ring_bytes;
     int R, K;
@@ -184,9 +183,12 @@ __device__ __forceinline__ bool axis_pos(int U, int Uw, int n, bool per, int k, 
     return (unsigned)p < (unsigned)n;
 }
 
-__device__ __forceinline__ int prog_index(const SysArgs& A, int a, int b, int c)
+// Ticket index of tile (a, b, c) of the band whose record is bi (the tile
+// must be in the band: band_has).
+__device__ __forceinline__ int ticket_of(const SysArgs& A, const int* bi, int a, int b, int c)
 {
-    return ((a - A.amin) * A.NB + (b - A.bmin)) * A.NC + (c - A.cmin);
+    return A.tix[bi[6] + ((a - bi[0]) * (bi[3] - bi[2] + 1) + (b - bi[2])) * (bi[5] - bi[4] + 1) +
+                 (c - bi[4])];
 }
 
 // Set the tile's progress counter (release): every wavefront has completed
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int t0 = bnd * A.K;
         const int t1 = min(A.nsteps, t0 + A.K);
         const int* bi = A.band + 8 * bnd;
-        const int me = prog_index(A, a, b, c);
+        const int me = t;  // progress counters are per ticket
         const int ox = a * WX, oy = b * WY, oz = c * WZ;
 
         // upwind neighbours that exist in this band
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const int ua = wrap_tile<PER>(A, 0, a + (d & 1)), ub = wrap_tile<PER>(A, 1, b + ((d >> 1) & 1)),
                       uc = wrap_tile<PER>(A, 2, c + ((d >> 2) & 1));
             if (band_has(bi, ua, ub, uc)) {
-                const int pi = prog_index(A, ua, ub, uc);
+                const int pi = ticket_of(A, bi, ua, ub, uc);
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
                     if (k == nup) ups[k] = pi;
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const int ua = wrap_tile<PER>(A, 0, a + (d & 1)), ub = wrap_tile<PER>(A, 1, b + ((d >> 1) & 1)),
                           uc = wrap_tile<PER>(A, 2, c + ((d >> 2) & 1));
                 if (band_has(bp, ua, ub, uc)) {
-                    const int pi = prog_index(A, ua, ub, uc);
+                    const int pi = ticket_of(A, bp, ua, ub, uc);
 #pragma unroll
                     for (int k = 0; k < 8; ++k)
                         if (k == nw) wl[k] = pi;
@@ -387,11 +389,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const int* pb = A.band + 8 * pk.x;
             const unsigned pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * A.K);
             int wl[8];
-            wl[0] = prog_index(A, pk.y, pk.z, pk.w);
+            wl[0] = t - A.R;
             int nw = 1;
             const int pcm = wrap_tile<PER>(A, 2, pk.w - 1);
             if (band_has(pb, pk.y, pk.z, pcm)) {
-                wl[1] = prog_index(A, pk.y, pk.z, pcm);
+                wl[1] = ticket_of(A, pb, pk.y, pk.z, pcm);
                 nw = 2;
             } else {
                 wl[1] = wl[0];
@@ -403,9 +405,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int has_consumer = band_has(bi, a, b, wrap_tile<PER>(A, 2, c - 1));
         const int czup = wrap_tile<PER>(A, 2, c + 1);
         const int has_zup = band_has(bi, a, b, czup);
-        const int slot_zup = has_zup ? A.tix[bi[6] + ((a - bi[0]) * (bi[3] - bi[2] + 1) + (b - bi[2])) *
-                                                      (bi[5] - bi[4] + 1) + (czup - bi[4])] % A.R
-                                     : 0;
+        const int slot_zup = has_zup ? ticket_of(A, bi, a, b, czup) % A.R : 0;
         // updated cells per axis (the last tile of a periodic ring is ragged),
         // the lanes that take the forward y and z faces, and the tile frame
         // origin modulo n on periodic axes
@@ -838,7 +838,6 @@ constexpr int kNW = 4;  // wavefronts per tile: tile = 15 x 15 x 15 updated cell
 struct SystolicState {
     int nsteps = -1, K = -1;
     int nt = 0, R = 0, D = 1, nbands = 0;
-    int amin = 0, bmin = 0, cmin = 0, NA = 0, NB = 0, NC = 0;
     int4* d_tickets = nullptr;
     int* d_tix = nullptr;
     int* d_band = nullptr;
@@ -888,7 +887,6 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     auto wrap = [&](int d, int v) { return per[d] ? ((v % L[d]) + L[d]) % L[d] : v; };
     const int nb = (nsteps + K - 1) / K;
     std::vector<int> band(8 * (size_t)nb);
-    int lo_all[3] = {1 << 30, 1 << 30, 1 << 30}, hi_all[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
     size_t ntot = 0;
     for (int bb = 0; bb < nb; ++bb) {
         const int t0 = bb * K, t1 = std::min(nsteps, t0 + K);
@@ -900,8 +898,6 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
             const int hi = per[d] ? L[d] - 1 : floordiv(N[d] - 2 - t0, W[d]);
             band[8 * bb + 2 * d] = lo;
             band[8 * bb + 2 * d + 1] = hi;
-            lo_all[d] = std::min(lo_all[d], lo);
-            hi_all[d] = std::max(hi_all[d], hi);
             cnt *= (size_t)(hi - lo + 1);
         }
         band[8 * bb + 6] = (int)ntot;
@@ -964,19 +960,13 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     s->nt = (int)ntot;
     s->nbands = nb;
     s->D = R;
-    s->amin = lo_all[0];
-    s->bmin = lo_all[1];
-    s->cmin = lo_all[2];
-    s->NA = hi_all[0] - lo_all[0] + 1;
-    s->NB = hi_all[1] - lo_all[1] + 1;
-    s->NC = hi_all[2] - lo_all[2] + 1;
     for (int d = 0; d < 3; ++d) {
         s->per[d] = per[d];
         s->L[d] = L[d];
     }
     s->group = group;
     hipError_t e;
-    size_t nprog = (size_t)s->NA * s->NB * s->NC;
+    const size_t nprog = ntot;  // one progress counter per ticket
     if ((e = hipMalloc(&s->d_tickets, ntot * sizeof(int4))) != hipSuccess ||
         (e = hipMalloc(&s->d_tix, ntot * sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&s->d_band, band.size() * sizeof(int))) != hipSuccess ||
@@ -1077,8 +1067,7 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
     ctx->sys_ring_slots = R;
     ctx->sys_band = s->K;
     ctx->sys_tickets = s->nt;
-    const size_t nprog = (size_t)s->NA * s->NB * s->NC;
-    hipLaunchKernelGGL(fill_u32, dim3(256), dim3(256), 0, ctx->stream, s->d_progress, 0u, (long long)nprog);
+    hipLaunchKernelGGL(fill_u32, dim3(256), dim3(256), 0, ctx->stream, s->d_progress, 0u, (long long)s->nt);
     hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, ctx->stream, s->d_counter, 0u, 1LL);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "systolic reset");
@@ -1097,12 +1086,6 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
     A.tix = s->d_tix;
     A.band = s->d_band;
     A.progress = s->d_progress;
-    A.amin = s->amin;
-    A.bmin = s->bmin;
-    A.cmin = s->cmin;
-    A.NA = s->NA;
-    A.NB = s->NB;
-    A.NC = s->NC;
     A.ring = s->d_ring;
     A.ring_bytes = (unsigned)s->ring_bytes;
     A.R = s->R;

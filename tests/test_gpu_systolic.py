@@ -59,6 +59,14 @@ def test_systolic_few_workgroups(wg):
     assert_bitwise(run_sys(w, band=6, wg=wg), oracle_f32(w), "systolic wg=%d" % wg)
 
 
+def test_systolic_long_call_small_grid():
+    """20000 steps in one call on 32^3: tiles drift one cell per step along the
+    diagonal, so over the call the tile indices span more than 1300 per axis
+    (the schedule keeps one progress counter per ticket, not per tile index)."""
+    w = wl.small_case((32, 32, 32), (PEC, PEC, PEC), seed=31, nsteps=20000, dipoles=[(16, 16, 16)])
+    assert_bitwise(run_sys(w), oracle_f32(w), "systolic 20000 steps")
+
+
 def test_systolic_c1_bitwise_and_fp64_bound():
     w = wl.c1_cavity_pulse()
     gpu = run_sys(w)

@@ -176,6 +176,40 @@ def sweep(args):
         print(json.dumps(row), flush=True)
 
 
+def adjoint_bench():
+    """One gradient of the 256x256x128 inverse-design objective: the forward
+    run (N steps with the monitor transform and checkpoints), the recompute of
+    every segment and the reverse sweep, timed together.  Reported as cell
+    updates/s of forward-step equivalents (3 N steps over the grid) and as
+    gradients per hour."""
+    import torch
+    from paper_2502_20610_amd import fdtd
+    from paper_2502_20610_amd import workloads as wl
+    w, a = wl.c5_adjoint()
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="plain")
+    try:
+        dev = torch.device("cuda:0")
+        sim.set_materials(torch.from_numpy(w.eps).to(dev))
+        for s in w.sources:
+            sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+        sim.synchronize()
+        t0 = time.perf_counter()
+        J, g = sim.adjoint(**a)
+        t = time.perf_counter() - t0
+    finally:
+        sim.close()
+    gs = g.sum(axis=0)   # all three components share the cell's permittivity
+    out = {"metric": "adjoint gradient time, %dx%dx%d FP32, %d steps" % (w.shape + (a["nsteps"],)),
+           "value": t, "unit": "s", "higher_is_better": False, "n_gpus": 1,
+           "forward_equiv_cups": 3 * w.cells * a["nsteps"] / t, "objective": J,
+           "grad_isotropic_absmax": float(np.abs(gs).max()),
+           "grad_isotropic_l2": float(np.linalg.norm(gs)),
+           "config": {"workload": w.name, "design_box": [a["des_lo"], a["des_hi"]],
+                      "monitor_box": [a["mon_lo"], a["mon_hi"]], "omega": a["omega"],
+                      "checkpoint_every": a["checkpoint_every"]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +223,9 @@ def main():
     ap.add_argument("--sweep", default="",
                     help="comma-separated n: instead of the headline line, one JSON line per "
                          "bare-bones n^3 grid with both schemes (the Fig. 1 size sweep)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the headline line, time the gradient of the 256x256x128 "
+                         "inverse-design setup (forward, checkpointed recompute, reverse sweep)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling HBM counters")
@@ -212,6 +249,9 @@ def main():
         del src, dst
     if args.sweep:
         sweep(args)
+        return
+    if args.adjoint:
+        adjoint_bench()
         return
     log("building workload %s" % args.workload)
     w = make_workload(args.workload)

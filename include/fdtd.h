@@ -144,9 +144,51 @@ int64_t fdtd_current_step(const fdtd_ctx* ctx);
  * NULL context, the message of the last failed fdtd_create on this thread. */
 const char* fdtd_last_error(const fdtd_ctx* ctx);
 
-/* Gradient of an objective with respect to permittivity (reverse-time
- * adjoint).  Not implemented in this build: returns FDTD_EUNSUPPORTED. */
-int fdtd_adjoint(fdtd_ctx* ctx, const void* objective, float* grad_eps, int where);
+/* ---- gradient with respect to permittivity (reverse-time adjoint) -------
+ *
+ * The paper motivates fast FDTD by inverse design (Section 1), where a
+ * solver is called for the gradient of a design objective.  The objective
+ * here is a frequency-domain monitor:
+ *
+ *     F(r) = sum_{n=1..nsteps} E_c^n(r) exp(-i omega n dt),   r in the monitor box,
+ *     J    = sum_r |F(r)|^2,
+ *
+ * E^n being the E field after step n of the run (E half-step and sources
+ * done).  The gradient is the exact derivative of the discrete update
+ * (Eq. 1 and its permutations, with cE = dt / (eps dx)): the reverse sweep
+ * runs the transposed half-steps backwards in time and accumulates
+ * dJ/dcE = sum_n lambda_E^n (.) CH(H^{n-1/2}) over the design box, and
+ * dJ/deps = -dJ/dcE * cE / eps (0 on the tangential entries of PEC walls,
+ * whose cE is pinned at 0).  The forward run is stored every
+ * checkpoint_every steps and recomputed segment by segment for the sweep. */
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(fdtd_adjoint_spec)                      */
+    int32_t mon_comp;       /* monitored component: FDTD_EX, FDTD_EY or FDTD_EZ */
+    int32_t mon_lo[3];      /* monitor box [mon_lo, mon_hi) per axis            */
+    int32_t mon_hi[3];
+    int32_t des_lo[3];      /* design box [des_lo, des_hi) per axis             */
+    int32_t des_hi[3];
+    int32_t checkpoint_every;  /* steps between stored states; 0 = 200         */
+    double omega;           /* angular frequency (radians per unit time)        */
+    int64_t nsteps;         /* steps of the forward run, >= 1                   */
+    double objective;       /* out: J (FP64)                                    */
+} fdtd_adjoint_spec;
+
+/* Run spec->nsteps steps forward from the current state (plain scheme, the
+ * sources included) while accumulating F in FP64, then the reverse sweep.
+ * Writes J to spec->objective and dJ/deps_c for c = x, y, z to grad_eps:
+ * three FP32 blocks of the design box, each C-ordered [dx][dy][dz], laid out
+ * component after component; `where` says whether grad_eps is host or device
+ * memory.  On return the context holds the state after the forward run
+ * (current step advanced by nsteps).  Device memory for the checkpoints
+ * ((nsteps / checkpoint_every + 2) copies of the six fields), the adjoint
+ * fields and the per-segment design-box history is allocated for the call
+ * and freed before it returns.
+ * Errors: FDTD_EINVAL for a bad spec (component, empty or out-of-grid
+ * boxes, nsteps < 1, checkpoint_every < 0, struct_size), FDTD_ENOMEM when
+ * the working memory does not fit; the context is unchanged in both cases.
+ * Synchronises the context's stream. */
+int fdtd_adjoint(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where);
 
 /* ---- tuning and measurement ------------------------------------------- */
 

@@ -527,13 +527,11 @@ const char* fdtd_last_error(const fdtd_ctx* ctx)
     return ctx->err.c_str();
 }
 
-int fdtd_adjoint(fdtd_ctx* ctx, const void* objective, float* grad_eps, int where)
+int fdtd_adjoint(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where)
 {
-    (void)objective;
-    (void)grad_eps;
-    (void)where;
-    if (!ctx) return FDTD_EINVAL;
-    return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: not implemented in this build");
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    return adjoint_run(ctx, spec, grad_eps, where);
 }
 
 int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)

@@ -100,6 +100,9 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps);
 void systolic_release(fdtd_ctx* ctx);
 void systolic_tile(int* wx, int* wy, int* wz);
 
+// Reverse-time adjoint of a monitor objective (adjoint.hip).
+int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where);
+
 // Launch the source-injection kernel for the step that starts at step count s.
 int launch_sources(fdtd_ctx* ctx, int64_t s);
 

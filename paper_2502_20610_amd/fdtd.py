@@ -54,6 +54,15 @@ class Config(ctypes.Structure):
                 ("stream", ctypes.c_void_p)]
 
 
+class AdjointSpec(ctypes.Structure):
+    """fdtd_adjoint_spec: monitor and design boxes are [lo, hi) per axis."""
+    _fields_ = [("struct_size", ctypes.c_uint32), ("mon_comp", ctypes.c_int32),
+                ("mon_lo", ctypes.c_int32 * 3), ("mon_hi", ctypes.c_int32 * 3),
+                ("des_lo", ctypes.c_int32 * 3), ("des_hi", ctypes.c_int32 * 3),
+                ("checkpoint_every", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("nsteps", ctypes.c_int64), ("objective", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -79,7 +88,7 @@ def load_library():
         "fdtd_synchronize": ([vp], ctypes.c_int),
         "fdtd_current_step": ([vp], i64),
         "fdtd_last_error": ([vp], ctypes.c_char_p),
-        "fdtd_adjoint": ([vp, vp, fp, ctypes.c_int], ctypes.c_int),
+        "fdtd_adjoint": ([vp, ctypes.POINTER(AdjointSpec), vp, ctypes.c_int], ctypes.c_int),
         "fdtd_set_option": ([vp, ctypes.c_int, i64], ctypes.c_int),
         "fdtd_kernel_stats": ([vp, ctypes.c_int, ctypes.POINTER(i64),
                                ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -241,8 +250,33 @@ class Simulation:
         self._check(self._lib.fdtd_get_info(self._h, int(key), ctypes.byref(v)))
         return int(v.value)
 
-    def adjoint(self):
-        self._check(self._lib.fdtd_adjoint(self._h, None, None, HOST))
+    def adjoint(self, nsteps: int, mon_comp: int, mon_lo, mon_hi, omega: float, des_lo, des_hi,
+                checkpoint_every: int = 0, out=None):
+        """Run ``nsteps`` forward with the monitor transform, then the reverse
+        sweep.  Returns (J, grad) with grad of shape (3, *design box) holding
+        dJ/deps_x, dJ/deps_y, dJ/deps_z; with ``out`` (a torch CUDA tensor of
+        that shape) the gradient is written there on the device."""
+        spec = AdjointSpec()
+        spec.struct_size = ctypes.sizeof(AdjointSpec)
+        spec.mon_comp = int(mon_comp)
+        for a in range(3):
+            spec.mon_lo[a], spec.mon_hi[a] = int(mon_lo[a]), int(mon_hi[a])
+            spec.des_lo[a], spec.des_hi[a] = int(des_lo[a]), int(des_hi[a])
+        spec.checkpoint_every = int(checkpoint_every)
+        spec.omega = float(omega)
+        spec.nsteps = int(nsteps)
+        shape = (3,) + tuple(int(des_hi[a]) - int(des_lo[a]) for a in range(3))
+        if out is not None:
+            if not _is_torch(out) or not out.is_cuda or tuple(out.shape) != shape or \
+                    str(out.dtype) != "torch.float32" or not out.is_contiguous():
+                raise ValueError("out must be a contiguous float32 CUDA tensor of shape %s" % (shape,))
+            self._check(self._lib.fdtd_adjoint(self._h, ctypes.byref(spec),
+                                               ctypes.c_void_p(out.data_ptr()), DEVICE))
+            return spec.objective, out
+        g = np.zeros(shape, np.float32)
+        self._check(self._lib.fdtd_adjoint(self._h, ctypes.byref(spec),
+                                           ctypes.c_void_p(g.ctypes.data), HOST))
+        return spec.objective, g
 
 
 def run_workload(w, scheme: str = "plain", nsteps: Optional[int] = None, device: int = 0,

@@ -196,6 +196,25 @@ def c3_centre_crop(n: int = 128, nsteps: int = 500, seed: int = 3) -> Workload:
                     [dipole(EZ, n // 2, n // 2, n // 2, wave)])
 
 
+def c5_adjoint(nsteps: int = 4000, seed: int = 5):
+    """Inverse-design gradient setup: 256x256x128 PEC box of eps 2.08 with a
+    centred 64x64x16 design block of per-cell eps ~ U[2.08, 12.25] (x 96-159,
+    y 96-159, z 56-71), an Ez dipole at (64, 128, 64) on its -x side, and the
+    objective sum |DFT Ez|^2 at the source frequency over the 64x64 monitor
+    plane x = 192, y 96-159, z 32-95.  Returns (workload, adjoint arguments)."""
+    shape = (256, 256, 128)
+    rng = np.random.default_rng(seed)
+    eps = np.full(shape, np.float32(2.08), dtype=np.float32)
+    eps[96:160, 96:160, 56:72] = rng.uniform(2.08, 12.25, (64, 64, 16)).astype(np.float32)
+    wave = gaussian_sine(nsteps, 0.5)
+    w = Workload("c5_adjoint_256x256x128", shape, (PEC, PEC, PEC), 0.5, 1.0, nsteps, eps, None,
+                 [dipole(EZ, 64, 128, 64, wave)])
+    omega = 2.0 * math.pi / (12.0 * math.sqrt(2.08))
+    args = dict(nsteps=nsteps, mon_comp=EZ, mon_lo=(192, 96, 32), mon_hi=(193, 160, 96),
+                omega=omega, des_lo=(96, 96, 56), des_hi=(160, 160, 72), checkpoint_every=200)
+    return w, args
+
+
 def bare_bones(n, seed: int = 6, nsteps: int = 100, shape=None) -> Workload:
     """Fig. 1-style sweep point: C2-style boxes, fields U(-1, 1), PEC walls, no
     sources (the paper's 'bare-bones' setup has none)."""

@@ -31,6 +31,40 @@ def test_config_struct_matches_header_layout():
     assert ctypes.sizeof(fdtd.Config) == 64
 
 
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and field offsets of the two ABI structs, as a C compiler lays
+    them out from include/fdtd.h, equal the binding's ctypes layouts."""
+    import subprocess
+    fields = {"fdtd_config": [f[0] for f in fdtd.Config._fields_],
+              "fdtd_adjoint_spec": [f[0] for f in fdtd.AdjointSpec._fields_]}
+    src = ['#include <stddef.h>', '#include <stdio.h>', '#include "fdtd.h"', "int main(void) {"]
+    for st, names in fields.items():
+        src.append('printf("%%s size %%zu\\n", "%s", sizeof(%s));' % (st, st))
+        for n in names:
+            src.append('printf("%%s %%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (st, n, st, n))
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st, cls in (("fdtd_config", fdtd.Config), ("fdtd_adjoint_spec", fdtd.AdjointSpec)):
+        assert got[(st, "size")] == ctypes.sizeof(cls)
+        for n in fields[st]:
+            assert got[(st, n)] == getattr(cls, n).offset, (st, n)
+
+
+def test_adjoint_rejects_bad_arguments_without_gpu():
+    lib = fdtd.load_library()
+    spec = fdtd.AdjointSpec()
+    spec.struct_size = ctypes.sizeof(fdtd.AdjointSpec)
+    g = (ctypes.c_float * 8)()
+    # a NULL context is rejected before anything else
+    assert lib.fdtd_adjoint(None, ctypes.byref(spec), g, fdtd.HOST) == fdtd.FDTD_EINVAL
+
+
 def _cfg(**kw):
     c = fdtd.Config()
     c.struct_size = ctypes.sizeof(fdtd.Config)

@@ -1,0 +1,140 @@
+"""GPU adjoint (fdtd_adjoint) against the FP64 adjoint oracle and finite differences.
+
+The GPU run is FP32 (fields, adjoint fields) with FP64 monitor transform and
+gradient sums; the oracle is FP64 throughout.  Checks:
+- J within 1e-5 and the design-box gradient within 1e-4 (relative L2) of the
+  oracle's, with checkpoint intervals that do and do not divide the run;
+- per-cell gradients within 1e-3 of central finite differences of the FP64
+  objective (the inverse-design accuracy bar), at cells chosen from the
+  oracle's gradient;
+- the context holds the forward run's final state afterwards (bitwise equal
+  to a plain run) and the device-output path equals the host-output path;
+- invalid specifications are refused without changing the context.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import adjoint as adj
+from paper_2502_20610_amd import fdtd
+from paper_2502_20610_amd import workloads as wl
+from tests.test_gpu_parity import assert_bitwise, oracle_f32
+
+pytestmark = pytest.mark.gpu
+PEC, PER = 0, 1
+
+
+def _sim(w, scheme="plain"):
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme)
+    sim.set_materials(w.eps)
+    if w.fields is not None:
+        sim.set_fields(w.fields)
+    for s in w.sources:
+        sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+    return sim
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _fd(w, c, cell, spec, h=1e-4):
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    base = oracle.coeff_E(eps3, w.bc, w.dt, w.dx)
+
+    def J(d):
+        e2 = [np.array(e, np.float64) for e in eps3]
+        e2[c][cell] += d
+        cE = tuple(np.where(b0 == 0.0, 0.0, w.dt / (e * w.dx)) for b0, e in zip(base, e2))
+        F, _, _ = adj.forward_dft(w.fields_or_zeros(), cE, w.dt / w.dx, spec["n"], spec["mon_lo"],
+                                  spec["mon_hi"], spec["comp"], spec["omega"], w.dt,
+                                  sources=w.sources)
+        return float(np.sum(np.abs(F) ** 2))
+    return (J(h) - J(-h)) / (2 * h)
+
+
+CASES = [
+    ("pec", (14, 12, 10), (PEC, PEC, PEC), 80, 25, (4, 3, 3), (8, 7, 6), (10, 1, 1), (11, 11, 9)),
+    ("mixed", (12, 13, 11), (PER, PEC, PER), 70, 70, (0, 4, 8), (5, 8, 11), (7, 2, 0), (8, 12, 11)),
+    ("ckpt1", (10, 9, 8), (PEC, PEC, PEC), 17, 1, (2, 2, 2), (5, 5, 5), (7, 1, 1), (8, 8, 7)),
+]
+
+
+@pytest.mark.parametrize("name,shape,bc,n,ck,dlo,dhi,mlo,mhi", CASES)
+def test_adjoint_matches_oracle(name, shape, bc, n, ck, dlo, dhi, mlo, mhi):
+    w = wl.small_case(shape, bc, seed=len(name), nsteps=n, dipoles=[(3, 4, 5)])
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    J_ref, g_ref = adj.gradient(w.fields, eps3, w.bc, w.dt, w.dx, n, mlo, mhi, 2, 0.4, dlo, dhi,
+                                sources=w.sources)
+    sim = _sim(w)
+    J, g = sim.adjoint(n, 2, mlo, mhi, 0.4, dlo, dhi, checkpoint_every=ck)
+    assert sim.current_step == n
+    # the context holds the forward run's final state
+    assert_bitwise(sim.read_fields(), oracle_f32(w, n), "state after adjoint")
+    sim.close()
+    assert abs(J - J_ref) <= 1e-5 * J_ref, (J, J_ref)
+    assert _rel(g, np.stack(g_ref)) < 1e-4
+
+
+def test_adjoint_gradient_matches_finite_differences():
+    """A scaled-down inverse-design setup: 64x64x32 PEC box with a dielectric
+    design block between a dipole and a monitor plane, 600 steps,
+    checkpoints every 200; eight cells checked against FP64 central
+    differences."""
+    shape = (64, 64, 32)
+    w = wl.random_dielectric(shape, (PEC, PEC, PEC), 6, 51, 600, side=(4, 16),
+                             dipoles=[(16, 32, 16)])
+    dlo, dhi = (24, 24, 14), (40, 40, 18)
+    rng = np.random.default_rng(52)
+    eps = np.array(w.eps)
+    eps[24:40, 24:40, 14:18] = rng.uniform(2.08, 12.25, (16, 16, 4)).astype(np.float32)
+    w.eps = eps
+    spec = dict(n=600, mon_lo=(48, 24, 8), mon_hi=(49, 40, 24), comp=2, omega=0.36305)
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    J_ref, g_ref = adj.gradient(w.fields_or_zeros(), eps3, w.bc, w.dt, w.dx, 600, spec["mon_lo"],
+                                spec["mon_hi"], 2, spec["omega"], dlo, dhi, sources=w.sources)
+    sim = _sim(w)
+    J, g = sim.adjoint(600, 2, spec["mon_lo"], spec["mon_hi"], spec["omega"], dlo, dhi,
+                       checkpoint_every=200)
+    sim.close()
+    assert abs(J - J_ref) <= 1e-5 * J_ref
+    gr = np.stack(g_ref)
+    big = np.argwhere(np.abs(gr) > 1e-2 * np.abs(gr).max())
+    pick = big[rng.choice(len(big), 8, replace=False)]
+    for c, a, b, k in pick:
+        cell = (dlo[0] + a, dlo[1] + b, dlo[2] + k)
+        fd = _fd(w, int(c), cell, spec)
+        assert abs(g[c, a, b, k] - fd) <= 1e-3 * abs(fd), (c, cell, g[c, a, b, k], fd)
+
+
+def test_adjoint_device_output_equals_host_output():
+    import torch
+    w = wl.small_case((12, 10, 9), (PEC, PEC, PEC), seed=9, nsteps=30, dipoles=[(4, 4, 4)])
+    args = (30, 2, (8, 1, 1), (9, 9, 8), 0.5, (2, 2, 2), (6, 5, 6))
+    sim = _sim(w)
+    J1, g1 = sim.adjoint(*args, checkpoint_every=7)
+    sim.close()
+    sim = _sim(w)
+    out = torch.empty((3, 4, 3, 4), dtype=torch.float32, device="cuda:0")
+    J2, g2 = sim.adjoint(*args, checkpoint_every=7, out=out)
+    sim.close()
+    assert J1 == J2
+    np.testing.assert_array_equal(g1, g2.cpu().numpy())
+
+
+@pytest.mark.parametrize("bad", [
+    dict(mon_comp=3), dict(mon_lo=(0, 0, 0), mon_hi=(0, 5, 5)), dict(des_hi=(13, 5, 5)),
+    dict(nsteps=0), dict(checkpoint_every=-2),
+])
+def test_adjoint_rejects_bad_spec(bad):
+    w = wl.small_case((12, 10, 9), (PEC, PEC, PEC), seed=9, nsteps=5)
+    kw = dict(nsteps=5, mon_comp=2, mon_lo=(8, 1, 1), mon_hi=(9, 9, 8), omega=0.5,
+              des_lo=(2, 2, 2), des_hi=(6, 5, 6), checkpoint_every=0)
+    kw.update(bad)
+    sim = _sim(w)
+    with pytest.raises(fdtd.FdtdError) as e:
+        sim.adjoint(**kw)
+    assert e.value.code == fdtd.FDTD_EINVAL
+    assert sim.current_step == 0
+    assert_bitwise(sim.read_fields(), w.fields, "unchanged state")
+    sim.close()

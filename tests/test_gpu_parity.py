@@ -138,9 +138,9 @@ def test_error_paths_on_gpu():
     with pytest.raises(fdtd.FdtdError) as e:
         sim.add_source(wl.EZ, 3, 3, 9, np.ones(4, np.float32))
     assert e.value.code == fdtd.FDTD_EINVAL
-    with pytest.raises(fdtd.FdtdError) as e:
-        sim.adjoint()
-    assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+    with pytest.raises(fdtd.FdtdError) as e:   # design box outside the grid
+        sim.adjoint(4, wl.EZ, (1, 1, 1), (2, 2, 2), 0.5, (6, 6, 6), (9, 8, 8))
+    assert e.value.code == fdtd.FDTD_EINVAL
     with pytest.raises(fdtd.FdtdError) as e:
         sim.step(-1)
     assert e.value.code == fdtd.FDTD_EINVAL

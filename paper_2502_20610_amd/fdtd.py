@@ -279,6 +279,58 @@ class Simulation:
         return spec.objective, g
 
 
+class DesignProblem:
+    """An inverse-design objective for :func:`design_objective`: a base
+    permittivity map (numpy float32, all three components share it), the
+    boundaries and step sizes, the sources, and the fdtd_adjoint arguments
+    (monitor and design boxes, omega, nsteps, checkpoint_every).  Every
+    evaluation starts from zero fields at step 0."""
+
+    def __init__(self, eps, bc, dt, dx, sources, adjoint_args, device: int = 0):
+        self.eps = np.ascontiguousarray(eps, dtype=np.float32)
+        self.bc, self.dt, self.dx = tuple(bc), float(dt), float(dx)
+        self.sources = list(sources)
+        self.args = dict(adjoint_args)
+        self.device = int(device)
+
+    def evaluate(self, eps_design: np.ndarray):
+        """(J, dJ/deps over the design box) for the given design permittivity."""
+        lo, hi = self.args["des_lo"], self.args["des_hi"]
+        eps = self.eps.copy()
+        eps[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = eps_design
+        sim = Simulation(eps.shape, self.dt, self.dx, self.bc, scheme="plain", device=self.device)
+        try:
+            sim.set_materials(eps)
+            for s in self.sources:
+                sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"],
+                               s.get("first_step", 0))
+            J, g = sim.adjoint(**self.args)
+        finally:
+            sim.close()
+        # one permittivity per cell drives all three components
+        return J, g.sum(axis=0)
+
+
+def design_objective(eps_design, problem: DesignProblem):
+    """J(eps_design) as a differentiable torch scalar: the forward value and
+    its gradient both come from one fdtd_adjoint call."""
+    import torch
+
+    class _Objective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x):
+            J, g = problem.evaluate(x.detach().to("cpu", torch.float32).numpy())
+            ctx.save_for_backward(torch.from_numpy(g).to(x.device, torch.float64))
+            return torch.tensor(J, dtype=torch.float64, device=x.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (g,) = ctx.saved_tensors
+            return (gJ * g).to(eps_design.dtype)
+
+    return _Objective.apply(eps_design)
+
+
 def run_workload(w, scheme: str = "plain", nsteps: Optional[int] = None, device: int = 0,
                  options=None):
     """Run a workloads.Workload through the library and return the six fields (host)."""

@@ -127,6 +127,21 @@ int fdtd_add_source(fdtd_ctx* ctx, int comp, int32_t i, int32_t j, int32_t k,
  * configurations it does not cover return FDTD_EUNSUPPORTED. */
 int fdtd_step(fdtd_ctx* ctx, int64_t nsteps);
 
+/* Advance n independent contexts (grids of any sizes and boundaries, their
+ * own materials and sources) by nsteps each in ONE persistent systolic launch
+ * over a shared queue of subdomain tickets (the paper's tile traversal of
+ * Section 3 extended over several simulations).  The result of each context
+ * is bit-identical to fdtd_step on it alone; the systolic scheme is used
+ * whatever each context's scheme option.  The launch runs on ctxs[0]'s
+ * stream, after the work already queued on every member's stream, and every
+ * member's stream continues after it.  Launch options (band steps, grid,
+ * spin limit) are ctxs[0]'s; a wait timeout is reported by every member.
+ * FDTD_EINVAL: NULL/empty list, n > 65536, a context listed twice, contexts
+ * on different devices, nsteps < 0; FDTD_EUNSUPPORTED: a member the systolic
+ * scheme does not cover, or a periodic ring group larger than the resident
+ * grid. */
+int fdtd_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps);
+
 /* Copy the components selected by comp_mask into dst[c].  A host destination
  * synchronises the stream before returning; a device destination is written
  * in stream order. */

@@ -488,6 +488,29 @@ int fdtd_step(fdtd_ctx* ctx, int64_t nsteps)
     return systolic_step(ctx, nsteps);
 }
 
+int fdtd_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps)
+{
+    if (!ctxs || n < 1 || n > 65536) return FDTD_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        int rc = check_live(ctxs[i]);
+        if (rc) return rc == FDTD_ESTATE ? fail(ctxs[i], rc, "context is poisoned") : rc;
+    }
+    fdtd_ctx* lead = ctxs[0];
+    if (nsteps < 0) return fail(lead, FDTD_EINVAL, "step_batch: nsteps must be >= 0");
+    for (int i = 0; i < n; ++i) {
+        if (ctxs[i]->device != lead->device)
+            return fail(lead, FDTD_EINVAL, "step_batch: all contexts must be on one device");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(lead, FDTD_EINVAL, "step_batch: a context appears twice");
+        std::string why;
+        if (!systolic_supported(ctxs[i], &why))
+            return fail(lead, FDTD_EUNSUPPORTED, "step_batch: context " + std::to_string(i) + ": " + why);
+    }
+    if (nsteps == 0) return FDTD_OK;
+    (void)hipSetDevice(lead->device);
+    return systolic_step_batch(ctxs, n, nsteps);
+}
+
 int fdtd_read_fields(fdtd_ctx* ctx, uint32_t comp_mask, float* const dst[6], int where)
 {
     int rc = check_live(ctx);

@@ -97,6 +97,7 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps);
 // Systolic scheme (systolic.hip).
 int systolic_supported(const fdtd_ctx* ctx, std::string* why);
 int systolic_step(fdtd_ctx* ctx, int64_t nsteps);
+int systolic_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps);
 void systolic_release(fdtd_ctx* ctx);
 void systolic_tile(int* wx, int* wy, int* wz);
 

@@ -43,6 +43,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <vector>
 
@@ -60,31 +61,51 @@ constexpr unsigned kOOB = 0xFFFFFFF0u;  // buffer offset that reads 0 / drops st
 constexpr int kMaxBand = 64;
 
 
-struct SysArgs {
+// One simulation of a launch (a launch advances one or several independent
+// simulations; every ticket names its simulation).
+struct SimArgs {
     float* f[6];
     const float* cE[3];
     float cH;
     int nx, ny, nz;
-    unsigned fbytes;  // bytes of one field array
-    const int4* tickets;
+    unsigned fbytes;   // bytes of one field array
+    const int* band;   // per band: alo ahi blo bhi clo chi tix_off pad (tix_off into the launch's table)
+    long long step0;
+    const DevSource* src;
+    int nsrc;
+    int per[3];  // periodic axis: tiles form a ring, positions wrap
+    int L[3];    // tiles of the ring on a periodic axis
+    int wr[3];   // updated cells of the ring's last (ragged) tile
+};
+
+struct SysArgs {
+    const SimArgs* sims;
+    const int* tsim;   // simulation of each ticket; null when there is one
+    const int4* tickets;  // (band, a, b, c)
     int nt;
     const int* tix;    // ticket index of (band, tile)
-    const int* band;   // per band: alo ahi blo bhi clo chi tix_off pad
     unsigned* progress;  // per ticket: last completed half-step level
     float* ring;
     unsigned ring_bytes;
     int R, K;
     int nsteps;
-    long long step0;
-    const DevSource* src;
-    int nsrc;
     unsigned* counter;
     int* error;
     long long spin_limit;
-    int per[3];  // periodic axis: tiles form a ring, positions wrap
-    int L[3];    // tiles of the ring on a periodic axis
-    int wr[3];   // updated cells of the ring's last (ragged) tile
 };
+
+// A simulation record read word by word into scalar registers (the record is
+// the same for every lane; the compiler cannot see that from a global load).
+__device__ __forceinline__ SimArgs load_sim(const SimArgs* p)
+{
+    static_assert(sizeof(SimArgs) % 4 == 0, "record of whole words");
+    SimArgs s;
+    const int* src = reinterpret_cast<const int*>(p);
+    int* dst = reinterpret_cast<int*>(&s);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(SimArgs) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return s;
+}
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes)
 {
@@ -161,10 +182,10 @@ __device__ __forceinline__ int band_has(const int* bi, int a, int b, int c)
 // Tile coordinate v + (-1, 0 or +1) on an axis: wrapped onto the ring of a
 // periodic axis.
 template <bool PER>
-__device__ __forceinline__ int wrap_tile(const SysArgs& A, int d, int v)
+__device__ __forceinline__ int wrap_tile(const SimArgs& P, int d, int v)
 {
-    if (!PER || !A.per[d]) return v;
-    return v >= A.L[d] ? v - A.L[d] : (v < 0 ? v + A.L[d] : v);
+    if (!PER || !P.per[d]) return v;
+    return v >= P.L[d] ? v - P.L[d] : (v < 0 ? v + P.L[d] : v);
 }
 
 // Grid position (o + tau) + k on an axis, k in [-1, 16]: U = o + tau (tile
@@ -296,26 +317,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const int ys = tid >> 4;        // y slot: 4 rows per wavefront, NW wavefronts
     const int zs = tid & 15;        // z slot: lane within the DPP row
     if (tid == 0) s_abort = 0;
-    if (tid < min(A.nsrc, kLdsSrc)) {
-        const DevSource sq = A.src[tid];
-        s_src[tid][0] = sq.comp;
-        s_src[tid][1] = sq.i;
-        s_src[tid][2] = sq.j;
-        s_src[tid][3] = sq.k;
-        s_srcw[tid][0] = sq.first;
-        s_srcw[tid][1] = sq.len;
-        s_srcp[tid] = sq.wave;
-    }
-
-    __amdgpu_buffer_rsrc_t rf[6], rc[3];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) rf[c] = make_rsrc(A.f[c], A.fbytes);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) rc[c] = make_rsrc(A.cE[c], A.fbytes);
     const __amdgpu_buffer_rsrc_t rring = make_rsrc(A.ring, A.ring_bytes);
-    const unsigned plane = (unsigned)A.ny * (unsigned)A.nz;
-    const float cH = A.cH;
-    const bool perx = PER && A.per[0], pery = PER && A.per[1], perz = PER && A.per[2];
     constexpr unsigned ring_step = 9u * PY * PX;  // floats per (slot, local step)
     constexpr unsigned ring_comp = PY * PX;       // floats per component
 
@@ -329,14 +331,35 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             s_ticket = err ? A.nt : (int)atomicAdd(A.counter, 1u);
         }
         __syncthreads();
-        const int t = s_ticket;
+        const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // wave-uniform
         if (t >= A.nt || s_abort) break;
 
         const int4 tk = A.tickets[t];
         const int bnd = tk.x, a = tk.y, b = tk.z, c = tk.w;
         const int t0 = bnd * A.K;
         const int t1 = min(A.nsteps, t0 + A.K);
-        const int* bi = A.band + 8 * bnd;
+        // this ticket's simulation: arrays, sizes, sources, boundaries
+        const SimArgs P = load_sim(A.sims + (A.tsim ? __builtin_amdgcn_readfirstlane(A.tsim[t]) : 0));
+        const int* bi = P.band + 8 * bnd;
+        __amdgpu_buffer_rsrc_t rf[6], rc[3];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) rf[q] = make_rsrc(P.f[q], P.fbytes);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) rc[q] = make_rsrc(P.cE[q], P.fbytes);
+        const unsigned plane = (unsigned)P.ny * (unsigned)P.nz;
+        const float cH = P.cH;
+        const bool perx = PER && P.per[0], pery = PER && P.per[1], perz = PER && P.per[2];
+        if (tid < min(P.nsrc, kLdsSrc)) {
+            const DevSource sq = P.src[tid];
+            s_src[tid][0] = sq.comp;
+            s_src[tid][1] = sq.i;
+            s_src[tid][2] = sq.j;
+            s_src[tid][3] = sq.k;
+            s_srcw[tid][0] = sq.first;
+            s_srcw[tid][1] = sq.len;
+            s_srcp[tid] = sq.wave;
+        }
+        __syncthreads();
         const int me = t;  // progress counters are per ticket
         const int ox = a * WX, oy = b * WY, oz = c * WZ;
 
@@ -345,8 +368,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         int nup = 0;
 #pragma unroll
         for (int d = 1; d < 8; ++d) {
-            const int ua = wrap_tile<PER>(A, 0, a + (d & 1)), ub = wrap_tile<PER>(A, 1, b + ((d >> 1) & 1)),
-                      uc = wrap_tile<PER>(A, 2, c + ((d >> 2) & 1));
+            const int ua = wrap_tile<PER>(P, 0, a + (d & 1)), ub = wrap_tile<PER>(P, 1, b + ((d >> 1) & 1)),
+                      uc = wrap_tile<PER>(P, 2, c + ((d >> 2) & 1));
             if (band_has(bi, ua, ub, uc)) {
                 const int pi = ticket_of(A, bi, ua, ub, uc);
 #pragma unroll
@@ -361,13 +384,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 
         // band start: this tile and its upwind neighbours finished the previous band
         if (bnd > 0) {
-            const int* bp = A.band + 8 * (bnd - 1);
+            const int* bp = P.band + 8 * (bnd - 1);
             int wl[8];
             int nw = 0;
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
-                const int ua = wrap_tile<PER>(A, 0, a + (d & 1)), ub = wrap_tile<PER>(A, 1, b + ((d >> 1) & 1)),
-                          uc = wrap_tile<PER>(A, 2, c + ((d >> 2) & 1));
+                const int ua = wrap_tile<PER>(P, 0, a + (d & 1)), ub = wrap_tile<PER>(P, 1, b + ((d >> 1) & 1)),
+                          uc = wrap_tile<PER>(P, 2, c + ((d >> 2) & 1));
                 if (band_has(bp, ua, ub, uc)) {
                     const int pi = ticket_of(A, bp, ua, ub, uc);
 #pragma unroll
@@ -386,12 +409,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int slot = t % A.R;
         if (t >= A.R) {
             const int4 pk = A.tickets[t - A.R];
-            const int* pb = A.band + 8 * pk.x;
+            const SimArgs PP = load_sim(A.sims + (A.tsim ? __builtin_amdgcn_readfirstlane(A.tsim[t - A.R]) : 0));
+            const int* pb = PP.band + 8 * pk.x;
             const unsigned pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * A.K);
             int wl[8];
             wl[0] = t - A.R;
             int nw = 1;
-            const int pcm = wrap_tile<PER>(A, 2, pk.w - 1);
+            const int pcm = wrap_tile<PER>(PP, 2, pk.w - 1);
             if (band_has(pb, pk.y, pk.z, pcm)) {
                 wl[1] = ticket_of(A, pb, pk.y, pk.z, pcm);
                 nw = 2;
@@ -402,29 +426,29 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             for (int k = 2; k < 8; ++k) wl[k] = wl[0];
             if (!wait_tiles<DEV>(A, wl, nw, pend, &s_abort, nullptr)) break;
         }
-        const int has_consumer = band_has(bi, a, b, wrap_tile<PER>(A, 2, c - 1));
-        const int czup = wrap_tile<PER>(A, 2, c + 1);
+        const int has_consumer = band_has(bi, a, b, wrap_tile<PER>(P, 2, c - 1));
+        const int czup = wrap_tile<PER>(P, 2, c + 1);
         const int has_zup = band_has(bi, a, b, czup);
         const int slot_zup = has_zup ? ticket_of(A, bi, a, b, czup) % A.R : 0;
         // updated cells per axis (the last tile of a periodic ring is ragged),
         // the lanes that take the forward y and z faces, and the tile frame
         // origin modulo n on periodic axes
-        const int wxr = (perx && a == A.L[0] - 1) ? A.wr[0] : WX;
-        const int wyr = (pery && b == A.L[1] - 1) ? A.wr[1] : WY;
-        const int wzr = (perz && c == A.L[2] - 1) ? A.wr[2] : WZ;
+        const int wxr = (perx && a == P.L[0] - 1) ? P.wr[0] : WX;
+        const int wyr = (pery && b == P.L[1] - 1) ? P.wr[1] : WY;
+        const int wzr = (perz && c == P.L[2] - 1) ? P.wr[2] : WZ;
         const int fy = (wyr + 1) & (PY - 1), fz = (wzr + 1) & (PZ - 1);
         int Xw = 0, Yw = 0, Zw = 0;
-        if (perx) Xw = (ox + t0 + 1) % A.nx;
-        if (pery) Yw = (oy + t0 + 1) % A.ny;
-        if (perz) Zw = (oz + t0 + 1) % A.nz;
+        if (perx) Xw = (ox + t0 + 1) % P.nx;
+        if (pery) Yw = (oy + t0 + 1) % P.ny;
+        if (perz) Zw = (oz + t0 + 1) % P.nz;
 
         // ---- the band's samples of the LDS-cached sources (step tau reads
         //      sample step0 + tau - 1 - first; the range test is repeated at use)
         {
-            const int nl = min(A.nsrc, kLdsSrc);
+            const int nl = min(P.nsrc, kLdsSrc);
             for (int i = tid; i < nl * kMaxBand; i += 64 * NW) {
                 const int q = i / kMaxBand, l = i % kMaxBand;
-                const long long m = A.step0 + t0 + l - s_srcw[q][0];
+                const long long m = P.step0 + t0 + l - s_srcw[q][0];
                 s_wv[q][l] = (l < t1 - t0 && m >= 0 && m < s_srcw[q][1]) ? s_srcp[q][m] : 0.f;
             }
             // Sources that can fall inside this tile during the band: on a PEC
@@ -445,8 +469,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     }
                 // and the waveform covers some of those steps
                 const long long first = s_srcw[tid][0], len = s_srcw[tid][1];
-                lo = (int)max((long long)lo, first + 1 - A.step0);
-                hi = (int)min((long long)hi, first + len - A.step0);
+                lo = (int)max((long long)lo, first + 1 - P.step0);
+                hi = (int)min((long long)hi, first + len - P.step0);
                 if (lo <= hi) atomicOr(&s_srcmask, 1u << tid);
             }
         }
@@ -456,14 +480,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         {
             const int by = oy + t0, bz = oz + t0;
             int y, z;
-            const bool oky = axis_pos<PER>(by + 1, Yw, A.ny, pery, ((ys - by) & (PY - 1)) - 1, y);
-            const bool okz = axis_pos<PER>(bz + 1, Zw, A.nz, perz, ((zs - bz) & (PZ - 1)) - 1, z);
+            const bool oky = axis_pos<PER>(by + 1, Yw, P.ny, pery, ((ys - by) & (PY - 1)) - 1, y);
+            const bool okz = axis_pos<PER>(bz + 1, Zw, P.nz, perz, ((zs - bz) & (PZ - 1)) - 1, z);
             const bool okyz = oky && okz;
-            const unsigned yz = (unsigned)y * (unsigned)A.nz + (unsigned)z;
+            const unsigned yz = (unsigned)y * (unsigned)P.nz + (unsigned)z;
 #pragma unroll
             for (int j = 0; j < PX; ++j) {
                 int x;
-                const bool okx = axis_pos<PER>(ox + t0 + 1, Xw, A.nx, perx, j - 1, x);
+                const bool okx = axis_pos<PER>(ox + t0 + 1, Xw, P.nx, perx, j - 1, x);
                 const unsigned off = (okyz && okx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
@@ -485,32 +509,32 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const int dz = (zs - bz) & (PZ - 1);
             const int Ux = ox + tau, Uy = oy + tau, Uz = oz + tau;  // frame origin of B_tau
             int y, z;
-            const bool oky = axis_pos<PER>(Uy, Yw, A.ny, pery, dy - 1, y);
-            const bool okz0 = axis_pos<PER>(Uz, Zw, A.nz, perz, dz - 1, z);
+            const bool oky = axis_pos<PER>(Uy, Yw, P.ny, pery, dy - 1, y);
+            const bool okz0 = axis_pos<PER>(Uz, Zw, P.nz, perz, dz - 1, z);
             const bool inB = dy >= 1 && dz >= 1 && dy <= wyr && dz <= wzr;
             const bool okyz = oky && okz0;
-            const unsigned yz = (unsigned)y * (unsigned)A.nz + (unsigned)z;
+            const unsigned yz = (unsigned)y * (unsigned)P.nz + (unsigned)z;
             // offset of this lane's cell at x = Ux + k
             auto off_at = [&](int k) -> unsigned {
                 int x;
-                const bool okx = axis_pos<PER>(Ux, Xw, A.nx, perx, k, x);
+                const bool okx = axis_pos<PER>(Ux, Xw, P.nx, perx, k, x);
                 return (okyz && okx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
             };
             // coordinates of this lane in the next box (after the one-cell move)
             const int dy1 = (dy - 1) & (PY - 1), dz1 = (dz - 1) & (PZ - 1);
             int y1, z1;
-            const bool oky1 = axis_pos<PER>(Uy, Yw, A.ny, pery, dy1, y1);
-            const bool okz1 = axis_pos<PER>(Uz, Zw, A.nz, perz, dz1, z1);
+            const bool oky1 = axis_pos<PER>(Uy, Yw, P.ny, pery, dy1, y1);
+            const bool okz1 = axis_pos<PER>(Uz, Zw, P.nz, perz, dz1, z1);
             const bool okyz1 = oky1 && okz1;
-            const unsigned yz1 = (unsigned)y1 * (unsigned)A.nz + (unsigned)z1;
+            const unsigned yz1 = (unsigned)y1 * (unsigned)P.nz + (unsigned)z1;
             const unsigned ring_base = ((unsigned)slot * (unsigned)A.K + (unsigned)ls) * ring_step;
             const unsigned ring_zup = ((unsigned)slot_zup * (unsigned)A.K + (unsigned)ls) * ring_step;
             // the forward y and z planes of the next box
             int yf, zf, zl;
-            const bool oky_f = axis_pos<PER>(Uy, Yw, A.ny, pery, wyr, yf);
-            const bool okz_f = axis_pos<PER>(Uz, Zw, A.nz, perz, wzr, zf);
+            const bool oky_f = axis_pos<PER>(Uy, Yw, P.ny, pery, wyr, yf);
+            const bool okz_f = axis_pos<PER>(Uz, Zw, P.nz, perz, wzr, zf);
             // z of DPP lane zs in the next box, for the y-face loads
-            const bool okz_l = axis_pos<PER>(Uz, Zw, A.nz, perz, (zs - oz - tau) & (PZ - 1), zl);
+            const bool okz_l = axis_pos<PER>(Uz, Zw, P.nz, perz, (zs - oz - tau) & (PZ - 1), zl);
             (void)zf;
 
             // Issue the loads of the next box's forward shell for components
@@ -521,21 +545,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
                 // x face: rows of the wavefront are y slots, lanes are z slots
                 int xf;
-                const bool okxf = axis_pos<PER>(Ux, Xw, A.nx, perx, wxr, xf);
+                const bool okxf = axis_pos<PER>(Ux, Xw, P.nx, perx, wxr, xf);
                 const unsigned oxf = (okyz1 && okxf) ? ((unsigned)xf * plane + yz1) * 4u : kOOB;
                 // y face: rows of the wavefront are x, lanes are z
                 const int j = 4 * w + r;
                 int x;
-                const bool okx = axis_pos<PER>(Ux, Xw, A.nx, perx, j, x);
+                const bool okx = axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
                 const unsigned oyf = (oky_f && okz_l && okx)
-                                         ? (((unsigned)x * (unsigned)A.ny + (unsigned)yf) * (unsigned)A.nz + (unsigned)zl) * 4u
+                                         ? (((unsigned)x * (unsigned)P.ny + (unsigned)yf) * (unsigned)P.nz + (unsigned)zl) * 4u
                                          : kOOB;
                 // z face: rows are y, lanes are x, from the +z neighbour's ring slot
                 const int yy = 4 * w + r;
                 int xr, yr;
                 const bool okz = has_zup && okz_f && zs < WX && yy < WY &&
-                                 axis_pos<PER>(Ux, Xw, A.nx, perx, zs, xr) &&
-                                 axis_pos<PER>(Uy, Yw, A.ny, pery, yy, yr);
+                                 axis_pos<PER>(Ux, Xw, P.nx, perx, zs, xr) &&
+                                 axis_pos<PER>(Uy, Yw, P.ny, pery, yy, yr);
                 const unsigned ozf = (ring_zup + (unsigned)yy * PX + (unsigned)zs) * 4u;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) {
@@ -564,11 +588,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const int dzl = (zs - oz - tau + 1) & (PZ - 1);
                 int xs_, ys_, zz;
                 const bool in = j < wxr && dzl >= 1 && dzl <= wzr &&
-                                axis_pos<PER>(Ux, Xw, A.nx, perx, j, xs_) &&
-                                axis_pos<PER>(Uy, Yw, A.ny, pery, 0, ys_) &&
-                                axis_pos<PER>(Uz, Zw, A.nz, perz, dzl - 1, zz);
-                const unsigned o = in ? ((((unsigned)xs_) * (unsigned)A.ny + (unsigned)ys_) *
-                                         (unsigned)A.nz + (unsigned)zz) * 4u : kOOB;
+                                axis_pos<PER>(Ux, Xw, P.nx, perx, j, xs_) &&
+                                axis_pos<PER>(Uy, Yw, P.ny, pery, 0, ys_) &&
+                                axis_pos<PER>(Uz, Zw, P.nz, perz, dzl - 1, zz);
+                const unsigned o = in ? ((((unsigned)xs_) * (unsigned)P.ny + (unsigned)ys_) *
+                                         (unsigned)P.nz + (unsigned)zz) * 4u : kOOB;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rf[q], o, ytr[q][j][zs]);
                 // (dropped offsets when there is no consumer: no branch)
@@ -619,11 +643,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // so that neither becomes a generic-address load)
 #define FDTD_APPLY_SOURCE(comp, si, sj, sk, first, len, sample)                                        \
     {                                                                                               \
-        const long long m = A.step0 + tau - 1 - (first);                                            \
+        const long long m = P.step0 + tau - 1 - (first);                                            \
         int px = (si) - (perx ? Xw : Ux), py = (sj) - (pery ? Yw : Uy), pz = (sk) - (perz ? Zw : Uz); \
-        px += (perx && px < 0) ? A.nx : 0;                                                          \
-        py += (pery && py < 0) ? A.ny : 0;                                                          \
-        pz += (perz && pz < 0) ? A.nz : 0;                                                          \
+        px += (perx && px < 0) ? P.nx : 0;                                                          \
+        py += (pery && py < 0) ? P.ny : 0;                                                          \
+        pz += (perz && pz < 0) ? P.nz : 0;                                                          \
         if (m >= 0 && m < (len) && (unsigned)px < (unsigned)wxr && (unsigned)py < (unsigned)wyr &&  \
             (unsigned)pz < (unsigned)wzr) {                                                         \
             const float wv = (sample);                                                              \
@@ -643,9 +667,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     FDTD_APPLY_SOURCE(s_src[q][0], s_src[q][1], s_src[q][2], s_src[q][3], s_srcw[q][0],
                                       s_srcw[q][1], s_wv[q][ls]);
                 }
-                for (int q = kLdsSrc; q < A.nsrc; ++q)
-                    FDTD_APPLY_SOURCE(A.src[q].comp, A.src[q].i, A.src[q].j, A.src[q].k, A.src[q].first,
-                                      A.src[q].len, A.src[q].wave[m]);
+                for (int q = kLdsSrc; q < P.nsrc; ++q)
+                    FDTD_APPLY_SOURCE(P.src[q].comp, P.src[q].i, P.src[q].j, P.src[q].k, P.src[q].first,
+                                      P.src[q].len, P.src[q].wave[m]);
             }
 #undef FDTD_APPLY_SOURCE
 
@@ -814,9 +838,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             }
             if (PER) {
-                Xw = (perx && Xw == A.nx - 1) ? 0 : Xw + 1;
-                Yw = (pery && Yw == A.ny - 1) ? 0 : Yw + 1;
-                Zw = (perz && Zw == A.nz - 1) ? 0 : Zw + 1;
+                Xw = (perx && Xw == P.nx - 1) ? 0 : Xw + 1;
+                Yw = (pery && Yw == P.ny - 1) ? 0 : Yw + 1;
+                Zw = (perz && Zw == P.nz - 1) ? 0 : Zw + 1;
             }
         }
         if (aborted) break;
@@ -834,44 +858,71 @@ constexpr int kNW = 4;  // wavefronts per tile: tile = 15 x 15 x 15 updated cell
 
 }  // namespace
 
-// Host-side plan of one call: tickets, per-band tile ranges, ring sizing.
+// Host-side plan of one context's call (tickets, per-band tile ranges, the
+// tile->ticket table) and the launch resources of the launches it leads.
 struct SystolicState {
     int nsteps = -1, K = -1;
-    int nt = 0, R = 0, D = 1, nbands = 0;
-    int4* d_tickets = nullptr;
-    int* d_tix = nullptr;
-    int* d_band = nullptr;
-    unsigned* d_progress = nullptr;
-    float* d_ring = nullptr;
-    unsigned* d_counter = nullptr;
-    size_t ring_bytes = 0;
+    int nt = 0, D = 1, nbands = 0;
     int per[3] = {0, 0, 0};  // periodic axes of the plan
     int L[3] = {0, 0, 0};    // ring tiles on periodic axes
     int group = 1;           // tiles of one ring group (must be co-resident)
+    std::vector<int4> tickets;  // (band, a, b, c) in dequeue order
+    std::vector<int> tix;       // per band, tile -> ticket
+    std::vector<int> band;      // per band: alo ahi blo bhi clo chi tix_off pad
+    std::vector<int> depth;     // per ticket: depth below the upwind corner (PEC axes)
+    uint64_t version = 0;       // bumped whenever the plan is rebuilt
+    // launch resources (used when this context leads a launch)
+    int4* d_tickets = nullptr;
+    int* d_tsim = nullptr;
+    int* d_tix = nullptr;
+    int* d_band = nullptr;
+    SimArgs* d_sims = nullptr;
+    unsigned* d_progress = nullptr;
+    float* d_ring = nullptr;
+    unsigned* d_counter = nullptr;
+    SimArgs* h_sims = nullptr;     // pinned staging of the per-simulation records
+    hipEvent_t sims_done = nullptr;  // the last upload from h_sims has completed
+    size_t cap_tickets = 0, cap_tsim = 0, cap_tix = 0, cap_band = 0, cap_sims = 0, cap_prog = 0;
+    int R = 0;
+    size_t ring_bytes = 0;
     int sm_count = 0;
+    // the uploaded launch plan: which contexts (and plan versions) it covers
+    std::vector<const fdtd_ctx*> up_ctx;
+    std::vector<uint64_t> up_ver;
+    int up_nt = 0, up_D = 1, up_group = 1;
+    std::vector<size_t> up_band_off;  // per simulation: offset of its band records
 };
 
 namespace {
 
-void free_plan(SystolicState* s)
+void free_launch(SystolicState* s)
 {
-    if (s->d_tickets) (void)hipFree(s->d_tickets);
-    if (s->d_tix) (void)hipFree(s->d_tix);
-    if (s->d_band) (void)hipFree(s->d_band);
-    if (s->d_progress) (void)hipFree(s->d_progress);
-    if (s->d_ring) (void)hipFree(s->d_ring);
-    if (s->d_counter) (void)hipFree(s->d_counter);
+    for (void* p : {(void*)s->d_tickets, (void*)s->d_tsim, (void*)s->d_tix, (void*)s->d_band,
+                    (void*)s->d_sims, (void*)s->d_progress, (void*)s->d_ring, (void*)s->d_counter})
+        if (p) (void)hipFree(p);
+    if (s->sims_done) (void)hipEventSynchronize(s->sims_done);
+    if (s->h_sims) (void)hipHostFree(s->h_sims);
+    if (s->sims_done) (void)hipEventDestroy(s->sims_done);
     s->d_tickets = nullptr;
+    s->d_tsim = nullptr;
     s->d_tix = nullptr;
     s->d_band = nullptr;
+    s->d_sims = nullptr;
     s->d_progress = nullptr;
     s->d_ring = nullptr;
     s->d_counter = nullptr;
-    s->nsteps = s->K = -1;
+    s->h_sims = nullptr;
+    s->sims_done = nullptr;
+    s->cap_tickets = s->cap_tsim = s->cap_tix = s->cap_band = s->cap_sims = s->cap_prog = 0;
+    s->R = 0;
+    s->ring_bytes = 0;
+    s->up_ctx.clear();
+    s->up_ver.clear();
 }
 
 int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// The plan of one context: tiles per band, tickets in topological order.
 int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 {
     constexpr int WY = 4 * kNW - 1;
@@ -902,10 +953,10 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
         }
         band[8 * bb + 6] = (int)ntot;
         ntot += cnt;
+        if (ntot > (size_t)1 << 30) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: too many tickets");
     }
-    if (ntot > (size_t)1 << 30) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: too many tickets");
     std::vector<int4> tickets(ntot);
-    std::vector<int> tix(ntot);
+    std::vector<int> tix(ntot), depth(ntot);
     size_t pos = 0;
     for (int bb = 0; bb < nb; ++bb) {
         const int* bi = &band[8 * bb];
@@ -921,7 +972,7 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
             if (!per[d]) ax[k++] = d;
         for (int d = 0; d < 3; ++d)
             if (per[d]) ax[k++] = d;
-        auto depth = [&](const int* i3) {
+        auto depth_of = [&](const int* i3) {
             int dd = 0;
             for (int d = 0; d < 3; ++d)
                 if (!per[d]) dd += n3[d] - 1 - i3[d];
@@ -932,55 +983,37 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
         int i3[3];
         for (i3[ax[0]] = 0; i3[ax[0]] < n3[ax[0]]; ++i3[ax[0]])
             for (i3[ax[1]] = 0; i3[ax[1]] < n3[ax[1]]; ++i3[ax[1]])
-                for (i3[ax[2]] = 0; i3[ax[2]] < n3[ax[2]]; ++i3[ax[2]]) count[depth(i3) + 1]++;
+                for (i3[ax[2]] = 0; i3[ax[2]] < n3[ax[2]]; ++i3[ax[2]]) count[depth_of(i3) + 1]++;
         for (int d = 1; d <= maxd + 1; ++d) count[d] += count[d - 1];
         for (i3[ax[0]] = 0; i3[ax[0]] < n3[ax[0]]; ++i3[ax[0]])
             for (i3[ax[1]] = 0; i3[ax[1]] < n3[ax[1]]; ++i3[ax[1]])
                 for (i3[ax[2]] = 0; i3[ax[2]] < n3[ax[2]]; ++i3[ax[2]]) {
-                    const size_t tix_i = pos + (size_t)count[depth(i3)]++;
+                    const int dd = depth_of(i3);
+                    const size_t tix_i = pos + (size_t)count[dd]++;
                     tickets[tix_i] = make_int4(bb, bi[0] + i3[0], bi[2] + i3[1], bi[4] + i3[2]);
+                    depth[tix_i] = dd;
                     tix[(size_t)bi[6] + ((size_t)i3[0] * n3[1] + i3[1]) * n3[2] + i3[2]] = (int)tix_i;
                 }
         pos += (size_t)n3[0] * n3[1] * n3[2];
     }
-    // largest distance (in tickets) from a face producer to its -z consumer
-    int R = 1;
-    for (size_t t = 0; t < ntot; ++t) {
-        const int4 tk = tickets[t];
-        const int* bi = &band[8 * tk.x];
-        const int cm = wrap(2, tk.w - 1);
-        if (cm < bi[4]) continue;
-        const int nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
-        const int j = tix[(size_t)bi[6] + ((size_t)(tk.y - bi[0]) * nbb + (tk.z - bi[2])) * nc + (cm - bi[4])];
-        R = std::max(R, (int)(j - (int)t + 1));
-    }
-    free_plan(s);
+    (void)wrap;
     s->nsteps = nsteps;
     s->K = K;
     s->nt = (int)ntot;
     s->nbands = nb;
-    s->D = R;
     for (int d = 0; d < 3; ++d) {
         s->per[d] = per[d];
         s->L[d] = L[d];
     }
     s->group = group;
-    hipError_t e;
-    const size_t nprog = ntot;  // one progress counter per ticket
-    if ((e = hipMalloc(&s->d_tickets, ntot * sizeof(int4))) != hipSuccess ||
-        (e = hipMalloc(&s->d_tix, ntot * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&s->d_band, band.size() * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc(&s->d_progress, nprog * sizeof(unsigned))) != hipSuccess ||
-        (e = hipMalloc(&s->d_counter, sizeof(unsigned))) != hipSuccess) {
-        free_plan(s);
-        return fail(ctx, FDTD_ENOMEM, std::string("systolic plan allocation: ") + hipGetErrorString(e));
-    }
-    if ((e = hipMemcpy(s->d_tickets, tickets.data(), ntot * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(s->d_tix, tix.data(), ntot * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(s->d_band, band.data(), band.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) {
-        free_plan(s);
-        return hip_fail(ctx, e, "systolic plan upload");
-    }
+    s->tickets.swap(tickets);
+    s->tix.swap(tix);
+    s->band.swap(band);
+    s->depth.swap(depth);
+    // unique across contexts, so a launch plan is never mistaken for the plan
+    // of another context that happens to reuse an address
+    static std::atomic<uint64_t> g_version{0};
+    s->version = ++g_version;
     return FDTD_OK;
 }
 
@@ -988,6 +1021,286 @@ int default_band(const fdtd_ctx* ctx, int64_t nsteps)
 {
     if (ctx->band_steps > 0) return (int)std::min<int64_t>(std::min(ctx->band_steps, kMaxBand), nsteps);
     return (int)std::min<int64_t>(32, nsteps);
+}
+
+template <typename T>
+int ensure_buffer(fdtd_ctx* ctx, T** p, size_t* cap, size_t n, const char* what)
+{
+    n = std::max<size_t>(n, 1);
+    if (*cap >= n && *p) return FDTD_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc(p, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FDTD_ENOMEM, std::string("systolic ") + what + ": " + hipGetErrorString(e));
+    }
+    *cap = n;
+    return FDTD_OK;
+}
+
+// Upload the launch plan of the contexts cs (one or several simulations) to
+// the lead state L.  Tickets are merged by (band, depth, simulation): every
+// wait of a ticket still targets an earlier ticket of its simulation or its
+// own ring group, and ring groups stay contiguous.
+int upload_plan(fdtd_ctx* lead, SystolicState* L, fdtd_ctx* const* cs, int n)
+{
+    bool same = (int)L->up_ctx.size() == n && L->d_tickets;
+    for (int i = 0; same && i < n; ++i) same = L->up_ctx[i] == cs[i] && L->up_ver[i] == cs[i]->sys->version;
+    if (same) return FDTD_OK;
+    L->up_ctx.clear();
+    L->up_ver.clear();
+    std::vector<size_t> base(n + 1, 0), tix_base(n + 1, 0), band_base(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        base[i + 1] = base[i] + cs[i]->sys->tickets.size();
+        tix_base[i + 1] = tix_base[i] + cs[i]->sys->tix.size();
+        band_base[i + 1] = band_base[i] + cs[i]->sys->band.size();
+    }
+    const size_t nt = base[n];
+    if (nt > (size_t)1 << 30 || tix_base[n] > (size_t)1 << 30)
+        return fail(lead, FDTD_EUNSUPPORTED, "systolic: too many tickets");
+    std::vector<int> sim(nt), order(nt);
+    for (int i = 0; i < n; ++i)
+        for (size_t q = base[i]; q < base[i + 1]; ++q) sim[q] = i;
+    for (size_t q = 0; q < nt; ++q) order[q] = (int)q;
+    if (n > 1)
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const SystolicState* sx = cs[sim[x]]->sys;
+            const SystolicState* sy = cs[sim[y]]->sys;
+            const size_t lx = x - base[sim[x]], ly = y - base[sim[y]];
+            if (sx->tickets[lx].x != sy->tickets[ly].x) return sx->tickets[lx].x < sy->tickets[ly].x;
+            if (sx->depth[lx] != sy->depth[ly]) return sx->depth[lx] < sy->depth[ly];
+            return sim[x] < sim[y];
+        });
+    std::vector<int> pos(nt);  // concatenated index -> merged position
+    for (size_t q = 0; q < nt; ++q) pos[order[q]] = (int)q;
+    std::vector<int4> tk(nt);
+    std::vector<int> tsim(nt), tix(tix_base[n]), band(band_base[n]);
+    for (int i = 0; i < n; ++i) {
+        const SystolicState* si = cs[i]->sys;
+        for (size_t q = 0; q < si->tickets.size(); ++q) {
+            tk[pos[base[i] + q]] = si->tickets[q];
+            tsim[pos[base[i] + q]] = i;
+        }
+        for (size_t q = 0; q < si->tix.size(); ++q) tix[tix_base[i] + q] = pos[base[i] + si->tix[q]];
+        for (size_t q = 0; q < si->band.size(); ++q)
+            band[band_base[i] + q] = si->band[q] + (q % 8 == 6 ? (int)tix_base[i] : 0);
+    }
+    // largest distance (in tickets) from a face producer to its -z consumer,
+    // and the largest ring group
+    int D = 1, group = 1;
+    for (int i = 0; i < n; ++i) group = std::max(group, cs[i]->sys->group);
+    for (size_t t = 0; t < nt; ++t) {
+        const SystolicState* si = cs[tsim[t]]->sys;
+        const int4 q = tk[t];
+        const int* bi = &band[band_base[tsim[t]] + 8 * (size_t)q.x];
+        int cm = q.w - 1;
+        if (si->per[2]) cm = ((cm % si->L[2]) + si->L[2]) % si->L[2];
+        if (cm < bi[4]) continue;
+        const int nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
+        const int j = tix[(size_t)bi[6] + ((size_t)(q.y - bi[0]) * nbb + (q.z - bi[2])) * nc + (cm - bi[4])];
+        D = std::max(D, j - (int)t + 1);
+    }
+    int rc;
+    if ((rc = ensure_buffer(lead, &L->d_tickets, &L->cap_tickets, nt, "tickets")) ||
+        (rc = ensure_buffer(lead, &L->d_tsim, &L->cap_tsim, nt, "ticket simulations")) ||
+        (rc = ensure_buffer(lead, &L->d_tix, &L->cap_tix, tix.size(), "tile table")) ||
+        (rc = ensure_buffer(lead, &L->d_band, &L->cap_band, band.size(), "band table")) ||
+        (rc = ensure_buffer(lead, &L->d_progress, &L->cap_prog, nt, "progress counters")))
+        return rc;
+    hipError_t e;
+    if ((e = hipMemcpy(L->d_tickets, tk.data(), nt * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(L->d_tsim, tsim.data(), nt * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(L->d_tix, tix.data(), tix.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(L->d_band, band.data(), band.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(lead, e, "systolic plan upload");
+    for (int i = 0; i < n; ++i) {
+        L->up_ctx.push_back(cs[i]);
+        L->up_ver.push_back(cs[i]->sys->version);
+    }
+    L->up_nt = (int)nt;
+    L->up_D = D;
+    L->up_group = group;
+    L->up_band_off.assign(band_base.begin(), band_base.end() - 1);
+    return FDTD_OK;
+}
+
+// One persistent launch advancing the contexts cs[0..n) by nsteps each, on
+// cs[0]'s stream (the others' streams wait for it and it for them).
+int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
+{
+    fdtd_ctx* lead = cs[0];
+    if (nsteps > (int64_t(1) << 24)) return fail(lead, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
+    const int K = default_band(lead, nsteps);
+    for (int i = 0; i < n; ++i) {
+        if (!cs[i]->sys) {
+            cs[i]->sys = new (std::nothrow) SystolicState();
+            if (!cs[i]->sys) return fail(lead, FDTD_ENOMEM, "systolic: host allocation failed");
+        }
+        SystolicState* si = cs[i]->sys;
+        if (si->nsteps != (int)nsteps || si->K != K) {
+            int rc = build_plan(cs[i], si, (int)nsteps, K);
+            if (rc) return rc == FDTD_OK ? rc : fail(lead, rc, cs[i]->err);
+        }
+    }
+    SystolicState* L = lead->sys;
+    int rc = upload_plan(lead, L, cs, n);
+    if (rc) return rc;
+    bool anyper = false;
+    for (int i = 0; i < n; ++i) anyper = anyper || cs[i]->sys->per[0] || cs[i]->sys->per[1] || cs[i]->sys->per[2];
+    // synchronisation variant: device-scope accesses (default) or cached
+    // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
+    const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
+    const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
+    auto kern = dev ? (anyper ? systolic_kernel<kNW, true, true> : systolic_kernel<kNW, true, false>)
+                    : (anyper ? systolic_kernel<kNW, false, true> : systolic_kernel<kNW, false, false>);
+    hipError_t e;
+    if (L->sm_count == 0) {
+        hipDeviceProp_t prop;
+        if ((e = hipGetDeviceProperties(&prop, lead->device)) != hipSuccess) return hip_fail(lead, e, "hipGetDeviceProperties");
+        L->sm_count = prop.multiProcessorCount;
+    }
+    int per_cu = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kNW, 0)) != hipSuccess)
+        return hip_fail(lead, e, "occupancy query");
+    // every workgroup of the persistent grid must be resident at once
+    const int capacity = std::max(1, per_cu) * L->sm_count;
+    const int nt = L->up_nt;
+    int grid = lead->workgroups > 0 ? std::min(lead->workgroups, capacity) : capacity;
+    grid = std::max(1, std::min(grid, nt));
+    // The tiles of a periodic ring wait on each other in a cycle that only
+    // time breaks, so a whole ring group must be resident together.
+    if (anyper && grid < L->up_group)
+        return fail(lead, FDTD_EUNSUPPORTED,
+                    "systolic: a periodic ring group of " + std::to_string(L->up_group) +
+                        " tiles needs as many resident workgroups (grid " + std::to_string(grid) + ")");
+    // Face ring: a slot is reused R tickets later, after its previous
+    // occupant and that occupant's consumer have finished.  R = D + 2 * grid
+    // keeps those two long finished by the time the slot comes round again,
+    // so the reuse wait never holds a workgroup in steady state; as grid is
+    // at least one ring group, both lie in groups before the reuser's own.
+    const int R = std::max(1, std::min(L->up_D + 2 * grid, nt));
+    const size_t ring_bytes = (size_t)R * K * 9 * (4 * kNW) * 16 * sizeof(float);
+    if (ring_bytes >= ((size_t)1 << 32)) return fail(lead, FDTD_EUNSUPPORTED, "systolic: face ring too large");
+    if (ring_bytes > L->ring_bytes || !L->d_ring) {
+        if (L->d_ring) (void)hipFree(L->d_ring);
+        L->d_ring = nullptr;
+        L->ring_bytes = 0;
+        if ((e = hipMalloc(&L->d_ring, ring_bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(lead, FDTD_ENOMEM, std::string("systolic face ring: ") + hipGetErrorString(e));
+        }
+        L->ring_bytes = ring_bytes;
+    }
+    L->R = R;
+    if (!L->d_counter && (e = hipMalloc(&L->d_counter, sizeof(unsigned))) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(lead, FDTD_ENOMEM, "systolic: ticket counter");
+    }
+    // per-simulation records, through pinned staging
+    if (!L->sims_done && (e = hipEventCreateWithFlags(&L->sims_done, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(lead, e, "hipEventCreate");
+    if ((e = hipEventSynchronize(L->sims_done)) != hipSuccess) return hip_fail(lead, e, "hipEventSynchronize");
+    if ((size_t)n > L->cap_sims) {
+        if (L->h_sims) (void)hipHostFree(L->h_sims);
+        if (L->d_sims) (void)hipFree(L->d_sims);
+        L->h_sims = nullptr;
+        L->d_sims = nullptr;
+        L->cap_sims = 0;
+        if ((e = hipHostMalloc(&L->h_sims, n * sizeof(SimArgs), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipMalloc(&L->d_sims, n * sizeof(SimArgs))) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(lead, FDTD_ENOMEM, "systolic: simulation records");
+        }
+        L->cap_sims = n;
+    }
+    for (int i = 0; i < n; ++i) {
+        const fdtd_ctx* c = cs[i];
+        SimArgs& P = L->h_sims[i];
+        memset(&P, 0, sizeof(P));
+        for (int q = 0; q < 6; ++q) P.f[q] = c->field[q];
+        for (int q = 0; q < 3; ++q) P.cE[q] = c->coef[q];
+        P.cH = c->cH;
+        P.nx = c->nx;
+        P.ny = c->ny;
+        P.nz = c->nz;
+        P.fbytes = (unsigned)((uint64_t)c->ncell * 4u);
+        P.band = L->d_band + L->up_band_off[i];
+        P.step0 = c->step_count;
+        P.src = c->dev_sources;
+        P.nsrc = c->dev_sources_n;
+        for (int d = 0; d < 3; ++d) {
+            const int nd = d == 0 ? c->nx : (d == 1 ? c->ny : c->nz);
+            const int W = d == 1 ? 4 * kNW - 1 : WX;
+            P.per[d] = c->sys->per[d];
+            P.L[d] = c->sys->L[d];
+            P.wr[d] = c->sys->per[d] ? nd - W * (c->sys->L[d] - 1) : W;
+        }
+    }
+    hipStream_t st = lead->stream;
+    // order the launch after each member's earlier work
+    std::vector<hipEvent_t> evs;
+    for (int i = 1; i < n; ++i) {
+        if (cs[i]->stream == st) continue;
+        hipEvent_t ev;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(lead, e, "hipEventCreate");
+        evs.push_back(ev);
+        if ((e = hipEventRecord(ev, cs[i]->stream)) != hipSuccess || (e = hipStreamWaitEvent(st, ev, 0)) != hipSuccess)
+            break;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(L->d_sims, L->h_sims, n * sizeof(SimArgs), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(L->sims_done, st);
+    for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+    evs.clear();
+    if (e != hipSuccess) return hip_fail(lead, e, "systolic launch set-up");
+    hipLaunchKernelGGL(fill_u32, dim3(256), dim3(256), 0, st, L->d_progress, 0u, (long long)nt);
+    hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, st, L->d_counter, 0u, 1LL);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(lead, e, "systolic reset");
+
+    SysArgs A;
+    memset(&A, 0, sizeof(A));
+    A.sims = L->d_sims;
+    A.tsim = n > 1 ? L->d_tsim : nullptr;
+    A.tickets = L->d_tickets;
+    A.nt = nt;
+    A.tix = L->d_tix;
+    A.progress = L->d_progress;
+    A.ring = L->d_ring;
+    A.ring_bytes = (unsigned)L->ring_bytes;
+    A.R = R;
+    A.K = K;
+    A.nsteps = (int)nsteps;
+    A.counter = L->d_counter;
+    A.error = lead->dev_error;
+    A.spin_limit = lead->spin_limit;
+    PendingTiming t;
+    timing_begin(lead, FDTD_KERNEL_SYSTOLIC, &t);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kNW), 0, st, A);
+    timing_end(lead, &t);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(lead, e, "launch(systolic)");
+    // members see a timeout of the shared launch in their own error word, and
+    // their streams continue after the launch
+    for (int i = 1; i < n && e == hipSuccess; ++i) {
+        e = hipMemcpyAsync(cs[i]->dev_error, lead->dev_error, sizeof(int), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && cs[i]->stream != st) {
+            hipEvent_t ev;
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) == hipSuccess) {
+                e = hipEventRecord(ev, st);
+                if (e == hipSuccess) e = hipStreamWaitEvent(cs[i]->stream, ev, 0);
+                (void)hipEventDestroy(ev);
+            }
+        }
+    }
+    if (e != hipSuccess) return hip_fail(lead, e, "systolic launch completion");
+    for (int i = 0; i < n; ++i) {
+        cs[i]->step_count += nsteps;
+        cs[i]->sys_grid = grid;
+        cs[i]->sys_ring_slots = R;
+        cs[i]->sys_band = K;
+        cs[i]->sys_tickets = nt;
+    }
+    return FDTD_OK;
 }
 
 }  // namespace
@@ -1009,110 +1322,11 @@ int systolic_supported(const fdtd_ctx* ctx, std::string* why)
 
 int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
 {
-    if (nsteps > (int64_t(1) << 24)) return fail(ctx, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
-    if (!ctx->sys) {
-        ctx->sys = new (std::nothrow) SystolicState();
-        if (!ctx->sys) return fail(ctx, FDTD_ENOMEM, "systolic: host allocation failed");
-    }
-    SystolicState* s = ctx->sys;
-    const int K = default_band(ctx, nsteps);
-    if (s->nsteps != (int)nsteps || s->K != K) {
-        int rc = build_plan(ctx, s, (int)nsteps, K);
-        if (rc) return rc;
-    }
-    // synchronisation variant: device-scope accesses (default) or cached
-    // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
-    const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
-    const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
-    const bool anyper = s->per[0] || s->per[1] || s->per[2];
-    auto kern = dev ? (anyper ? systolic_kernel<kNW, true, true> : systolic_kernel<kNW, true, false>)
-                    : (anyper ? systolic_kernel<kNW, false, true> : systolic_kernel<kNW, false, false>);
-    if (s->sm_count == 0) {
-        hipDeviceProp_t prop;
-        hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDeviceProperties");
-        s->sm_count = prop.multiProcessorCount;
-    }
-    int per_cu = 0;
-    hipError_t eo = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kNW, 0);
-    if (eo != hipSuccess) return hip_fail(ctx, eo, "occupancy query");
-    // every workgroup of the persistent grid must be resident at once
-    const int capacity = std::max(1, per_cu) * s->sm_count;
-    int grid = ctx->workgroups > 0 ? std::min(ctx->workgroups, capacity) : capacity;
-    grid = std::max(1, std::min(grid, s->nt));
-    // The tiles of a periodic ring wait on each other in a cycle that only
-    // time breaks, so a whole ring group must be resident together.
-    if (anyper && grid < s->group)
-        return fail(ctx, FDTD_EUNSUPPORTED,
-                    "systolic: a periodic ring group of " + std::to_string(s->group) +
-                        " tiles needs as many resident workgroups (grid " + std::to_string(grid) + ")");
-    // Face ring: a slot is reused R tickets later, after its previous
-    // occupant and that occupant's consumer have finished.  R = D + 2 * grid
-    // keeps those two long finished by the time the slot comes round again,
-    // so the reuse wait never holds a workgroup in steady state; as grid is
-    // at least one ring group, both lie in groups before the reuser's own.
-    const int R = std::max(1, std::min(s->D + 2 * grid, s->nt));
-    const size_t ring_bytes = (size_t)R * s->K * 9 * (4 * kNW) * 16 * sizeof(float);
-    if (ring_bytes >= ((size_t)1 << 32)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: face ring too large");
-    if (R != s->R || !s->d_ring) {
-        if (s->d_ring) (void)hipFree(s->d_ring);
-        s->d_ring = nullptr;
-        s->R = 0;
-        hipError_t e0 = hipMalloc(&s->d_ring, ring_bytes);
-        if (e0 != hipSuccess) return fail(ctx, FDTD_ENOMEM, std::string("systolic face ring: ") + hipGetErrorString(e0));
-        s->R = R;
-        s->ring_bytes = ring_bytes;
-    }
-    ctx->sys_grid = grid;
-    ctx->sys_ring_slots = R;
-    ctx->sys_band = s->K;
-    ctx->sys_tickets = s->nt;
-    hipLaunchKernelGGL(fill_u32, dim3(256), dim3(256), 0, ctx->stream, s->d_progress, 0u, (long long)s->nt);
-    hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, ctx->stream, s->d_counter, 0u, 1LL);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, "systolic reset");
-
-    SysArgs A;
-    memset(&A, 0, sizeof(A));
-    for (int c = 0; c < 6; ++c) A.f[c] = ctx->field[c];
-    for (int c = 0; c < 3; ++c) A.cE[c] = ctx->coef[c];
-    A.cH = ctx->cH;
-    A.nx = ctx->nx;
-    A.ny = ctx->ny;
-    A.nz = ctx->nz;
-    A.fbytes = (unsigned)((uint64_t)ctx->ncell * 4u);
-    A.tickets = s->d_tickets;
-    A.nt = s->nt;
-    A.tix = s->d_tix;
-    A.band = s->d_band;
-    A.progress = s->d_progress;
-    A.ring = s->d_ring;
-    A.ring_bytes = (unsigned)s->ring_bytes;
-    A.R = s->R;
-    A.K = s->K;
-    A.nsteps = (int)nsteps;
-    A.step0 = ctx->step_count;
-    A.src = ctx->dev_sources;
-    A.nsrc = ctx->dev_sources_n;
-    A.counter = s->d_counter;
-    A.error = ctx->dev_error;
-    A.spin_limit = ctx->spin_limit;
-    for (int d = 0; d < 3; ++d) {
-        const int n = d == 0 ? ctx->nx : (d == 1 ? ctx->ny : ctx->nz);
-        const int W = d == 1 ? 4 * kNW - 1 : WX;
-        A.per[d] = s->per[d];
-        A.L[d] = s->L[d];
-        A.wr[d] = s->per[d] ? n - W * (s->L[d] - 1) : W;
-    }
-    PendingTiming t;
-    timing_begin(ctx, FDTD_KERNEL_SYSTOLIC, &t);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kNW), 0, ctx->stream, A);
-    timing_end(ctx, &t);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, "launch(systolic)");
-    ctx->step_count += nsteps;
-    return FDTD_OK;
+    fdtd_ctx* one[1] = {ctx};
+    return launch(one, 1, nsteps);
 }
+
+int systolic_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps) { return launch(ctxs, n, nsteps); }
 
 void systolic_tile(int* wx, int* wy, int* wz)
 {
@@ -1124,7 +1338,7 @@ void systolic_tile(int* wx, int* wy, int* wz)
 void systolic_release(fdtd_ctx* ctx)
 {
     if (!ctx->sys) return;
-    free_plan(ctx->sys);
+    free_launch(ctx->sys);
     delete ctx->sys;
     ctx->sys = nullptr;
 }

@@ -35,7 +35,7 @@ SCHEMES = {"plain": SCHEME_PLAIN, "systolic": SCHEME_SYSTOLIC}
 
 # every symbol the header declares
 EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_fields",
-           "fdtd_add_source", "fdtd_step", "fdtd_read_fields", "fdtd_synchronize",
+           "fdtd_add_source", "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_synchronize",
            "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
            "fdtd_kernel_stats", "fdtd_get_info")
 
@@ -84,6 +84,7 @@ def load_library():
         "fdtd_add_source": ([vp, ctypes.c_int, i32, i32, i32, vp, i64, i64, ctypes.c_int],
                             ctypes.c_int),
         "fdtd_step": ([vp, i64], ctypes.c_int),
+        "fdtd_step_batch": ([ctypes.POINTER(vp), ctypes.c_int, i64], ctypes.c_int),
         "fdtd_read_fields": ([vp, u32, ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
         "fdtd_synchronize": ([vp], ctypes.c_int),
         "fdtd_current_step": ([vp], i64),
@@ -329,6 +330,19 @@ def design_objective(eps_design, problem: DesignProblem):
             return (gJ * g).to(eps_design.dtype)
 
     return _Objective.apply(eps_design)
+
+
+def step_batch(sims: Sequence["Simulation"], nsteps: int):
+    """Advance several Simulation objects by nsteps each in one persistent
+    systolic launch (fdtd_step_batch)."""
+    sims = list(sims)
+    if not sims:
+        raise ValueError("step_batch needs at least one simulation")
+    lib = sims[0]._lib
+    arr = (ctypes.c_void_p * len(sims))(*[s._h.value for s in sims])
+    rc = lib.fdtd_step_batch(arr, len(sims), int(nsteps))
+    if rc < 0:
+        raise FdtdError(rc, lib.fdtd_last_error(sims[0]._h).decode())
 
 
 def run_workload(w, scheme: str = "plain", nsteps: Optional[int] = None, device: int = 0,

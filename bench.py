@@ -164,8 +164,11 @@ def sweep(args):
         for scheme in args.schemes.split(","):
             steps = max(128, int(0.3 * 5e10 / w.cells) // 32 * 32)
             steps = min(steps, 20000)
+            opts = {}
+            if scheme == "systolic" and args.band:
+                opts[fdtd.OPT_BAND_STEPS] = args.band
             try:
-                t, _ = run_scheme(w, scheme, steps, 32)
+                t, _ = run_scheme(w, scheme, steps, 32, opts)
             except fdtd.FdtdError as e:
                 row[scheme] = None
                 log("n=%d %s unavailable: %s" % (n, scheme, e))
@@ -174,6 +177,64 @@ def sweep(args):
         if row.get("systolic") and row.get("plain"):
             row["systolic_over_plain"] = row["systolic"]["cups"] / row["plain"]["cups"]
         print(json.dumps(row), flush=True)
+
+
+def batch_bench(nsims: int, steps: int, dims=(64, 192)):
+    """The batched sweep: nsims uneven PEC grids advanced by `steps` steps.
+    Three ways, each after a warm-up band, with inputs resident: one
+    fdtd_step_batch launch for all grids; one systolic launch per grid (queued
+    back to back on one stream); the plain scheme per grid.  Value = aggregate
+    cell updates/s of the batched launch."""
+    import torch
+    from paper_2502_20610_amd import fdtd
+    from paper_2502_20610_amd import workloads as wl
+    ws = wl.c4_batch(nsims, steps, dims=dims)
+    cells = sum(w.cells for w in ws)
+    stream = torch.cuda.current_stream()
+    dev = torch.device("cuda:0")
+
+    def make(scheme):
+        sims = []
+        for w in ws:
+            sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, stream=stream.cuda_stream)
+            sim.set_materials(torch.from_numpy(w.eps).to(dev))
+            for s in w.sources:
+                sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+            sims.append(sim)
+        return sims
+
+    res = {}
+    for mode in ("batched", "per_grid", "plain"):
+        sims = make("plain" if mode == "plain" else "systolic")
+        try:
+            def run(n):
+                if mode == "batched":
+                    fdtd.step_batch(sims, n)
+                else:
+                    for sim in sims:
+                        sim.step(n)
+            # warm-up: the same call once (it also builds and uploads the plans,
+            # which the timed call then reuses)
+            run(steps if mode != "plain" else 32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run(steps)
+            torch.cuda.synchronize()
+            res[mode] = time.perf_counter() - t0
+            log("batch %s: %d grids x %d steps in %.3f s" % (mode, nsims, steps, res[mode]))
+        finally:
+            for sim in sims:
+                sim.close()
+    out = {"metric": "aggregate cell updates/s, %d uneven grids in one launch" % nsims,
+           "value": cells * steps / res["batched"], "unit": "cell updates/s",
+           "higher_is_better": True, "n_gpus": 1, "steps": steps, "cells": cells,
+           "per_grid_launches_cups": cells * steps / res["per_grid"],
+           "plain_cups": cells * steps / res["plain"],
+           "batched_over_per_grid": res["per_grid"] / res["batched"],
+           "batched_over_plain": res["plain"] / res["batched"],
+           "config": {"workload": "c4_batch", "grids": nsims, "dims": list(dims),
+                      "shapes": [list(w.shape) for w in ws]}}
+    print(json.dumps(out), flush=True)
 
 
 def adjoint_bench():
@@ -226,6 +287,12 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the headline line, time the gradient of the 256x256x128 "
                          "inverse-design setup (forward, checkpointed recompute, reverse sweep)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the headline line, advance this many uneven grids (the "
+                         "batched sweep, 64 in its full form) in one launch, against one launch "
+                         "per grid and the plain scheme")
+    ap.add_argument("--batch-dims", default="64,192",
+                    help="lo,hi: per-axis sizes of the batched grids (multiples of 16)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling HBM counters")
@@ -252,6 +319,10 @@ def main():
         return
     if args.adjoint:
         adjoint_bench()
+        return
+    if args.batch:
+        batch_bench(args.batch, args.steps if args.steps != 128 else 2000,
+                    tuple(int(x) for x in args.batch_dims.split(",")))
         return
     log("building workload %s" % args.workload)
     w = make_workload(args.workload)

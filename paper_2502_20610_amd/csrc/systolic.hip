@@ -76,6 +76,7 @@ struct SimArgs {
     int per[3];  // periodic axis: tiles form a ring, positions wrap
     int L[3];    // tiles of the ring on a periodic axis
     int wr[3];   // updated cells of the ring's last (ragged) tile
+    int K;       // steps per band of this simulation
 };
 
 struct SysArgs {
@@ -87,7 +88,7 @@ struct SysArgs {
     unsigned* progress;  // per ticket: last completed half-step level
     float* ring;
     unsigned ring_bytes;
-    int R, K;
+    int R, Kmax;   // ring slots; the longest band (the ring's slot stride)
     int nsteps;
     unsigned* counter;
     int* error;
@@ -336,10 +337,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 
         const int4 tk = A.tickets[t];
         const int bnd = tk.x, a = tk.y, b = tk.z, c = tk.w;
-        const int t0 = bnd * A.K;
-        const int t1 = min(A.nsteps, t0 + A.K);
+        const int t0_ = bnd;  // band index; its steps follow once the record is read
         // this ticket's simulation: arrays, sizes, sources, boundaries
         const SimArgs P = load_sim(A.sims + (A.tsim ? __builtin_amdgcn_readfirstlane(A.tsim[t]) : 0));
+        const int t0 = t0_ * P.K;
+        const int t1 = min(A.nsteps, t0 + P.K);
         const int* bi = P.band + 8 * bnd;
         __amdgpu_buffer_rsrc_t rf[6], rc[3];
 #pragma unroll
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const int4 pk = A.tickets[t - A.R];
             const SimArgs PP = load_sim(A.sims + (A.tsim ? __builtin_amdgcn_readfirstlane(A.tsim[t - A.R]) : 0));
             const int* pb = PP.band + 8 * pk.x;
-            const unsigned pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * A.K);
+            const unsigned pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * PP.K);
             int wl[8];
             wl[0] = t - A.R;
             int nw = 1;
@@ -527,8 +529,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const bool okz1 = axis_pos<PER>(Uz, Zw, P.nz, perz, dz1, z1);
             const bool okyz1 = oky1 && okz1;
             const unsigned yz1 = (unsigned)y1 * (unsigned)P.nz + (unsigned)z1;
-            const unsigned ring_base = ((unsigned)slot * (unsigned)A.K + (unsigned)ls) * ring_step;
-            const unsigned ring_zup = ((unsigned)slot_zup * (unsigned)A.K + (unsigned)ls) * ring_step;
+            const unsigned ring_base = ((unsigned)slot * (unsigned)A.Kmax + (unsigned)ls) * ring_step;
+            const unsigned ring_zup = ((unsigned)slot_zup * (unsigned)A.Kmax + (unsigned)ls) * ring_step;
             // the forward y and z planes of the next box
             int yf, zf, zl;
             const bool oky_f = axis_pos<PER>(Uy, Yw, P.ny, pery, wyr, yf);
@@ -1017,10 +1019,47 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     return FDTD_OK;
 }
 
-int default_band(const fdtd_ctx* ctx, int64_t nsteps)
+// Band length (steps per residency) for a launch over the contexts cs.  An
+// explicit option wins; otherwise a cost model picks it.  Per cell update, a
+// band of K steps costs the tile slots that cover the band's skewed
+// space-time region, prod_d (n_d + K + 30) / n_d on PEC axes (15 L_d / n_d
+// on periodic rings), times (1 + beta / K) for the band's start and end (box
+// load, state write-back, the pipeline refill behind the band barrier of each
+// tile); beta = 10 steps was fitted to the measured rate against K on 512^3
+// and predicts 64^3..1024x1024x512 within a few percent.  Over several grids
+// the cell-weighted mean is minimised (a batched launch asks per grid).
+int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
-    if (ctx->band_steps > 0) return (int)std::min<int64_t>(std::min(ctx->band_steps, kMaxBand), nsteps);
-    return (int)std::min<int64_t>(32, nsteps);
+    if (cs[0]->band_steps > 0) return (int)std::min<int64_t>(std::min(cs[0]->band_steps, kMaxBand), nsteps);
+    constexpr double kBeta = 10.0;
+    static const int cand[] = {8, 12, 16, 24, 32, 48, 64};
+    int best = (int)std::min<int64_t>(nsteps, 32);
+    double best_cost = 1e300;
+    for (int K0 : cand) {
+        const int K = (int)std::min<int64_t>(K0, nsteps);
+        double cost = 0.0, cells = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const fdtd_ctx* c = cs[i];
+            const int nd[3] = {c->nx, c->ny, c->nz};
+            const int W[3] = {WX, 4 * kNW - 1, WZ};
+            double f = 1.0 + kBeta / K;
+            for (int d = 0; d < 3; ++d) {
+                const double slots = c->cfg.bc[d] == FDTD_BC_PERIODIC
+                                         ? (double)W[d] * ((nd[d] + W[d] - 1) / W[d])
+                                         : (double)nd[d] + K + 30.0;
+                f *= slots / nd[d];
+            }
+            cost += f * (double)c->ncell;
+            cells += (double)c->ncell;
+        }
+        cost /= cells;
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
+            best = K;
+        }
+        if (K0 >= nsteps) break;
+    }
+    return best;
 }
 
 template <typename T>
@@ -1041,9 +1080,13 @@ int ensure_buffer(fdtd_ctx* ctx, T** p, size_t* cap, size_t n, const char* what)
 }
 
 // Upload the launch plan of the contexts cs (one or several simulations) to
-// the lead state L.  Tickets are merged by (band, depth, simulation): every
-// wait of a ticket still targets an earlier ticket of its simulation or its
-// own ring group, and ring groups stay contiguous.
+// the lead state L.  Tickets are merged by (band start step, simulation), each
+// simulation's tickets keeping their own order: every wait of a ticket still
+// targets an earlier ticket of its simulation or its own ring group, ring
+// groups stay contiguous, and a producer stays close to its consumers (the
+// face ring stays as shallow as for the simulation alone), while the next
+// simulation's tickets fill the workgroups a simulation's band tail leaves
+// idle.
 int upload_plan(fdtd_ctx* lead, SystolicState* L, fdtd_ctx* const* cs, int n)
 {
     bool same = (int)L->up_ctx.size() == n && L->d_tickets;
@@ -1069,8 +1112,9 @@ int upload_plan(fdtd_ctx* lead, SystolicState* L, fdtd_ctx* const* cs, int n)
             const SystolicState* sx = cs[sim[x]]->sys;
             const SystolicState* sy = cs[sim[y]]->sys;
             const size_t lx = x - base[sim[x]], ly = y - base[sim[y]];
-            if (sx->tickets[lx].x != sy->tickets[ly].x) return sx->tickets[lx].x < sy->tickets[ly].x;
-            if (sx->depth[lx] != sy->depth[ly]) return sx->depth[lx] < sy->depth[ly];
+            // band start step (simulations may have different band lengths)
+            const long long bx = (long long)sx->tickets[lx].x * sx->K, by = (long long)sy->tickets[ly].x * sy->K;
+            if (bx != by) return bx < by;
             return sim[x] < sim[y];
         });
     std::vector<int> pos(nt);  // concatenated index -> merged position
@@ -1132,13 +1176,17 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
     fdtd_ctx* lead = cs[0];
     if (nsteps > (int64_t(1) << 24)) return fail(lead, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
-    const int K = default_band(lead, nsteps);
+    // band length per simulation: the lead's option for all, else each
+    // simulation's own choice of the cost model
+    int Kmax = 1;
     for (int i = 0; i < n; ++i) {
         if (!cs[i]->sys) {
             cs[i]->sys = new (std::nothrow) SystolicState();
             if (!cs[i]->sys) return fail(lead, FDTD_ENOMEM, "systolic: host allocation failed");
         }
         SystolicState* si = cs[i]->sys;
+        const int K = lead->band_steps > 0 ? default_band(cs, 1, nsteps) : default_band(cs + i, 1, nsteps);
+        Kmax = std::max(Kmax, K);
         if (si->nsteps != (int)nsteps || si->K != K) {
             int rc = build_plan(cs[i], si, (int)nsteps, K);
             if (rc) return rc == FDTD_OK ? rc : fail(lead, rc, cs[i]->err);
@@ -1181,7 +1229,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     // so the reuse wait never holds a workgroup in steady state; as grid is
     // at least one ring group, both lie in groups before the reuser's own.
     const int R = std::max(1, std::min(L->up_D + 2 * grid, nt));
-    const size_t ring_bytes = (size_t)R * K * 9 * (4 * kNW) * 16 * sizeof(float);
+    const size_t ring_bytes = (size_t)R * Kmax * 9 * (4 * kNW) * 16 * sizeof(float);
     if (ring_bytes >= ((size_t)1 << 32)) return fail(lead, FDTD_EUNSUPPORTED, "systolic: face ring too large");
     if (ring_bytes > L->ring_bytes || !L->d_ring) {
         if (L->d_ring) (void)hipFree(L->d_ring);
@@ -1237,6 +1285,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
             P.L[d] = c->sys->L[d];
             P.wr[d] = c->sys->per[d] ? nd - W * (c->sys->L[d] - 1) : W;
         }
+        P.K = c->sys->K;
     }
     hipStream_t st = lead->stream;
     // order the launch after each member's earlier work
@@ -1269,7 +1318,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     A.ring = L->d_ring;
     A.ring_bytes = (unsigned)L->ring_bytes;
     A.R = R;
-    A.K = K;
+    A.Kmax = Kmax;
     A.nsteps = (int)nsteps;
     A.counter = L->d_counter;
     A.error = lead->dev_error;
@@ -1297,7 +1346,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
         cs[i]->step_count += nsteps;
         cs[i]->sys_grid = grid;
         cs[i]->sys_ring_slots = R;
-        cs[i]->sys_band = K;
+        cs[i]->sys_band = cs[i]->sys->K;
         cs[i]->sys_tickets = nt;
     }
     return FDTD_OK;

@@ -215,6 +215,23 @@ def c5_adjoint(nsteps: int = 4000, seed: int = 5):
     return w, args
 
 
+def c4_batch(nsims: int = 64, nsteps: int = 2000, seed: int = 4, dims=(64, 192)):
+    """Batched sweep: nsims PEC grids, each axis drawn from {64, 80, ..., 192}
+    (multiples of 16 in ``dims``);
+    per grid a background of eps 1 with 16 boxes of eps ~ U[1, 12.25] (sides 4
+    to n/2) and an Ez dipole at the centre (seed + grid index)."""
+    out = []
+    for q in range(nsims):
+        rng = np.random.default_rng(seed + q)
+        shape = tuple(int(rng.choice(np.arange(dims[0], dims[1] + 1, 16))) for _ in range(3))
+        eps = paint_boxes(shape, 16, 4, tuple(max(4, s // 2) for s in shape), 1.0,
+                          lambda r: float(r.uniform(1.0, 12.25)), rng)
+        wave = gaussian_sine(nsteps, 0.5, eps_bg=1.0)
+        out.append(Workload("c4_member_%d_%dx%dx%d" % ((q,) + shape), shape, (PEC, PEC, PEC), 0.5,
+                            1.0, nsteps, eps, None, [dipole(EZ, *(s // 2 for s in shape), wave)]))
+    return out
+
+
 def bare_bones(n, seed: int = 6, nsteps: int = 100, shape=None) -> Workload:
     """Fig. 1-style sweep point: C2-style boxes, fields U(-1, 1), PEC walls, no
     sources (the paper's 'bare-bones' setup has none)."""

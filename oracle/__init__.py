@@ -12,8 +12,10 @@ marshals numpy arrays through ctypes.
 Functions
 ---------
 coeff_E(eps, bc, dt, dx)           -> (cEx, cEy, cEz) in float64
+coeff_lossy(eps, sigma, bc, dt, dx) -> ((caX, caY, caZ), (cbX, cbY, cbZ)) in float64
 step(cE, cH, fields, nsteps, ...)  -> advances six fields in place (f64 or f32)
-run(fields, eps, bc, dt, dx, ...)  -> convenience: coefficients + steps
+step_lossy(ca, cb, cH, fields, ...) -> the same with conductivity
+run(fields, eps, bc, dt, dx, ...)  -> convenience: coefficients + steps (sigma optional)
 
 Field tuples are always ordered (Ex, Ey, Ez, Hx, Hy, Hz); arrays are C-ordered
 ``[nx, ny, nz]`` (z fastest).  ``bc[a]`` is 0 for PEC and 1 for periodic.
@@ -69,6 +71,16 @@ def _load():
             f.argtypes = [ctypes.c_int] * 3 + [P, P, P, S] + [P] * 6 + [
                 ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Source), ctypes.c_int]
             f.restype = None
+        lib.oracle_coeff_lossy.argtypes = [ctypes.c_int] * 3 + [i32p, ctypes.c_double,
+                                                                 ctypes.c_double, ctypes.c_int, fp,
+                                                                 fp, dp, dp]
+        lib.oracle_coeff_lossy.restype = None
+        for name, P, S in (("oracle_step_lossy_f64", dp, ctypes.c_double),
+                           ("oracle_step_lossy_f32", fp, ctypes.c_float)):
+            f = getattr(lib, name)
+            f.argtypes = [ctypes.c_int] * 3 + [P] * 6 + [S] + [P] * 6 + [
+                ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Source), ctypes.c_int]
+            f.restype = None
         lib.oracle_round_f32.argtypes = [dp, fp, ctypes.c_int64]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -105,6 +117,26 @@ def coeff_E(eps: Sequence[np.ndarray], bc: Sequence[int], dt: float, dx: float):
                            _ptr(o, ctypes.c_double))
         out.append(o)
     return tuple(out)
+
+
+def coeff_lossy(eps: Sequence[np.ndarray], sigma: Sequence[np.ndarray], bc: Sequence[int],
+                dt: float, dx: float):
+    """(ca, cb) per component in float64 for conductivity sigma: see yee_oracle.c."""
+    lib = _load()
+    nx, ny, nz = eps[0].shape
+    bcarr = (ctypes.c_int32 * 3)(*[int(b) for b in bc])
+    ca, cb = [], []
+    for c in range(3):
+        e = np.ascontiguousarray(eps[c], dtype=np.float32)
+        g = np.ascontiguousarray(sigma[c], dtype=np.float32)
+        a = np.empty((nx, ny, nz), dtype=np.float64)
+        b = np.empty((nx, ny, nz), dtype=np.float64)
+        lib.oracle_coeff_lossy(nx, ny, nz, bcarr, float(dt), float(dx), c,
+                               _ptr(e, ctypes.c_float), _ptr(g, ctypes.c_float),
+                               _ptr(a, ctypes.c_double), _ptr(b, ctypes.c_double))
+        ca.append(a)
+        cb.append(b)
+    return tuple(ca), tuple(cb)
 
 
 def round_f32(a: np.ndarray) -> np.ndarray:
@@ -154,17 +186,48 @@ def step(cE, cH, fields, nsteps: int, step0: int = 0, sources=(), dtype=np.float
     return fields
 
 
+def step_lossy(ca, cb, cH, fields, nsteps: int, step0: int = 0, sources=(), dtype=np.float64):
+    """Like :func:`step`, with the conductive E half-step E = (ca E + cb d1) - cb d2."""
+    lib = _load()
+    dtype = np.dtype(dtype)
+    if dtype == np.float64:
+        fn, ct = lib.oracle_step_lossy_f64, ctypes.c_double
+    elif dtype == np.float32:
+        fn, ct = lib.oracle_step_lossy_f32, ctypes.c_float
+    else:
+        raise TypeError("oracle supports float64 and float32 only")
+    nx, ny, nz = fields[0].shape
+    for a in list(ca) + list(cb) + list(fields):
+        if a.dtype != dtype or a.shape != (nx, ny, nz) or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("coefficient and field arrays must be C-contiguous %s of shape %s"
+                             % (dtype, (nx, ny, nz)))
+    src, keep = _sources(list(sources))
+    fn(nx, ny, nz, *[_ptr(c, ct) for c in ca], *[_ptr(c, ct) for c in cb], ct(cH),
+       *[_ptr(f, ct) for f in fields], int(nsteps), int(step0), src, len(sources))
+    del keep
+    return fields
+
+
 def run(fields, eps, bc, dt: float, dx: float, nsteps: int, step0: int = 0, sources=(),
-        dtype=np.float64):
-    """Copy ``fields``, build the coefficients from ``eps`` and run ``nsteps``.
+        dtype=np.float64, sigma=None):
+    """Copy ``fields``, build the coefficients from ``eps`` (and the
+    conductivity ``sigma``, three arrays, if given) and run ``nsteps``.
 
     The FP32 variant rounds the FP64 coefficients (and cH = dt/dx) to float,
     as the structural fields of the GPU path are FP32.
     """
-    cE = coeff_E(eps, bc, dt, dx)
     cH = float(dt) / float(dx)
-    if np.dtype(dtype) == np.float32:
-        cE = tuple(round_f32(c) for c in cE)
+    f32 = np.dtype(dtype) == np.float32
+    if f32:
         cH = np.float32(cH)
     out = tuple(np.array(f, dtype=dtype, order="C", copy=True) for f in fields)
+    if sigma is not None:
+        ca, cb = coeff_lossy(eps, sigma, bc, dt, dx)
+        if f32:
+            ca = tuple(round_f32(c) for c in ca)
+            cb = tuple(round_f32(c) for c in cb)
+        return step_lossy(ca, cb, cH, out, nsteps, step0=step0, sources=sources, dtype=dtype)
+    cE = coeff_E(eps, bc, dt, dx)
+    if f32:
+        cE = tuple(round_f32(c) for c in cE)
     return step(cE, cH, out, nsteps, step0=step0, sources=sources, dtype=dtype)

@@ -78,6 +78,31 @@ void oracle_coeff_E(int nx, int ny, int nz, const int32_t bc[3], double dt, doub
             }
 }
 
+/* H half-step (shared by the lossless and lossy steps): reads the new E at
+ * the forward neighbours. */
+#define H_HALF_STEP(T)                                                                    \
+        _Pragma("omp parallel for schedule(static)")                                      \
+        for (int i = 0; i < nx; ++i) {                                                    \
+            int ip = (i == nx - 1) ? 0 : i + 1;                                           \
+            for (int j = 0; j < ny; ++j) {                                                \
+                int jp = (j == ny - 1) ? 0 : j + 1;                                       \
+                for (int k = 0; k < nz; ++k) {                                            \
+                    int kp = (k == nz - 1) ? 0 : k + 1;                                   \
+                    size_t p = IDX(i, j, k);                                              \
+                    T a, b;                                                               \
+                    a = Hx[p] - cH * (Ez[IDX(i, jp, k)] - Ez[p]);                         \
+                    b = cH * (Ey[IDX(i, j, kp)] - Ey[p]);                                 \
+                    Hx[p] = a + b;                                                        \
+                    a = Hy[p] - cH * (Ex[IDX(i, j, kp)] - Ex[p]);                         \
+                    b = cH * (Ez[IDX(ip, j, k)] - Ez[p]);                                 \
+                    Hy[p] = a + b;                                                        \
+                    a = Hz[p] - cH * (Ey[IDX(ip, j, k)] - Ey[p]);                         \
+                    b = cH * (Ex[IDX(i, jp, k)] - Ex[p]);                                 \
+                    Hz[p] = a + b;                                                        \
+                }                                                                         \
+            }                                                                             \
+        }
+
 #define DEFINE_STEP(T, NAME)                                                              \
 void NAME(int nx, int ny, int nz, const T* cEx, const T* cEy, const T* cEz, T cH,         \
           T* Ex, T* Ey, T* Ez, T* Hx, T* Hy, T* Hz, int64_t nsteps, int64_t step0,         \
@@ -114,33 +139,87 @@ void NAME(int nx, int ny, int nz, const T* cEx, const T* cEy, const T* cEz, T cH
             size_t p = IDX(src[q].i, src[q].j, src[q].k);                                 \
             f[p] = f[p] + (T)src[q].w[m];                                                 \
         }                                                                                 \
-        /* H half-step: reads the new E at the forward neighbours */                      \
-        _Pragma("omp parallel for schedule(static)")                                      \
-        for (int i = 0; i < nx; ++i) {                                                    \
-            int ip = (i == nx - 1) ? 0 : i + 1;                                           \
-            for (int j = 0; j < ny; ++j) {                                                \
-                int jp = (j == ny - 1) ? 0 : j + 1;                                       \
-                for (int k = 0; k < nz; ++k) {                                            \
-                    int kp = (k == nz - 1) ? 0 : k + 1;                                   \
-                    size_t p = IDX(i, j, k);                                              \
-                    T a, b;                                                               \
-                    a = Hx[p] - cH * (Ez[IDX(i, jp, k)] - Ez[p]);                         \
-                    b = cH * (Ey[IDX(i, j, kp)] - Ey[p]);                                 \
-                    Hx[p] = a + b;                                                        \
-                    a = Hy[p] - cH * (Ex[IDX(i, j, kp)] - Ex[p]);                         \
-                    b = cH * (Ez[IDX(ip, j, k)] - Ez[p]);                                 \
-                    Hy[p] = a + b;                                                        \
-                    a = Hz[p] - cH * (Ey[IDX(ip, j, k)] - Ey[p]);                         \
-                    b = cH * (Ex[IDX(i, jp, k)] - Ex[p]);                                 \
-                    Hz[p] = a + b;                                                        \
-                }                                                                         \
-            }                                                                             \
-        }                                                                                 \
+        H_HALF_STEP(T)                                                                    \
     }                                                                                     \
 }
 
 DEFINE_STEP(double, oracle_step_f64)
 DEFINE_STEP(float, oracle_step_f32)
+
+/*
+ * Lossy materials (the conductivity "structural fields" of Section 4).
+ * With conductivity sigma, Ampere's law eps dE/dt + sigma E = curl H is
+ * discretised semi-implicitly (sigma E at the half-step mean of the old and
+ * new E), which gives, per component c,
+ *
+ *   E = (ca*E + cb*(d1)) - cb*(d2),
+ *   ca = (1 - h) / (1 + h),  cb = (dt / (eps dx)) / (1 + h),  h = sigma dt / (2 eps),
+ *
+ * with d1, d2 the same differences as in the lossless step.  With sigma = 0,
+ * ca = 1 and cb = dt/(eps dx) exactly, and 1*E = E, so this step equals the
+ * lossless one bit for bit.  On PEC-tangential index-0 entries ca = 1 and
+ * cb = 0 (the entry stays +0).  The H half-step is unchanged.
+ */
+void oracle_coeff_lossy(int nx, int ny, int nz, const int32_t bc[3], double dt, double dx,
+                        int comp, const float* eps, const float* sigma, double* ca, double* cb)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < nz; ++k) {
+                size_t p = IDX(i, j, k);
+                double e = (double)eps[p];
+                double h = (double)sigma[p] * dt / (2.0 * e);
+                double a = (1.0 - h) / (1.0 + h);
+                double b = (dt / (e * dx)) / (1.0 + h);
+                int coord[3] = {i, j, k};
+                for (int d = 0; d < 3; ++d)
+                    if (d != comp && bc[d] == 0 && coord[d] == 0) {
+                        a = 1.0;
+                        b = 0.0;
+                    }
+                ca[p] = a;
+                cb[p] = b;
+            }
+}
+
+#define DEFINE_STEP_LOSSY(T, NAME)                                                        \
+void NAME(int nx, int ny, int nz, const T* cax, const T* cay, const T* caz, const T* cbx, \
+          const T* cby, const T* cbz, T cH, T* Ex, T* Ey, T* Ez, T* Hx, T* Hy, T* Hz,     \
+          int64_t nsteps, int64_t step0, const oracle_source* src, int nsrc)             \
+{                                                                                         \
+    for (int64_t s = step0; s < step0 + nsteps; ++s) {                                    \
+        _Pragma("omp parallel for schedule(static)")                                      \
+        for (int i = 0; i < nx; ++i) {                                                    \
+            int im = (i == 0) ? nx - 1 : i - 1;                                           \
+            for (int j = 0; j < ny; ++j) {                                                \
+                int jm = (j == 0) ? ny - 1 : j - 1;                                       \
+                for (int k = 0; k < nz; ++k) {                                            \
+                    int km = (k == 0) ? nz - 1 : k - 1;                                   \
+                    size_t p = IDX(i, j, k);                                              \
+                    T a, b;                                                               \
+                    a = cax[p] * Ex[p] + cbx[p] * (Hz[p] - Hz[IDX(i, jm, k)]);            \
+                    b = cbx[p] * (Hy[p] - Hy[IDX(i, j, km)]);                             \
+                    Ex[p] = a - b;                                                        \
+                    a = cay[p] * Ey[p] + cby[p] * (Hx[p] - Hx[IDX(i, j, km)]);            \
+                    b = cby[p] * (Hz[p] - Hz[IDX(im, j, k)]);                             \
+                    Ey[p] = a - b;                                                        \
+                    a = caz[p] * Ez[p] + cbz[p] * (Hy[p] - Hy[IDX(im, j, k)]);            \
+                    b = cbz[p] * (Hx[p] - Hx[IDX(i, jm, k)]);                             \
+                    Ez[p] = a - b;                                                        \
+                }                                                                         \
+            }                                                                             \
+        }                                                                                 \
+        for (int q = 0; q < nsrc; ++q) {                                                  \
+            int64_t m = s - src[q].first_step;                                            \
+            if (m < 0 || m >= src[q].len) continue;                                       \
+            T* f = src[q].comp == 0 ? Ex : (src[q].comp == 1 ? Ey : Ez);                  \
+            size_t p = IDX(src[q].i, src[q].j, src[q].k);                                 \
+            f[p] = f[p] + (T)src[q].w[m];                                                 \
+        }                                                                                 \
+        H_HALF_STEP(T)                                                                    \
+    }                                                                                     \
+}
 
 /* Round an FP64 coefficient array to FP32 (the FP32 oracle's structural field). */
 void oracle_round_f32(const double* in, float* out, int64_t n)
@@ -158,3 +237,6 @@ void oracle_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 int oracle_num_threads(void) { return 1; }
 void oracle_set_threads(int n) { (void)n; }
 #endif
+
+DEFINE_STEP_LOSSY(double, oracle_step_lossy_f64)
+DEFINE_STEP_LOSSY(float, oracle_step_lossy_f32)

@@ -108,6 +108,21 @@ int fdtd_destroy(fdtd_ctx* ctx);
 int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
                        const float* eps_z, int where);
 
+/* Set permittivity and conductivity (the permittivity and conductivity
+ * structural fields of Section 4): six arrays of nx*ny*nz floats, eps >= 1,
+ * sigma >= 0, all finite (else FDTD_EINVAL as for fdtd_set_materials).  The
+ * E half-step becomes the semi-implicit conductive update
+ *     E_c = (ca_c * E_c + cb_c * d1) - cb_c * d2,
+ *     h = sigma dt / (2 eps), ca = (1 - h) / (1 + h), cb = (dt / (eps dx)) / (1 + h),
+ * all in IEEE double, rounded to FP32 (ca = 1, cb = 0 on PEC-tangential
+ * index-0 entries); sigma = 0 gives the lossless update bit for bit.  The
+ * plain scheme runs it; the systolic scheme, fdtd_step_batch and
+ * fdtd_adjoint return FDTD_EUNSUPPORTED for a context with conductivity.  A
+ * later fdtd_set_materials makes the context lossless again. */
+int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
+                             const float* eps_z, const float* sigma_x, const float* sigma_y,
+                             const float* sigma_z, int where);
+
 /* Set the components selected by comp_mask (bit c = component c) from
  * src[c] (nx*ny*nz floats each; src entries for unselected components are
  * ignored and may be NULL).  The fields are E^n and H^(n+1/2) of the current

@@ -239,6 +239,8 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         return fail(ctx, FDTD_EINVAL, "adjoint: spec is NULL or struct_size does not match");
     if (!grad_eps || (where != FDTD_HOST && where != FDTD_DEVICE))
         return fail(ctx, FDTD_EINVAL, "adjoint: grad_eps is NULL or where is invalid");
+    if (ctx->ca[0])
+        return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: conductive (lossy) materials are not supported");
     if (spec->mon_comp < FDTD_EX || spec->mon_comp > FDTD_EZ)
         return fail(ctx, FDTD_EINVAL, "adjoint: the monitored component must be Ex, Ey or Ez");
     if (spec->nsteps < 1 || spec->nsteps > (int64_t(1) << 31) || spec->checkpoint_every < 0)

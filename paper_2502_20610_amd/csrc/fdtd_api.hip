@@ -43,6 +43,38 @@ __global__ void build_coef_kernel(const float* __restrict__ eps, float* __restri
     }
 }
 
+// Conductive coefficients of component `comp`, in IEEE double like cE:
+// h = sigma dt / (2 eps), ca = (1 - h) / (1 + h), cb = (dt / (eps dx)) / (1 + h);
+// on PEC-tangential index-0 entries ca = 1, cb = 0.  Bad permittivity or
+// conductivity (eps < 1, sigma < 0, not finite) sets bit 0 of *err.
+__global__ void build_lossy_kernel(const float* __restrict__ eps, const float* __restrict__ sig,
+                                   float* __restrict__ ca, float* __restrict__ cb, int comp, int nx,
+                                   int ny, int nz, int bcx, int bcy, int bcz, double dt, double dx,
+                                   int* err)
+{
+    const long long n = (long long)nx * ny * nz;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        int k = (int)(p % nz);
+        long long r = p / nz;
+        int j = (int)(r % ny);
+        int i = (int)(r / ny);
+        float ef = eps[p], sf = sig[p];
+        if (!(ef >= 1.0f) || !(ef <= 3.0e38f) || !(sf >= 0.0f) || !(sf <= 3.0e38f)) atomicOr(err, 1);
+        const double e = (double)ef;
+        const double h = (double)sf * dt / (2.0 * e);
+        double a = (1.0 - h) / (1.0 + h);
+        double b = (dt / (e * dx)) / (1.0 + h);
+        if ((comp != 0 && bcx == FDTD_BC_PEC && i == 0) || (comp != 1 && bcy == FDTD_BC_PEC && j == 0) ||
+            (comp != 2 && bcz == FDTD_BC_PEC && k == 0)) {
+            a = 1.0;
+            b = 0.0;
+        }
+        ca[p] = (float)a;
+        cb[p] = (float)b;
+    }
+}
+
 // Force the PEC-tangential entries of E component `comp` to +0.
 __global__ void zero_pec_kernel(float* __restrict__ f, int comp, int nx, int ny, int nz, int bcx,
                                 int bcy, int bcz)
@@ -122,7 +154,8 @@ int check_device_error(fdtd_ctx* ctx)
     if (h & 1) {
         int z = 0;
         (void)hipMemcpy(ctx->dev_error, &z, sizeof(int), hipMemcpyHostToDevice);
-        return fail(ctx, FDTD_EINVAL, "set_materials: permittivity < 1 or not finite (device input)");
+        return fail(ctx, FDTD_EINVAL,
+                    "set_materials: permittivity < 1, conductivity < 0, or not finite (device input)");
     }
     return FDTD_OK;
 }
@@ -354,8 +387,10 @@ int fdtd_destroy(fdtd_ctx* ctx)
     systolic_release(ctx);
     for (int c = 0; c < 6; ++c)
         if (ctx->field[c]) (void)hipFree(ctx->field[c]);
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
         if (ctx->coef[c]) (void)hipFree(ctx->coef[c]);
+        if (ctx->ca[c]) (void)hipFree(ctx->ca[c]);
+    }
     for (auto& s : ctx->sources)
         if (s.wave) (void)hipFree(s.wave);
     if (ctx->dev_sources) (void)hipFree(ctx->dev_sources);
@@ -411,6 +446,73 @@ int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y, co
         (void)hipFree(stage);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "set_materials");
+    // lossless from now on
+    for (int c = 0; c < 3; ++c) {
+        if (ctx->ca[c]) (void)hipFree(ctx->ca[c]);
+        ctx->ca[c] = nullptr;
+    }
+    return FDTD_OK;
+}
+
+int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
+                             const float* eps_z, const float* sigma_x, const float* sigma_y,
+                             const float* sigma_z, int where)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (where != FDTD_HOST && where != FDTD_DEVICE) return fail(ctx, FDTD_EINVAL, "bad `where`");
+    const float* eps[3] = {eps_x, eps_y, eps_z};
+    const float* sig[3] = {sigma_x, sigma_y, sigma_z};
+    for (int c = 0; c < 3; ++c)
+        if (!ok_ptr(eps[c]) || !ok_ptr(sig[c])) return fail(ctx, FDTD_EINVAL, "set_lossy_materials: NULL array");
+    if (where == FDTD_HOST) {
+        for (int c = 0; c < 3; ++c)
+            for (int64_t p = 0; p < ctx->ncell; ++p) {
+                float v = eps[c][p], g = sig[c][p];
+                if (!(v >= 1.0f) || !(v <= 3.0e38f) || !(g >= 0.0f) || !(g <= 3.0e38f))
+                    return fail(ctx, FDTD_EINVAL,
+                                "set_lossy_materials: permittivity < 1, conductivity < 0, or not finite");
+            }
+    }
+    (void)hipSetDevice(ctx->device);
+    const size_t bytes = (size_t)ctx->ncell * sizeof(float);
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 3 && e == hipSuccess; ++c)
+        if (!ctx->ca[c]) e = hipMalloc(&ctx->ca[c], bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FDTD_ENOMEM, "set_lossy_materials: allocation failed");
+    }
+    float* stage = nullptr;
+    if (where == FDTD_HOST && (e = hipMalloc(&stage, 2 * bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FDTD_ENOMEM, "set_lossy_materials: staging allocation failed");
+    }
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        const float* se = eps[c];
+        const float* ss = sig[c];
+        if (where == FDTD_HOST) {
+            e = hipMemcpyAsync(stage, eps[c], bytes, hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(stage + ctx->ncell, sig[c], bytes, hipMemcpyHostToDevice, ctx->stream);
+            se = stage;
+            ss = stage + ctx->ncell;
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(build_lossy_kernel, dim3(grid_for(ctx->ncell)), dim3(kThreads), 0,
+                               ctx->stream, se, ss, ctx->ca[c], ctx->coef[c], c, ctx->nx, ctx->ny,
+                               ctx->nz, ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2], ctx->cfg.dt,
+                               ctx->cfg.dx, ctx->dev_error);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+    }
+    if (stage) {
+        hipError_t e2 = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess) e = e2;
+        (void)hipFree(stage);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_lossy_materials");
     return FDTD_OK;
 }
 

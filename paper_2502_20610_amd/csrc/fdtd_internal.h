@@ -49,7 +49,8 @@ struct fdtd_ctx {
     bool own_stream;
 
     float* field[6];  // Ex Ey Ez Hx Hy Hz
-    float* coef[3];   // cEx cEy cEz
+    float* coef[3];   // cEx cEy cEz (cb, the curl coefficient, with conductivity)
+    float* ca[3];     // E decay per step with conductivity; null when lossless
     float cH;
 
     std::vector<fdtd::SourceRec> sources;

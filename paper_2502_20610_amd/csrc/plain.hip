@@ -16,10 +16,14 @@ constexpr int kBX = 64;  // threads along z (one wavefront)
 constexpr int kBY = 4;   // threads along y
 
 // E half-step (in place): reads H at the backward neighbours (i-1, j-1, k-1).
+// LOSSY: E = (ca E + cb d1) - cb d2 with the conductive coefficients (cE is
+// then cb); with ca = 1 that is the lossless update bit for bit.
+template <bool LOSSY>
 __global__ __launch_bounds__(kBX* kBY) void plain_E_kernel(
     float* __restrict__ Ex, float* __restrict__ Ey, float* __restrict__ Ez,
     const float* __restrict__ Hx, const float* __restrict__ Hy, const float* __restrict__ Hz,
     const float* __restrict__ cEx, const float* __restrict__ cEy, const float* __restrict__ cEz,
+    const float* __restrict__ cax, const float* __restrict__ cay, const float* __restrict__ caz,
     int nx, int ny, int nz, int xchunk)
 {
     const int k = blockIdx.x * kBX + threadIdx.x;
@@ -44,6 +48,11 @@ __global__ __launch_bounds__(kBX* kBY) void plain_E_kernel(
         const float hy_km = Hy[b + row_km], hx_km = Hx[b + row_km];
         const float cx = cEx[p], cy = cEy[p], cz = cEz[p];
         float ex = Ex[p], ey = Ey[p], ez = Ez[p];
+        if (LOSSY) {
+            ex = cax[p] * ex;
+            ey = cay[p] * ey;
+            ez = caz[p] * ez;
+        }
         ex = (ex + cx * (hz - hz_jm)) - cx * (hy - hy_km);
         ey = (ey + cy * (hx - hx_km)) - cy * (hz - hz_im);
         ez = (ez + cz * (hy - hy_im)) - cz * (hx - hx_jm);
@@ -122,9 +131,16 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps)
         const int64_t s = ctx->step_count;
         PendingTiming t;
         timing_begin(ctx, FDTD_KERNEL_PLAIN_E, &t);
-        hipLaunchKernelGGL(plain_E_kernel, grid, block, 0, ctx->stream, ctx->field[0], ctx->field[1],
-                           ctx->field[2], ctx->field[3], ctx->field[4], ctx->field[5], ctx->coef[0],
-                           ctx->coef[1], ctx->coef[2], ctx->nx, ctx->ny, ctx->nz, xchunk);
+        if (ctx->ca[0])
+            hipLaunchKernelGGL(plain_E_kernel<true>, grid, block, 0, ctx->stream, ctx->field[0],
+                               ctx->field[1], ctx->field[2], ctx->field[3], ctx->field[4], ctx->field[5],
+                               ctx->coef[0], ctx->coef[1], ctx->coef[2], ctx->ca[0], ctx->ca[1],
+                               ctx->ca[2], ctx->nx, ctx->ny, ctx->nz, xchunk);
+        else
+            hipLaunchKernelGGL(plain_E_kernel<false>, grid, block, 0, ctx->stream, ctx->field[0],
+                               ctx->field[1], ctx->field[2], ctx->field[3], ctx->field[4], ctx->field[5],
+                               ctx->coef[0], ctx->coef[1], ctx->coef[2], nullptr, nullptr, nullptr,
+                               ctx->nx, ctx->ny, ctx->nz, xchunk);
         timing_end(ctx, &t);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "launch(plain E)");

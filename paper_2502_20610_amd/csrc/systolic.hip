@@ -1366,6 +1366,10 @@ int systolic_supported(const fdtd_ctx* ctx, std::string* why)
         *why = "field arrays above 4 GiB are not supported by the systolic scheme";
         return 0;
     }
+    if (ctx->ca[0]) {
+        *why = "conductive (lossy) materials run on the plain scheme only in this build";
+        return 0;
+    }
     return 1;
 }
 

@@ -34,7 +34,8 @@ KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC = range(4)
 SCHEMES = {"plain": SCHEME_PLAIN, "systolic": SCHEME_SYSTOLIC}
 
 # every symbol the header declares
-EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_fields",
+EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_lossy_materials",
+           "fdtd_set_fields",
            "fdtd_add_source", "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_synchronize",
            "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
            "fdtd_kernel_stats", "fdtd_get_info")
@@ -80,6 +81,7 @@ def load_library():
         "fdtd_create": ([ctypes.POINTER(Config), ctypes.POINTER(vp)], ctypes.c_int),
         "fdtd_destroy": ([vp], ctypes.c_int),
         "fdtd_set_materials": ([vp, vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "fdtd_set_lossy_materials": ([vp] + [vp] * 6 + [ctypes.c_int], ctypes.c_int),
         "fdtd_set_fields": ([vp, u32, ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
         "fdtd_add_source": ([vp, ctypes.c_int, i32, i32, i32, vp, i64, i64, ctypes.c_int],
                             ctypes.c_int),
@@ -172,15 +174,24 @@ class Simulation:
         self.close()
 
     # -- API ------------------------------------------------------------------
-    def set_materials(self, eps_x, eps_y=None, eps_z=None):
+    def set_materials(self, eps_x, eps_y=None, eps_z=None, sigma=None):
+        """Permittivity per component (one array for all three if only eps_x);
+        with ``sigma`` (one array or three) the materials are conductive."""
         eps_y = eps_x if eps_y is None else eps_y
         eps_z = eps_x if eps_z is None else eps_z
-        ptrs = [_pointer(e, self.ncell) for e in (eps_x, eps_y, eps_z)]
+        arrays = [eps_x, eps_y, eps_z]
+        if sigma is not None:
+            arrays += list(sigma) if isinstance(sigma, (list, tuple)) else [sigma] * 3
+        ptrs = [_pointer(e, self.ncell) for e in arrays]
         wheres = {p[1] for p in ptrs}
         if len(wheres) != 1:
-            raise ValueError("all permittivity arrays must live on the same side")
-        self._check(self._lib.fdtd_set_materials(self._h, ptrs[0][0], ptrs[1][0], ptrs[2][0],
-                                                 ptrs[0][1]))
+            raise ValueError("all material arrays must live on the same side")
+        if sigma is None:
+            self._check(self._lib.fdtd_set_materials(self._h, ptrs[0][0], ptrs[1][0], ptrs[2][0],
+                                                     ptrs[0][1]))
+        else:
+            self._check(self._lib.fdtd_set_lossy_materials(self._h, *[q[0] for q in ptrs],
+                                                           ptrs[0][1]))
 
     def set_fields(self, fields, mask: Optional[int] = None):
         """``fields``: six arrays (None entries skipped) in (Ex..Hz) order."""

@@ -35,16 +35,18 @@ PLAIN_E_BYTES, PLAIN_H_BYTES = 48, 36   # algorithmic bytes per cell, per half-s
 PLAIN_BYTES_PER_UPDATE = PLAIN_E_BYTES + PLAIN_H_BYTES
 
 
-def systolic_bytes_per_update(tile, band):
+def systolic_bytes_per_update(tile, band, conductive=False):
     """Algorithmic HBM bytes per cell update of the systolic scheme (Section 4
     accounting): every step a tile of V = Wx*Wy*Wz updated cells takes in its
-    leading faces (E, H and the coefficient: 36 B per cell) and puts out its
-    trailing faces (E and H: 24 B per cell), A = WyWz + WxWz + WxWy cells each;
-    once per band of K steps the whole state goes out and comes back in (60 B
-    per cell)."""
+    leading faces (E, H and the coefficient: 36 B per cell; 48 B with the
+    conductive decay) and puts out its trailing faces (E and H: 24 B per
+    cell), A = WyWz + WxWz + WxWy cells each; once per band of K steps the
+    whole state goes out and comes back in (60 B per cell; 72 B with the
+    conductive decay)."""
     wx, wy, wz = tile
     area = wy * wz + wx * wz + wx * wy
-    return (36 + 24) * area / (wx * wy * wz) + 60.0 / band
+    lead = 48 if conductive else 36
+    return (lead + 24) * area / (wx * wy * wz) + (lead + 24.0) / band
 
 
 def counter_traffic(kernel: str, source: str, launch: dict):
@@ -83,7 +85,7 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %r" % name)
 
 
-def run_scheme(w, scheme: str, steps: int, warmup: int, options=None):
+def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None):
     import torch
     from paper_2502_20610_amd import fdtd
     stream = torch.cuda.current_stream()
@@ -92,7 +94,10 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None):
         for k, v in (options or {}).items():
             sim.set_option(k, v)
         dev = torch.device("cuda:0")
-        sim.set_materials(torch.from_numpy(w.eps).to(dev))
+        if sigma is None:
+            sim.set_materials(torch.from_numpy(w.eps).to(dev))
+        else:
+            sim.set_materials(torch.from_numpy(w.eps).to(dev), sigma=sigma)
         if w.fields is not None:
             sim.set_fields([torch.from_numpy(f).to(dev) for f in w.fields])
         for s in w.sources:
@@ -293,6 +298,9 @@ def main():
                          "per grid and the plain scheme")
     ap.add_argument("--batch-dims", default="64,192",
                     help="lo,hi: per-axis sizes of the batched grids (multiples of 16)")
+    ap.add_argument("--sigma", type=float, default=0.0,
+                    help="conductive variant: a graded absorbing shell (16 cells) with this peak "
+                         "conductivity around the workload (0 = lossless)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling HBM counters")
@@ -328,6 +336,11 @@ def main():
     w = make_workload(args.workload)
     cells = w.cells
     log("workload %s: %d cells, %d sources" % (w.name, cells, len(w.sources)))
+    sigma = None
+    if args.sigma > 0:
+        from paper_2502_20610_amd import workloads as wl
+        sigma = torch.from_numpy(wl.graded_shell(w.shape, 16, args.sigma)).to("cuda:0")
+        log("conductive: graded shell of 16 cells, peak sigma %g" % args.sigma)
 
     results = {}
     for scheme in args.schemes.split(","):
@@ -338,7 +351,7 @@ def main():
                     opts[fdtd.OPT_BAND_STEPS] = args.band
                 if args.workgroups:
                     opts[fdtd.OPT_WORKGROUPS] = args.workgroups
-            t, stats = run_scheme(w, scheme, args.steps, args.warmup, opts)
+            t, stats = run_scheme(w, scheme, args.steps, args.warmup, opts, sigma)
         except fdtd.FdtdError as e:
             if e.code == fdtd.FDTD_EUNSUPPORTED:
                 log("%s unavailable: %s" % (scheme, e))
@@ -356,11 +369,12 @@ def main():
         avg_s = ms / 1e3 / max(n, 1)
         steps_per_launch = args.steps / max(n, 1)
         band = stats["info"]["band_steps"]
-        b_alg = systolic_bytes_per_update(stats["info"]["tile"], band)
+        b_alg = systolic_bytes_per_update(stats["info"]["tile"], band, sigma is not None)
         updates = cells * steps_per_launch
         achieved = b_alg * updates / avg_s / 1e9
         flops = FLOPS_PER_CELL * updates / avg_s / 1e12
-        launch = {"workload": w.name, "steps": int(round(steps_per_launch)), "band": band}
+        launch = {"workload": w.name + ("_conductive" if sigma is not None else ""),
+                  "steps": int(round(steps_per_launch)), "band": band}
         traffic = counter_traffic("systolic_kernel", "paper_2502_20610_amd/csrc/systolic.hip",
                                   dict(launch, cells=cells))
         # arithmetic intensity 36 / b_alg flop/B is below the machine balance
@@ -376,15 +390,18 @@ def main():
     else:
         n, ms = stats[fdtd.KERNEL_PLAIN_E]
         avg_s = ms / 1e3 / max(n, 1)
-        achieved = PLAIN_E_BYTES * cells / avg_s / 1e9
+        e_bytes = PLAIN_E_BYTES + (12 if sigma is not None else 0)
+        achieved = e_bytes * cells / avg_s / 1e9
         traffic = counter_traffic("plain_E_kernel", "paper_2502_20610_amd/csrc/plain.hip",
-                                  {"workload": w.name, "steps": 1, "cells": cells})
+                                  {"workload": w.name + ("_conductive" if sigma is not None else ""),
+                                   "steps": 1, "cells": cells})
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "plain_E_kernel",
                 "launches": n, "avg_launch_ms": avg_s * 1e3}
 
     out = {
-        "metric": "cell updates/s, systolic vs plain Yee FDTD, %dx%dx%d FP32" % w.shape,
+        "metric": "cell updates/s, systolic vs plain Yee FDTD, %dx%dx%d FP32" % w.shape
+                  + (", conductive" if sigma is not None else ""),
         "value": cups, "unit": "cell updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -397,7 +414,8 @@ def main():
         entry = {"cups": c, "ms_per_step": ts / args.steps * 1e3}
         if scheme == "systolic":
             entry.update(st["info"])
-            b = systolic_bytes_per_update(st["info"]["tile"], st["info"]["band_steps"])
+            b = systolic_bytes_per_update(st["info"]["tile"], st["info"]["band_steps"],
+                                          sigma is not None)
             entry["alg_bytes_per_update"] = b
             entry["alg_roofline_frac"] = c * b / (HBM_PEAK_GBS * 1e9)
             entry["effective_bw_frac_84B"] = c * PLAIN_BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9)
@@ -406,11 +424,14 @@ def main():
             nh, msh = st[fdtd.KERNEL_PLAIN_H]
             entry["E_avg_ms"] = mse / max(ne, 1)
             entry["H_avg_ms"] = msh / max(nh, 1)
-            entry["alg_bytes_per_update"] = PLAIN_BYTES_PER_UPDATE
-            entry["alg_roofline_frac"] = c * PLAIN_BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9)
+            pb = PLAIN_BYTES_PER_UPDATE + (12 if sigma is not None else 0)
+            entry["alg_bytes_per_update"] = pb
+            entry["alg_roofline_frac"] = c * pb / (HBM_PEAK_GBS * 1e9)
         out[scheme] = entry
     if "plain" in results and "systolic" in results:
         out["systolic_over_plain"] = out["systolic"]["cups"] / out["plain"]["cups"]
+    if sigma is not None:
+        out["config"]["conductive"] = {"shell_cells": 16, "sigma_max": args.sigma}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -115,10 +115,13 @@ int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
  *     E_c = (ca_c * E_c + cb_c * d1) - cb_c * d2,
  *     h = sigma dt / (2 eps), ca = (1 - h) / (1 + h), cb = (dt / (eps dx)) / (1 + h),
  * all in IEEE double, rounded to FP32 (ca = 1, cb = 0 on PEC-tangential
- * index-0 entries); sigma = 0 gives the lossless update bit for bit.  The
- * plain scheme runs it; the systolic scheme, fdtd_step_batch and
- * fdtd_adjoint return FDTD_EUNSUPPORTED for a context with conductivity.  A
- * later fdtd_set_materials makes the context lossless again. */
+ * index-0 entries); sigma = 0 gives the lossless update bit for bit.  Both
+ * schemes run it (the systolic tile is then 11 cells wide along x, since ca
+ * travels with the tile as three more per-cell coefficients);
+ * fdtd_step_batch refuses (FDTD_EUNSUPPORTED) a batch that mixes
+ * conductive and lossless contexts, and fdtd_adjoint returns
+ * FDTD_EUNSUPPORTED for a context with conductivity.  A later
+ * fdtd_set_materials makes the context lossless again. */
 int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
                              const float* eps_z, const float* sigma_x, const float* sigma_y,
                              const float* sigma_z, int where);
@@ -253,7 +256,8 @@ enum {
     FDTD_INFO_SYSTOLIC_BAND = 1,   /* steps per band of the last systolic launch         */
     FDTD_INFO_SYSTOLIC_TICKETS = 2,/* (band, tile) tickets of the last systolic launch    */
     FDTD_INFO_RING_SLOTS = 3,      /* face-ring slots of the last systolic launch        */
-    FDTD_INFO_TILE_X = 4,          /* updated cells per systolic tile along x, y, z      */
+    FDTD_INFO_TILE_X = 4,          /* updated cells per systolic tile along x, y, z (x:  */
+                                   /* 15, or 11 for a context with conductivity)         */
     FDTD_INFO_TILE_Y = 5,
     FDTD_INFO_TILE_Z = 6
 };

@@ -717,7 +717,7 @@ int fdtd_get_info(const fdtd_ctx* ctx, int key, int64_t* value)
 {
     if (!ctx || !value) return FDTD_EINVAL;
     int wx, wy, wz;
-    systolic_tile(&wx, &wy, &wz);
+    systolic_tile(ctx, &wx, &wy, &wz);
     switch (key) {
     case FDTD_INFO_SYSTOLIC_GRID: *value = ctx->sys_grid; return FDTD_OK;
     case FDTD_INFO_SYSTOLIC_BAND: *value = ctx->sys_band; return FDTD_OK;

@@ -100,7 +100,7 @@ int systolic_supported(const fdtd_ctx* ctx, std::string* why);
 int systolic_step(fdtd_ctx* ctx, int64_t nsteps);
 int systolic_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps);
 void systolic_release(fdtd_ctx* ctx);
-void systolic_tile(int* wx, int* wy, int* wz);
+void systolic_tile(const fdtd_ctx* ctx, int* wx, int* wy, int* wz);
 
 // Reverse-time adjoint of a monitor objective (adjoint.hip).
 int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where);

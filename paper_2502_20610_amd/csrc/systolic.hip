@@ -55,6 +55,7 @@ namespace {
 
 constexpr int PX = 16, PZ = 16;         // slots along x (registers) and z (lanes)
 constexpr int WX = PX - 1, WZ = PZ - 1; // updated cells along x and z
+constexpr int WX_LOSSY = 11;              // updated cells along x with conductivity
 constexpr unsigned kOOB = 0xFFFFFFF0u;  // buffer offset that reads 0 / drops stores
 
 // longest band: the per-band source samples are staged in LDS
@@ -66,6 +67,7 @@ constexpr int kMaxBand = 64;
 struct SimArgs {
     float* f[6];
     const float* cE[3];
+    const float* ca[3];  // conductive decay per cell (conductive variant only)
     float cH;
     int nx, ny, nz;
     unsigned fbytes;   // bytes of one field array
@@ -285,22 +287,32 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     return *s_abort == 0;
 }
 
-template <int NW, bool DEV, bool PER>
+template <int NW, bool DEV, bool PER, bool LOSSY>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void systolic_kernel(SysArgs A)
 {
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
     constexpr int PY = 4 * NW;
     constexpr int WY = PY - 1;
     static_assert(PY == 16, "face staging assumes 16 slots on every axis");
+    // x slots in registers: 16 (15 updated); with conductivity 12 (11
+    // updated), which frees the registers of the per-cell decay ca
+    constexpr int PXk = LOSSY ? WX_LOSSY + 1 : PX;
+    constexpr int WXk = PXk - 1;
+    // staged components: E, H, cb (cE), and ca with conductivity
+    constexpr int NQA = LOSSY ? 12 : 9;
+    constexpr int LS = 16;  // row stride of the LDS and ring face layouts
+    // rows (x slots) of the incoming y face: whole wavefronts of four rows,
+    // so that the conductive variant fits two workgroups in a CU's LDS
+    constexpr int YR = (PXk + 3) & ~3;
     // y-neighbour exchange, two components per half-step
-    __shared__ float xch[2][WX][PY][PZ];
+    __shared__ float xch[2][WXk][PY][PZ];
     // incoming faces of the next box: y face [comp][x][z], z face [comp][y][x]
-    __shared__ float xst[9][PY][PZ];   // x face [comp][y slot][z slot]
-    __shared__ float yst[9][PX][PZ];
-    __shared__ __attribute__((aligned(16))) float zst[9][PY][PX];
+    __shared__ float xst[NQA][PY][PZ];   // x face [comp][y slot][z slot]
+    __shared__ float yst[NQA][YR][PZ];
+    __shared__ __attribute__((aligned(16))) float zst[NQA][PY][LS];
     // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
-    __shared__ float ytr[6][PX][PZ];
-    __shared__ __attribute__((aligned(16))) float ztr[9][PY][PX];
+    __shared__ float ytr[6][LS][PZ];
+    __shared__ __attribute__((aligned(16))) float ztr[NQA][PY][LS];
     __shared__ int s_ticket;
     __shared__ int s_abort;
     __shared__ unsigned s_up;  // lower bound of the upwind neighbours' progress
@@ -319,10 +331,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const int zs = tid & 15;        // z slot: lane within the DPP row
     if (tid == 0) s_abort = 0;
     const __amdgpu_buffer_rsrc_t rring = make_rsrc(A.ring, A.ring_bytes);
-    constexpr unsigned ring_step = 9u * PY * PX;  // floats per (slot, local step)
-    constexpr unsigned ring_comp = PY * PX;       // floats per component
+    constexpr unsigned ring_step = (unsigned)NQA * PY * LS;  // floats per (slot, local step)
+    constexpr unsigned ring_comp = PY * LS;                  // floats per component
 
-    float E[3][PX], H[3][PX], C[3][PX];
+    float E[3][PXk], H[3][PXk], C[3][PXk];
+    float CA[LOSSY ? 3 : 1][PXk];  // conductive decay per cell (unused when lossless)
 
     for (;;) {
         __syncthreads();
@@ -348,6 +361,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         for (int q = 0; q < 6; ++q) rf[q] = make_rsrc(P.f[q], P.fbytes);
 #pragma unroll
         for (int q = 0; q < 3; ++q) rc[q] = make_rsrc(P.cE[q], P.fbytes);
+        __amdgpu_buffer_rsrc_t rca[3];
+        if (LOSSY) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rca[q] = make_rsrc(P.ca[q], P.fbytes);
+        }
         const unsigned plane = (unsigned)P.ny * (unsigned)P.nz;
         const float cH = P.cH;
         const bool perx = PER && P.per[0], pery = PER && P.per[1], perz = PER && P.per[2];
@@ -363,7 +381,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
         __syncthreads();
         const int me = t;  // progress counters are per ticket
-        const int ox = a * WX, oy = b * WY, oz = c * WZ;
+        const int ox = a * WXk, oy = b * WY, oz = c * WZ;
 
         // upwind neighbours that exist in this band
         int ups[8];
@@ -435,7 +453,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         // updated cells per axis (the last tile of a periodic ring is ragged),
         // the lanes that take the forward y and z faces, and the tile frame
         // origin modulo n on periodic axes
-        const int wxr = (perx && a == P.L[0] - 1) ? P.wr[0] : WX;
+        const int wxr = (perx && a == P.L[0] - 1) ? P.wr[0] : WXk;
         const int wyr = (pery && b == P.L[1] - 1) ? P.wr[1] : WY;
         const int wzr = (perz && c == P.L[2] - 1) ? P.wr[2] : WZ;
         const int fy = (wyr + 1) & (PY - 1), fz = (wzr + 1) & (PZ - 1);
@@ -487,7 +505,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const bool okyz = oky && okz;
             const unsigned yz = (unsigned)y * (unsigned)P.nz + (unsigned)z;
 #pragma unroll
-            for (int j = 0; j < PX; ++j) {
+            for (int j = 0; j < PXk; ++j) {
                 int x;
                 const bool okx = axis_pos<PER>(ox + t0 + 1, Xw, P.nx, perx, j - 1, x);
                 const unsigned off = (okyz && okx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
@@ -496,6 +514,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     E[q][j] = bld<SP>(rf[q], off);
                     H[q][j] = bld<SP>(rf[3 + q], off);
                     C[q][j] = bld<0>(rc[q], off);
+                    if (LOSSY) CA[q][j] = bld<0>(rca[q], off);
                 }
             }
         }
@@ -551,28 +570,32 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const unsigned oxf = (okyz1 && okxf) ? ((unsigned)xf * plane + yz1) * 4u : kOOB;
                 // y face: rows of the wavefront are x, lanes are z
                 const int j = 4 * w + r;
+                const bool ydo = YR == PY || 4 * w < YR;  // wavefront-uniform
                 int x;
-                const bool okx = axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
+                const bool okx = (!LOSSY || j < WXk) && axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
                 const unsigned oyf = (oky_f && okz_l && okx)
                                          ? (((unsigned)x * (unsigned)P.ny + (unsigned)yf) * (unsigned)P.nz + (unsigned)zl) * 4u
                                          : kOOB;
                 // z face: rows are y, lanes are x, from the +z neighbour's ring slot
                 const int yy = 4 * w + r;
                 int xr, yr;
-                const bool okz = has_zup && okz_f && zs < WX && yy < WY &&
+                const bool okz = has_zup && okz_f && zs < WXk && yy < WY &&
                                  axis_pos<PER>(Ux, Xw, P.nx, perx, zs, xr) &&
                                  axis_pos<PER>(Uy, Yw, P.ny, pery, yy, yr);
-                const unsigned ozf = (ring_zup + (unsigned)yy * PX + (unsigned)zs) * 4u;
+                const unsigned ozf = (ring_zup + (unsigned)yy * LS + (unsigned)zs) * 4u;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) {
-                    const unsigned ly = lds_offset(&yst[q][4 * w][0]);
+                    const unsigned ly = lds_offset(&yst[q][ydo ? 4 * w : 0][0]);
                     const unsigned lx = lds_offset(&xst[q][4 * w][0]);
                     if (q < 6) {
                         dma_dword<DEV>(rf[q], lx, oxf);
-                        dma_dword<DEV>(rf[q], ly, oyf);
-                    } else {
+                        if (ydo) dma_dword<DEV>(rf[q], ly, oyf);
+                    } else if (q < 9) {
                         dma_dword<false>(rc[q - 6], lx, oxf);
-                        dma_dword<false>(rc[q - 6], ly, oyf);
+                        if (ydo) dma_dword<false>(rc[q - 6], ly, oyf);
+                    } else if (LOSSY) {
+                        dma_dword<false>(rca[q - 9], lx, oxf);
+                        if (ydo) dma_dword<false>(rca[q - 9], ly, oyf);
                     }
                     dma_dword<DEV>(rring, lds_offset(&zst[q][4 * w][0]),
                                    okz ? ozf + (unsigned)q * ring_comp * 4u : kOOB);
@@ -598,7 +621,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rf[q], o, ytr[q][j][zs]);
                 // (dropped offsets when there is no consumer: no branch)
-                const unsigned oz_ = (ring_base + (unsigned)j * PX + (unsigned)zs) * 4u;
+                const unsigned oz_ = (ring_base + (unsigned)j * LS + (unsigned)zs) * 4u;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQZ; ++q)
                     bst<SP>(rring, has_consumer ? oz_ + (unsigned)q * ring_comp * 4u : kOOB, ztr[q][j][zs]);
@@ -612,7 +635,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
             if (earlyE) prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
 #pragma unroll
-            for (int j = 1; j < PX; ++j) {
+            for (int j = 1; j < PXk; ++j) {
                 xch[0][j - 1][ys][zs] = H[2][j];
                 xch[1][j - 1][ys][zs] = H[0][j];
             }
@@ -620,23 +643,30 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             {
                 const int ysm = (ys - 1) & (PY - 1);
 #pragma unroll
-                for (int j = 1; j < PX; ++j) {
+                for (int j = 1; j < PXk; ++j) {
                     const float hz_ym = xch[0][j - 1][ysm][zs];
                     const float hx_ym = xch[1][j - 1][ysm][zs];
                     const float hy_zm = from_zm(H[1][j]);
                     const float hx_zm = from_zm(H[0][j]);
-                    const float ex = (E[0][j] + C[0][j] * (H[2][j] - hz_ym)) - C[0][j] * (H[1][j] - hy_zm);
-                    const float ey = (E[1][j] + C[1][j] * (H[0][j] - hx_zm)) - C[1][j] * (H[2][j] - H[2][j - 1]);
-                    const float ez = (E[2][j] + C[2][j] * (H[1][j] - H[1][j - 1])) - C[2][j] * (H[0][j] - hx_ym);
+                    // with conductivity the old E decays by ca first (ca = 1
+                    // reproduces the lossless update)
+                    const float e0 = LOSSY ? CA[0][j] * E[0][j] : E[0][j];
+                    const float e1 = LOSSY ? CA[1][j] * E[1][j] : E[1][j];
+                    const float e2 = LOSSY ? CA[2][j] * E[2][j] : E[2][j];
+                    const float ex = (e0 + C[0][j] * (H[2][j] - hz_ym)) - C[0][j] * (H[1][j] - hy_zm);
+                    const float ey = (e1 + C[1][j] * (H[0][j] - hx_zm)) - C[1][j] * (H[2][j] - H[2][j - 1]);
+                    const float ez = (e2 + C[2][j] * (H[1][j] - H[1][j - 1])) - C[2][j] * (H[0][j] - hx_ym);
                     E[0][j - 1] = ex;
                     E[1][j - 1] = ey;
                     E[2][j - 1] = ez;
-                    C[0][j - 1] = C[0][j];
-                    C[1][j - 1] = C[1][j];
-                    C[2][j - 1] = C[2][j];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        C[q][j - 1] = C[q][j];
+                        if (LOSSY) CA[q][j - 1] = CA[q][j];
+                    }
                 }
             }
-            // now E and C registers j <-> x = ox+tau+j (j = 0..14); j = 15 stale
+            // now E and C registers j <-> x = ox+tau+j (j < WXk); j = WXk stale
 
             // point sources of this step on cells of the tile (registers are
             // only ever indexed with compile-time constants, so they stay in
@@ -655,11 +685,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const float wv = (sample);                                                              \
             const int lx = (dy == py + 1 && dz == pz + 1) ? px : -1;                                \
             if ((comp) == 0) {                                                                      \
-                _Pragma("unroll") for (int j = 0; j < WX; ++j) E[0][j] = lx == j ? E[0][j] + wv : E[0][j]; \
+                _Pragma("unroll") for (int j = 0; j < WXk; ++j) E[0][j] = lx == j ? E[0][j] + wv : E[0][j]; \
             } else if ((comp) == 1) {                                                               \
-                _Pragma("unroll") for (int j = 0; j < WX; ++j) E[1][j] = lx == j ? E[1][j] + wv : E[1][j]; \
+                _Pragma("unroll") for (int j = 0; j < WXk; ++j) E[1][j] = lx == j ? E[1][j] + wv : E[1][j]; \
             } else {                                                                                \
-                _Pragma("unroll") for (int j = 0; j < WX; ++j) E[2][j] = lx == j ? E[2][j] + wv : E[2][j]; \
+                _Pragma("unroll") for (int j = 0; j < WXk; ++j) E[2][j] = lx == j ? E[2][j] + wv : E[2][j]; \
             }                                                                                       \
         }                                                                                           \
     }
@@ -683,7 +713,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
             if (dy == 1) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j)
+                for (int j = 0; j < WXk; ++j)
 #pragma unroll
                     for (int q = 0; q < 3; ++q) ytr[q][j][zs] = E[q][j];
             }
@@ -691,7 +721,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int j = 0; j < WX; ++j) ztr[q][dy1][j] = E[q][j];
+                    for (int j = 0; j < WXk; ++j) ztr[q][dy1][j] = E[q][j];
             }
             store_faces(std::integral_constant<int, 0>(), std::integral_constant<int, 3>(), std::integral_constant<int, 3>());
             // publish (which also completes an early prefetch); a late prefetch
@@ -710,33 +740,33 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // forward shell's E^tau into the registers
             if (dy == fy) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j)
+                for (int j = 0; j < WXk; ++j)
 #pragma unroll
                     for (int q = 0; q < 3; ++q) E[q][j] = yst[q][j][zs];
             } else if (dz == fz) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int j = 0; j < WX; ++j) E[q][j] = zst[q][dy1][j];
+                    for (int j = 0; j < WXk; ++j) E[q][j] = zst[q][dy1][j];
             }
-            if (!PER || wxr == WX) {
+            if (!PER || wxr == WXk) {
 #pragma unroll
-                for (int q = 0; q < 3; ++q) E[q][WX] = xst[q][ys][zs];
+                for (int q = 0; q < 3; ++q) E[q][WXk] = xst[q][ys][zs];
             } else {
                 // ragged tile of a periodic ring: the x face enters at slot wxr
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     const float v = xst[q][ys][zs];
 #pragma unroll
-                    for (int j = 0; j < WX; ++j) E[q][j] = j == wxr ? v : E[q][j];
+                    for (int j = 0; j < WXk; ++j) E[q][j] = j == wxr ? v : E[q][j];
                 }
             }
 
             // ================= H half-step (E frame: register j <-> x = ox+tau+j)
             const bool earlyH = tau < t1 && s_up >= 2u * (unsigned)tau;
-            if (earlyH) prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
+            if (earlyH) prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, NQA - 3>());
 #pragma unroll
-            for (int j = 0; j < WX; ++j) {
+            for (int j = 0; j < WXk; ++j) {
                 xch[0][j][ys][zs] = E[2][j];
                 xch[1][j][ys][zs] = E[0][j];
             }
@@ -744,7 +774,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             {
                 const int ysp = (ys + 1) & (PY - 1);
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
+                for (int j = 0; j < WXk; ++j) {
                     const float ez_yp = xch[0][j][ysp][zs];
                     const float ex_yp = xch[1][j][ysp][zs];
                     const float ey_zp = from_zp(E[1][j]);
@@ -767,7 +797,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
             if (dy == 1) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j)
+                for (int j = 0; j < WXk; ++j)
 #pragma unroll
                     for (int q = 0; q < 3; ++q) ytr[3 + q][j][zs] = H[q][j];
             }
@@ -775,16 +805,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int j = 0; j < WX; ++j) {
+                    for (int j = 0; j < WXk; ++j) {
                         ztr[3 + q][dy1][j] = H[q][j];
                         ztr[6 + q][dy1][j] = C[q][j];
+                        if (LOSSY) ztr[9 + q][dy1][j] = CA[q][j];
                     }
             }
-            store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
+            store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, 3>(), std::integral_constant<int, NQA - 3>());
             if (tau == t1 && inB) {
                 // band end: the whole subdomain goes back to the field arrays
 #pragma unroll
-                for (int j = 0; j < WX; ++j) {
+                for (int j = 0; j < WXk; ++j) {
                     const unsigned o = j < wxr ? off_at(j) : kOOB;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
@@ -800,42 +831,47 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     aborted = true;
                     break;
                 }
-                prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, 6>());
+                prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, NQA - 3>());
                 complete_loads();
             }
 
             // forward shell's H^(tau+1/2) and coefficients into the registers
             if (dy == fy) {
 #pragma unroll
-                for (int j = 0; j < WX; ++j)
+                for (int j = 0; j < WXk; ++j)
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         H[q][j] = yst[3 + q][j][zs];
                         C[q][j] = yst[6 + q][j][zs];
+                        if (LOSSY) CA[q][j] = yst[9 + q][j][zs];
                     }
             } else if (dz == fz) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int j = 0; j < WX; ++j) {
+                    for (int j = 0; j < WXk; ++j) {
                         H[q][j] = zst[3 + q][dy1][j];
                         C[q][j] = zst[6 + q][dy1][j];
+                        if (LOSSY) CA[q][j] = zst[9 + q][dy1][j];
                     }
             }
-            if (!PER || wxr == WX) {
+            if (!PER || wxr == WXk) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    H[q][WX] = xst[3 + q][ys][zs];
-                    C[q][WX] = xst[6 + q][ys][zs];
+                    H[q][WXk] = xst[3 + q][ys][zs];
+                    C[q][WXk] = xst[6 + q][ys][zs];
+                    if (LOSSY) CA[q][WXk] = xst[9 + q][ys][zs];
                 }
             } else {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     const float vh = xst[3 + q][ys][zs], vc = xst[6 + q][ys][zs];
+                    const float va = LOSSY ? xst[9 + q][ys][zs] : 0.f;
 #pragma unroll
-                    for (int j = 0; j < WX; ++j) {
+                    for (int j = 0; j < WXk; ++j) {
                         H[q][j] = j == wxr ? vh : H[q][j];
                         C[q][j] = j == wxr ? vc : C[q][j];
+                        if (LOSSY) CA[q][j] = j == wxr ? va : CA[q][j];
                     }
                 }
             }
@@ -863,7 +899,7 @@ constexpr int kNW = 4;  // wavefronts per tile: tile = 15 x 15 x 15 updated cell
 // Host-side plan of one context's call (tickets, per-band tile ranges, the
 // tile->ticket table) and the launch resources of the launches it leads.
 struct SystolicState {
-    int nsteps = -1, K = -1;
+    int nsteps = -1, K = -1, wx = -1;  // the plan's step count, band and tile width along x
     int nt = 0, D = 1, nbands = 0;
     int per[3] = {0, 0, 0};  // periodic axes of the plan
     int L[3] = {0, 0, 0};    // ring tiles on periodic axes
@@ -924,11 +960,15 @@ void free_launch(SystolicState* s)
 
 int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// updated cells along x of a tile of this context: conductive grids use the
+// narrower register tile that leaves room for the per-cell decay
+int tile_x(const fdtd_ctx* c) { return c->ca[0] ? WX_LOSSY : WX; }
+
 // The plan of one context: tiles per band, tickets in topological order.
 int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 {
     constexpr int WY = 4 * kNW - 1;
-    const int W[3] = {WX, WY, WZ};
+    const int W[3] = {tile_x(ctx), WY, WZ};
     const int N[3] = {ctx->nx, ctx->ny, ctx->nz};
     int per[3], L[3], group = 1;
     for (int d = 0; d < 3; ++d) {
@@ -1001,6 +1041,7 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     (void)wrap;
     s->nsteps = nsteps;
     s->K = K;
+    s->wx = W[0];
     s->nt = (int)ntot;
     s->nbands = nb;
     for (int d = 0; d < 3; ++d) {
@@ -1041,7 +1082,7 @@ int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
         for (int i = 0; i < n; ++i) {
             const fdtd_ctx* c = cs[i];
             const int nd[3] = {c->nx, c->ny, c->nz};
-            const int W[3] = {WX, 4 * kNW - 1, WZ};
+            const int W[3] = {tile_x(c), 4 * kNW - 1, WZ};
             double f = 1.0 + kBeta / K;
             for (int d = 0; d < 3; ++d) {
                 const double slots = c->cfg.bc[d] == FDTD_BC_PERIODIC
@@ -1176,6 +1217,11 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
     fdtd_ctx* lead = cs[0];
     if (nsteps > (int64_t(1) << 24)) return fail(lead, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
+    // one kernel variant per launch: all members conductive or none
+    const bool lossy = lead->ca[0] != nullptr;
+    for (int i = 1; i < n; ++i)
+        if ((cs[i]->ca[0] != nullptr) != lossy)
+            return fail(lead, FDTD_EUNSUPPORTED, "systolic batch: conductive and lossless grids cannot share a launch");
     // band length per simulation: the lead's option for all, else each
     // simulation's own choice of the cost model
     int Kmax = 1;
@@ -1187,7 +1233,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
         SystolicState* si = cs[i]->sys;
         const int K = lead->band_steps > 0 ? default_band(cs, 1, nsteps) : default_band(cs + i, 1, nsteps);
         Kmax = std::max(Kmax, K);
-        if (si->nsteps != (int)nsteps || si->K != K) {
+        if (si->nsteps != (int)nsteps || si->K != K || si->wx != tile_x(cs[i])) {
             int rc = build_plan(cs[i], si, (int)nsteps, K);
             if (rc) return rc == FDTD_OK ? rc : fail(lead, rc, cs[i]->err);
         }
@@ -1197,12 +1243,18 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     if (rc) return rc;
     bool anyper = false;
     for (int i = 0; i < n; ++i) anyper = anyper || cs[i]->sys->per[0] || cs[i]->sys->per[1] || cs[i]->sys->per[2];
+
     // synchronisation variant: device-scope accesses (default) or cached
     // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
     const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
     const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
-    auto kern = dev ? (anyper ? systolic_kernel<kNW, true, true> : systolic_kernel<kNW, true, false>)
-                    : (anyper ? systolic_kernel<kNW, false, true> : systolic_kernel<kNW, false, false>);
+    using Kern = void (*)(SysArgs);
+    static const Kern kernels[2][2][2] = {
+        {{systolic_kernel<kNW, false, false, false>, systolic_kernel<kNW, false, false, true>},
+         {systolic_kernel<kNW, false, true, false>, systolic_kernel<kNW, false, true, true>}},
+        {{systolic_kernel<kNW, true, false, false>, systolic_kernel<kNW, true, false, true>},
+         {systolic_kernel<kNW, true, true, false>, systolic_kernel<kNW, true, true, true>}}};
+    const Kern kern = kernels[dev][anyper][lossy];
     hipError_t e;
     if (L->sm_count == 0) {
         hipDeviceProp_t prop;
@@ -1229,7 +1281,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     // so the reuse wait never holds a workgroup in steady state; as grid is
     // at least one ring group, both lie in groups before the reuser's own.
     const int R = std::max(1, std::min(L->up_D + 2 * grid, nt));
-    const size_t ring_bytes = (size_t)R * Kmax * 9 * (4 * kNW) * 16 * sizeof(float);
+    const size_t ring_bytes = (size_t)R * Kmax * (lossy ? 12 : 9) * (4 * kNW) * 16 * sizeof(float);
     if (ring_bytes >= ((size_t)1 << 32)) return fail(lead, FDTD_EUNSUPPORTED, "systolic: face ring too large");
     if (ring_bytes > L->ring_bytes || !L->d_ring) {
         if (L->d_ring) (void)hipFree(L->d_ring);
@@ -1269,6 +1321,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
         memset(&P, 0, sizeof(P));
         for (int q = 0; q < 6; ++q) P.f[q] = c->field[q];
         for (int q = 0; q < 3; ++q) P.cE[q] = c->coef[q];
+        for (int q = 0; q < 3; ++q) P.ca[q] = c->ca[q];
         P.cH = c->cH;
         P.nx = c->nx;
         P.ny = c->ny;
@@ -1280,7 +1333,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
         P.nsrc = c->dev_sources_n;
         for (int d = 0; d < 3; ++d) {
             const int nd = d == 0 ? c->nx : (d == 1 ? c->ny : c->nz);
-            const int W = d == 1 ? 4 * kNW - 1 : WX;
+            const int W = d == 0 ? tile_x(c) : (d == 1 ? 4 * kNW - 1 : WZ);
             P.per[d] = c->sys->per[d];
             P.L[d] = c->sys->L[d];
             P.wr[d] = c->sys->per[d] ? nd - W * (c->sys->L[d] - 1) : W;
@@ -1366,10 +1419,6 @@ int systolic_supported(const fdtd_ctx* ctx, std::string* why)
         *why = "field arrays above 4 GiB are not supported by the systolic scheme";
         return 0;
     }
-    if (ctx->ca[0]) {
-        *why = "conductive (lossy) materials run on the plain scheme only in this build";
-        return 0;
-    }
     return 1;
 }
 
@@ -1381,9 +1430,9 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
 
 int systolic_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps) { return launch(ctxs, n, nsteps); }
 
-void systolic_tile(int* wx, int* wy, int* wz)
+void systolic_tile(const fdtd_ctx* ctx, int* wx, int* wy, int* wz)
 {
-    *wx = WX;
+    *wx = tile_x(ctx);
     *wy = 4 * kNW - 1;
     *wz = WZ;
 }

@@ -255,3 +255,22 @@ def small_case(shape, bc, seed: int, nsteps: int, n_boxes: int = 6, noise: float
     sources = [dipole(EZ, *p, wave) for p in dipoles]
     return Workload("small_%dx%dx%d_seed%d" % (tuple(shape) + (seed,)), tuple(shape), tuple(bc),
                     0.5, 1.0, nsteps, eps, tuple(f), sources)
+
+
+def graded_shell(shape, thickness: int = 16, sigma_max: float = 0.4) -> np.ndarray:
+    """Conductivity of a simple absorbing layer: zero inside, growing as the
+    square of the depth into a shell of ``thickness`` cells along every wall
+    up to ``sigma_max`` at the wall (one FP32 array for all three E
+    components).  Built plane by plane, so a full-size grid needs no
+    temporaries of its own size."""
+    nx, ny, nz = (int(s) for s in shape)
+    dist = [np.minimum(np.arange(n), n - 1 - np.arange(n)).astype(np.int32) for n in (nx, ny, nz)]
+    dyz = np.minimum(dist[1][:, None], dist[2][None, :])
+    ramp = np.where(np.arange(thickness + 1) < thickness,
+                    sigma_max * ((thickness - np.arange(thickness + 1)) / thickness) ** 2,
+                    0.0).astype(np.float32)
+    out = np.empty((nx, ny, nz), np.float32)
+    for i in range(nx):
+        d = np.minimum(dyz, dist[0][i])
+        out[i] = ramp[np.minimum(d, thickness)]
+    return out

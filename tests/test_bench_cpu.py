@@ -15,6 +15,10 @@ def test_systolic_bytes_per_update():
     # Section 4 accounting: (36 in + 24 out) * A / V + 60 / K
     assert bench.systolic_bytes_per_update((31, 15, 15), 64) == pytest.approx(10.873, abs=1e-3)
     assert bench.systolic_bytes_per_update((15, 15, 15), 32) == pytest.approx(12.0 + 60 / 32)
+    # conductive: 11-wide tile along x, ca travels with the leading faces
+    area = 15 * 15 + 2 * 11 * 15
+    assert bench.systolic_bytes_per_update((11, 15, 15), 16, True) == pytest.approx(
+        72 * area / (11 * 15 * 15) + 72 / 16)
     # the plain two-launch scheme moves 84 B per update
     assert bench.PLAIN_BYTES_PER_UPDATE == 84
 

@@ -1,6 +1,7 @@
-"""GPU parity of conductive (lossy) materials: the plain scheme's conductive
-E half-step against the FP32 lossy oracle, bit for bit; sigma = 0 through
-the lossy entry point equals the lossless path; the schemes and calls that
+"""GPU parity of conductive (lossy) materials: the conductive E half-step of
+both schemes (plain, and the systolic tile's 11-wide conductive variant)
+against the FP32 lossy oracle, bit for bit; sigma = 0 through the lossy entry
+point equals the lossless path; batches of conductive grids; the calls that
 do not cover conductivity refuse it."""
 import numpy as np
 import pytest
@@ -24,9 +25,11 @@ def _lossy_ref(w, sig, n):
                       dtype=np.float32, sigma=sig)
 
 
-def _sim(w, sig, device=False):
+def _sim(w, sig, device=False, scheme="plain", band=0):
     import torch
-    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="plain")
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme)
+    if band:
+        sim.set_option(fdtd.OPT_BAND_STEPS, band)
     if device:
         dev = torch.device("cuda:0")
         sim.set_materials(torch.from_numpy(w.eps).to(dev),
@@ -67,10 +70,60 @@ def test_absorbing_shell_bitwise_and_decay():
     got = sim.read_fields()
     sim.close()
     assert_bitwise(got, _lossy_ref(w, sig, 300), "absorber")
+    sim = _sim(w, sig, scheme="systolic")
+    sim.step(300)
+    assert sim.info(fdtd.INFO_TILE_X) == 11
+    assert_bitwise(sim.read_fields(), got, "absorber, systolic")
+    sim.close()
     ref0 = oracle_f32(w, 300)
     e_lossy = sum(float(np.sum(np.asarray(f, np.float64) ** 2)) for f in got)
     e_lossless = sum(float(np.sum(np.asarray(f, np.float64) ** 2)) for f in ref0)
     assert e_lossy < 0.5 * e_lossless
+
+
+# (shape, boundaries, band): several 11-wide x tiles with a ragged periodic
+# ring tile (35 = 3 * 11 + 2), short axes, several bands per call
+SYSTOLIC_CASES = [
+    ((33, 29, 40), (PEC, PEC, PEC), 0),
+    ((35, 29, 40), (PER, PER, PER), 0),
+    ((35, 31, 17), (PER, PEC, PER), 8),
+    ((23, 16, 45), (PEC, PER, PEC), 5),
+    ((12, 9, 7), (PEC, PEC, PEC), 0),
+]
+
+
+@pytest.mark.parametrize("shape,bc,band", SYSTOLIC_CASES)
+def test_lossy_systolic_bitwise(shape, bc, band):
+    w = wl.small_case(shape, bc, seed=sum(shape), nsteps=37,
+                      dipoles=[tuple(s // 2 for s in shape), (1, 1, 0)])
+    sig = _sigma(w.shape, sum(shape) + 1)
+    sim = _sim(w, sig, scheme="systolic", band=band)
+    sim.step(20)
+    sim.step(17)   # a second call continues the same state
+    assert sim.info(fdtd.INFO_TILE_X) == 11
+    assert_bitwise(sim.read_fields(), _lossy_ref(w, sig, 37), "lossy systolic %s %s" % (shape, bc))
+    sim.close()
+
+
+def test_lossy_batch_and_mixed_batch_refused():
+    ws = [wl.small_case(sh, bc, seed=30 + q, nsteps=19, dipoles=[tuple(s // 2 for s in sh)])
+          for q, (sh, bc, _) in enumerate(SYSTOLIC_CASES[:4])]
+    sigs = [_sigma(w.shape, 40 + q) for q, w in enumerate(ws)]
+    sims = [_sim(w, s, scheme="systolic") for w, s in zip(ws, sigs)]
+    lossless = fdtd.Simulation(ws[0].shape, ws[0].dt, ws[0].dx, ws[0].bc, scheme="systolic")
+    try:
+        lossless.set_materials(ws[0].eps)
+        with pytest.raises(fdtd.FdtdError) as e:
+            fdtd.step_batch([sims[0], lossless], 3)
+        assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+        assert sims[0].current_step == 0 and lossless.current_step == 0
+        fdtd.step_batch(sims, 19)
+        for w, sg, s in zip(ws, sigs, sims):
+            assert_bitwise(s.read_fields(), _lossy_ref(w, sg, 19), "lossy batch member %s" % (w.shape,))
+    finally:
+        lossless.close()
+        for s in sims:
+            s.close()
 
 
 def test_zero_conductivity_equals_lossless_and_back():
@@ -87,6 +140,15 @@ def test_zero_conductivity_equals_lossless_and_back():
     ref = oracle.run(w.fields, w.eps3(), w.bc, w.dt, w.dx, 25, step0=25, sources=w.sources,
                      dtype=np.float32)
     assert_bitwise(sim.read_fields(), ref, "lossless again")
+    # and conductive again on the systolic scheme: the launch plan follows
+    # the narrower conductive tile
+    sig = _sigma(w.shape, 13)
+    sim.set_materials(w.eps, sigma=sig)
+    sim.step(10)
+    assert sim.info(fdtd.INFO_TILE_X) == 11
+    ref2 = oracle.run(ref, w.eps3(), w.bc, w.dt, w.dx, 10, step0=50, sources=w.sources,
+                      dtype=np.float32, sigma=sig)
+    assert_bitwise(sim.read_fields(), ref2, "conductive systolic after lossless")
     sim.close()
 
 
@@ -94,13 +156,6 @@ def test_conductivity_is_refused_where_not_covered():
     w = wl.small_case((20, 20, 20), (PEC, PEC, PEC), seed=11, nsteps=4)
     sig = _sigma(w.shape, 12)
     sim = _sim(w, sig)
-    sim.set_option(fdtd.OPT_SCHEME, fdtd.SCHEME_SYSTOLIC)
-    with pytest.raises(fdtd.FdtdError) as e:
-        sim.step(2)
-    assert e.value.code == fdtd.FDTD_EUNSUPPORTED
-    with pytest.raises(fdtd.FdtdError) as e:
-        fdtd.step_batch([sim], 2)
-    assert e.value.code == fdtd.FDTD_EUNSUPPORTED
     with pytest.raises(fdtd.FdtdError) as e:
         sim.adjoint(2, 2, (10, 1, 1), (11, 9, 9), 0.5, (2, 2, 2), (5, 5, 5))
     assert e.value.code == fdtd.FDTD_EUNSUPPORTED

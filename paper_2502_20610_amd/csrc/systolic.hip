@@ -25,20 +25,25 @@
 //   modulo 16 on y and z, so cells never move between lanes.
 //
 // Faces: after each half-step a tile publishes the first layer of its
-// subdomain.  The x and y faces go straight into the field arrays at their
-// own coordinates (z-contiguous runs); the z face, which would be a strided
-// column in [x][y][z] memory, goes into a ring of per-ticket face buffers.
-// Published values stay where they are until the consumer has taken them,
-// because the next writer of a cell is its consumer.
+// subdomain (E and H; the z face also the coefficients) into per-ticket face
+// rings, one per face orientation, laid out so that every face is one
+// contiguous block per component.  A consumer assembles its forward shell
+// from up to seven upwind producers (edges and the corner come from the
+// diagonal neighbours).  The field arrays are read only when a band starts
+// and written only when it ends, so within a band every hand-off keeps full
+// precision whatever the arrays store.  A ring slot is reused R tickets
+// later, after its occupant's consumers have finished with it.
 //
 // Schedule: tickets (band, tile) in topological order (bands in order; in a
 // band, tiles by depth below the most upwind corner).  Workgroups take
-// tickets from an atomic counter; every wait targets an earlier ticket, so
-// the schedule cannot deadlock however many workgroups are resident.  Waits
-// are bounded: on expiry the kernel raises the error word and drains.
+// tickets from an atomic counter; every wait targets an earlier ticket or a
+// tile of the same periodic ring group (which must be resident together),
+// so the schedule cannot deadlock.  Waits are bounded: on expiry the kernel
+// raises the error word and drains.
 //
-// All axes must be PEC: cells outside the grid are ghosts that read as +0,
-// which reproduces the closed box of the periodic-index definition.
+// On PEC axes cells outside the grid are ghosts that read as +0, which
+// reproduces the closed box of the periodic-index definition; on periodic
+// axes the tiles form rings and positions wrap.
 #include <stdlib.h>
 #include <string.h>
 
@@ -88,8 +93,8 @@ struct SysArgs {
     int nt;
     const int* tix;    // ticket index of (band, tile)
     unsigned* progress;  // per ticket: last completed half-step level
-    float* ring;
-    unsigned ring_bytes;
+    float* ring[4];          // face rings: x, y and z faces (E, H); z-face coefficients
+    unsigned ring_bytes[4];
     int R, Kmax;   // ring slots; the longest band (the ring's slot stride)
     int nsteps;
     unsigned* counter;
@@ -330,9 +335,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const int ys = tid >> 4;        // y slot: 4 rows per wavefront, NW wavefronts
     const int zs = tid & 15;        // z slot: lane within the DPP row
     if (tid == 0) s_abort = 0;
-    const __amdgpu_buffer_rsrc_t rring = make_rsrc(A.ring, A.ring_bytes);
-    constexpr unsigned ring_step = (unsigned)NQA * PY * LS;  // floats per (slot, local step)
-    constexpr unsigned ring_comp = PY * LS;                  // floats per component
+    // Face rings, one per face orientation: per (slot, local step) the x
+    // face holds E and H as [comp][dy][dz] (the producer's own slots), the y
+    // face E and H as [comp][x register][dz], the z face E and H as
+    // [comp][next-box y slot][x register], and a fourth ring the z face's
+    // coefficients (cE, and ca) in the same layout.  Every ring holds at most
+    // six components per (slot, step), which keeps each within the 32-bit
+    // offsets of a buffer descriptor on large grids.
+    const __amdgpu_buffer_rsrc_t rrx = make_rsrc(A.ring[0], A.ring_bytes[0]);
+    const __amdgpu_buffer_rsrc_t rry = make_rsrc(A.ring[1], A.ring_bytes[1]);
+    const __amdgpu_buffer_rsrc_t rrz = make_rsrc(A.ring[2], A.ring_bytes[2]);
+    const __amdgpu_buffer_rsrc_t rrc = make_rsrc(A.ring[3], A.ring_bytes[3]);
+    constexpr unsigned ring_comp = PY * LS;      // floats per component
+    constexpr unsigned step_f = 6u * ring_comp;  // floats per (slot, local step): E and H
+    constexpr unsigned step_c = (unsigned)(NQA - 6) * ring_comp;  // the z face's coefficients
+    constexpr unsigned cb = ring_comp * 4u;      // bytes per component
 
     float E[3][PXk], H[3][PXk], C[3][PXk];
     float CA[LOSSY ? 3 : 1][PXk];  // conductive decay per cell (unused when lossless)
@@ -383,19 +400,23 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int me = t;  // progress counters are per ticket
         const int ox = a * WXk, oy = b * WY, oz = c * WZ;
 
-        // upwind neighbours that exist in this band
-        int ups[8];
+        // upwind neighbours that exist in this band, and the ring slot of
+        // each (d: bit 0 = +x, bit 1 = +y, bit 2 = +z; -1 when absent)
+        int ups[8], sl_up[8];
         int nup = 0;
+        sl_up[0] = -1;
 #pragma unroll
         for (int d = 1; d < 8; ++d) {
             const int ua = wrap_tile<PER>(P, 0, a + (d & 1)), ub = wrap_tile<PER>(P, 1, b + ((d >> 1) & 1)),
                       uc = wrap_tile<PER>(P, 2, c + ((d >> 2) & 1));
+            sl_up[d] = -1;
             if (band_has(bi, ua, ub, uc)) {
                 const int pi = ticket_of(A, bi, ua, ub, uc);
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
                     if (k == nup) ups[k] = pi;
                 ++nup;
+                sl_up[d] = pi % A.R;
             }
         }
 #pragma unroll
@@ -425,7 +446,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             if (!wait_tiles<DEV>(A, wl, nw, 2u * (unsigned)t0, &s_abort, nullptr)) break;
         }
         // ring slot reuse: the previous occupant has finished writing it and
-        // its consumer (the -z neighbour) has finished reading it
+        // its consumers (its downwind neighbours) have finished reading it
         const int slot = t % A.R;
         if (t >= A.R) {
             const int4 pk = A.tickets[t - A.R];
@@ -435,21 +456,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             int wl[8];
             wl[0] = t - A.R;
             int nw = 1;
-            const int pcm = wrap_tile<PER>(PP, 2, pk.w - 1);
-            if (band_has(pb, pk.y, pk.z, pcm)) {
-                wl[1] = ticket_of(A, pb, pk.y, pk.z, pcm);
-                nw = 2;
-            } else {
-                wl[1] = wl[0];
+#pragma unroll
+            for (int d = 1; d < 8; ++d) {
+                const int da = wrap_tile<PER>(PP, 0, pk.y - (d & 1)), db = wrap_tile<PER>(PP, 1, pk.z - ((d >> 1) & 1)),
+                          dc = wrap_tile<PER>(PP, 2, pk.w - ((d >> 2) & 1));
+                if (band_has(pb, da, db, dc)) {
+                    const int ci = ticket_of(A, pb, da, db, dc);
+#pragma unroll
+                    for (int k = 1; k < 8; ++k)
+                        if (k == nw) wl[k] = ci;
+                    ++nw;
+                }
             }
 #pragma unroll
-            for (int k = 2; k < 8; ++k) wl[k] = wl[0];
+            for (int k = 1; k < 8; ++k)
+                if (k >= nw) wl[k] = wl[0];
             if (!wait_tiles<DEV>(A, wl, nw, pend, &s_abort, nullptr)) break;
         }
+        // consumers of this tile's x, y and z faces in this band
+        const int has_xc = band_has(bi, wrap_tile<PER>(P, 0, a - 1), b, c);
+        const int has_yc = band_has(bi, a, wrap_tile<PER>(P, 1, b - 1), c);
         const int has_consumer = band_has(bi, a, b, wrap_tile<PER>(P, 2, c - 1));
-        const int czup = wrap_tile<PER>(P, 2, c + 1);
-        const int has_zup = band_has(bi, a, b, czup);
-        const int slot_zup = has_zup ? ticket_of(A, bi, a, b, czup) % A.R : 0;
         // updated cells per axis (the last tile of a periodic ring is ragged),
         // the lanes that take the forward y and z faces, and the tile frame
         // origin modulo n on periodic axes
@@ -548,8 +575,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const bool okz1 = axis_pos<PER>(Uz, Zw, P.nz, perz, dz1, z1);
             const bool okyz1 = oky1 && okz1;
             const unsigned yz1 = (unsigned)y1 * (unsigned)P.nz + (unsigned)z1;
-            const unsigned ring_base = ((unsigned)slot * (unsigned)A.Kmax + (unsigned)ls) * ring_step;
-            const unsigned ring_zup = ((unsigned)slot_zup * (unsigned)A.Kmax + (unsigned)ls) * ring_step;
+            // (slot, local step) index of this tile's faces, and of a producer's
+            const unsigned sls = (unsigned)slot * (unsigned)A.Kmax + (unsigned)ls;
+            auto sls_of = [&](int sl) { return (unsigned)sl * (unsigned)A.Kmax + (unsigned)ls; };
             // the forward y and z planes of the next box
             int yf, zf, zl;
             const bool oky_f = axis_pos<PER>(Uy, Yw, P.ny, pery, wyr, yf);
@@ -559,37 +587,54 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             (void)zf;
 
             // Issue the loads of the next box's forward shell for components
-            // [Q0, Q0 + NQ) (0..2 = E, 3..5 = H, 6..8 = cE): the x face into
-            // registers, the y and z faces straight into LDS.  Wavefront w
-            // loads rows 4w..4w+3 of every component of both faces.
+            // [Q0, Q0 + NQ) (0..2 = E, 3..5 = H, 6..8 = cE, 9..11 = ca)
+            // straight into LDS: E and H from the producers' face rings, the
+            // coefficients from their arrays.  Wavefront w loads rows
+            // 4w..4w+3 of every component of the three faces.
             auto prefetch = [&](auto q0c, auto nqc) {
                 constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
-                // x face: rows of the wavefront are y slots, lanes are z slots
+                // x face: rows of the wavefront are y slots, lanes are z
+                // slots.  The next box's slots dy1 < wyr, dz1 < wzr are the +x
+                // neighbour's cells (its slots dy1 + 1, dz1 + 1); dy1 == wyr
+                // (dz1 == wzr) is the first row (column) of the neighbour
+                // further along +y (+z).
                 int xf;
                 const bool okxf = axis_pos<PER>(Ux, Xw, P.nx, perx, wxr, xf);
                 const unsigned oxf = (okyz1 && okxf) ? ((unsigned)xf * plane + yz1) * 4u : kOOB;
-                // y face: rows of the wavefront are x, lanes are z
+                const bool fwy = dy1 == wyr, fwz = dz1 == wzr;
+                const int sx = fwy ? (fwz ? sl_up[7] : sl_up[3]) : (fwz ? sl_up[5] : sl_up[1]);
+                const bool okxr = okyz1 && okxf && dy1 <= wyr && dz1 <= wzr && sx >= 0;
+                const unsigned oxr = (sls_of(sx) * step_f + (unsigned)(fwy ? 1 : dy1 + 1) * LS +
+                                      (unsigned)(fwz ? 1 : dz1 + 1)) * 4u;
+                // y face: rows of the wavefront are x registers, lanes are z;
+                // the +y neighbour's (or, on the forward z lane, the +y+z
+                // neighbour's) first y row
                 const int j = 4 * w + r;
                 const bool ydo = YR == PY || 4 * w < YR;  // wavefront-uniform
                 int x;
-                const bool okx = (!LOSSY || j < WXk) && axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
+                const bool okx = j < WXk && axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
                 const unsigned oyf = (oky_f && okz_l && okx)
                                          ? (((unsigned)x * (unsigned)P.ny + (unsigned)yf) * (unsigned)P.nz + (unsigned)zl) * 4u
                                          : kOOB;
+                const bool fwzl = dz1 == wzr;
+                const int sy = fwzl ? sl_up[6] : sl_up[2];
+                const bool okyr = oky_f && okz_l && okx && dz1 <= wzr && sy >= 0;
+                const unsigned oyr = (sls_of(sy) * step_f + (unsigned)j * LS + (unsigned)(fwzl ? 1 : dz1 + 1)) * 4u;
                 // z face: rows are y, lanes are x, from the +z neighbour's ring slot
                 const int yy = 4 * w + r;
                 int xr, yr;
-                const bool okz = has_zup && okz_f && zs < WXk && yy < WY &&
+                const bool okz = sl_up[4] >= 0 && okz_f && zs < WXk && yy < WY &&
                                  axis_pos<PER>(Ux, Xw, P.nx, perx, zs, xr) &&
                                  axis_pos<PER>(Uy, Yw, P.ny, pery, yy, yr);
-                const unsigned ozf = (ring_zup + (unsigned)yy * LS + (unsigned)zs) * 4u;
+                const unsigned ozf = (sls_of(sl_up[4]) * step_f + (unsigned)yy * LS + (unsigned)zs) * 4u;
+                const unsigned ozc = (sls_of(sl_up[4]) * step_c + (unsigned)yy * LS + (unsigned)zs) * 4u;
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) {
                     const unsigned ly = lds_offset(&yst[q][ydo ? 4 * w : 0][0]);
                     const unsigned lx = lds_offset(&xst[q][4 * w][0]);
                     if (q < 6) {
-                        dma_dword<DEV>(rf[q], lx, oxf);
-                        if (ydo) dma_dword<DEV>(rf[q], ly, oyf);
+                        dma_dword<DEV>(rrx, lx, okxr ? oxr + (unsigned)q * cb : kOOB);
+                        if (ydo) dma_dword<DEV>(rry, ly, okyr ? oyr + (unsigned)q * cb : kOOB);
                     } else if (q < 9) {
                         dma_dword<false>(rc[q - 6], lx, oxf);
                         if (ydo) dma_dword<false>(rc[q - 6], ly, oyf);
@@ -597,8 +642,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         dma_dword<false>(rca[q - 9], lx, oxf);
                         if (ydo) dma_dword<false>(rca[q - 9], ly, oyf);
                     }
-                    dma_dword<DEV>(rring, lds_offset(&zst[q][4 * w][0]),
-                                   okz ? ozf + (unsigned)q * ring_comp * 4u : kOOB);
+                    if (q < 6)
+                        dma_dword<DEV>(rrz, lds_offset(&zst[q][4 * w][0]), okz ? ozf + (unsigned)q * cb : kOOB);
+                    else
+                        dma_dword<DEV>(rrc, lds_offset(&zst[q][4 * w][0]), okz ? ozc + (unsigned)(q - 6) * cb : kOOB);
                 }
             };
             // Write the staged first-layer faces for components [Q0, Q0+NQ)
@@ -609,22 +656,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 constexpr int NQZ = decltype(nqzc)::value;
                 lds_barrier();
                 const int j = 4 * w + r;
-                // y face at y = oy + tau: cells inside the tile only
+                // y face (the first y row) as [x register][dz]
                 const int dzl = (zs - oz - tau + 1) & (PZ - 1);
-                int xs_, ys_, zz;
-                const bool in = j < wxr && dzl >= 1 && dzl <= wzr &&
-                                axis_pos<PER>(Ux, Xw, P.nx, perx, j, xs_) &&
-                                axis_pos<PER>(Uy, Yw, P.ny, pery, 0, ys_) &&
-                                axis_pos<PER>(Uz, Zw, P.nz, perz, dzl - 1, zz);
-                const unsigned o = in ? ((((unsigned)xs_) * (unsigned)P.ny + (unsigned)ys_) *
-                                         (unsigned)P.nz + (unsigned)zz) * 4u : kOOB;
+                const bool oky_ = has_yc && j < WXk;
+                const unsigned oy_ = (sls * step_f + (unsigned)j * LS + (unsigned)dzl) * 4u;
 #pragma unroll
-                for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rf[q], o, ytr[q][j][zs]);
+                for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rry, oky_ ? oy_ + (unsigned)q * cb : kOOB, ytr[q][j][zs]);
                 // (dropped offsets when there is no consumer: no branch)
-                const unsigned oz_ = (ring_base + (unsigned)j * LS + (unsigned)zs) * 4u;
+                const unsigned oz_ = (sls * step_f + (unsigned)j * LS + (unsigned)zs) * 4u;
+                const unsigned oc_ = (sls * step_c + (unsigned)j * LS + (unsigned)zs) * 4u;
 #pragma unroll
-                for (int q = Q0; q < Q0 + NQZ; ++q)
-                    bst<SP>(rring, has_consumer ? oz_ + (unsigned)q * ring_comp * 4u : kOOB, ztr[q][j][zs]);
+                for (int q = Q0; q < Q0 + NQZ; ++q) {
+                    if (q < 6)
+                        bst<SP>(rrz, has_consumer ? oz_ + (unsigned)q * cb : kOOB, ztr[q][j][zs]);
+                    else
+                        bst<SP>(rrc, has_consumer ? oc_ + (unsigned)(q - 6) * cb : kOOB, ztr[q][j][zs]);
+                }
             };
             auto ensure_up = [&](unsigned level) -> bool {
                 if (s_up >= level) return true;
@@ -705,12 +752,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
 #undef FDTD_APPLY_SOURCE
 
-            // publish E of the first layer of the tile
-            {
-                const unsigned o = inB ? off_at(0) : kOOB;
+            // E of the first x layer of the tile (every lane: slot [dy][dz])
+            const unsigned ox_ = (sls * step_f + (unsigned)dy * LS + (unsigned)dz) * 4u;
 #pragma unroll
-                for (int q = 0; q < 3; ++q) bst<SP>(rf[q], o, E[q][0]);
-            }
+            for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)q * cb : kOOB, E[q][0]);
             if (dy == 1) {
 #pragma unroll
                 for (int j = 0; j < WXk; ++j)
@@ -789,12 +834,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
             // now H registers j <-> x = ox+tau+j as well
 
-            // publish H (and, on the z face, the coefficients) of the first layer
-            {
-                const unsigned o = inB ? off_at(0) : kOOB;
+            // H (and, on the z face, the coefficients) of the first layer
 #pragma unroll
-                for (int q = 0; q < 3; ++q) bst<SP>(rf[3 + q], o, H[q][0]);
-            }
+            for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)(3 + q) * cb : kOOB, H[q][0]);
             if (dy == 1) {
 #pragma unroll
                 for (int j = 0; j < WXk; ++j)
@@ -1172,20 +1214,26 @@ int upload_plan(fdtd_ctx* lead, SystolicState* L, fdtd_ctx* const* cs, int n)
         for (size_t q = 0; q < si->band.size(); ++q)
             band[band_base[i] + q] = si->band[q] + (q % 8 == 6 ? (int)tix_base[i] : 0);
     }
-    // largest distance (in tickets) from a face producer to its -z consumer,
-    // and the largest ring group
+    // largest distance (in tickets) from a face producer to one of its
+    // consumers (the downwind neighbours), and the largest ring group
     int D = 1, group = 1;
     for (int i = 0; i < n; ++i) group = std::max(group, cs[i]->sys->group);
     for (size_t t = 0; t < nt; ++t) {
         const SystolicState* si = cs[tsim[t]]->sys;
         const int4 q = tk[t];
         const int* bi = &band[band_base[tsim[t]] + 8 * (size_t)q.x];
-        int cm = q.w - 1;
-        if (si->per[2]) cm = ((cm % si->L[2]) + si->L[2]) % si->L[2];
-        if (cm < bi[4]) continue;
         const int nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
-        const int j = tix[(size_t)bi[6] + ((size_t)(q.y - bi[0]) * nbb + (q.z - bi[2])) * nc + (cm - bi[4])];
-        D = std::max(D, j - (int)t + 1);
+        for (int d = 1; d < 8; ++d) {
+            int v[3] = {q.y - (d & 1), q.z - ((d >> 1) & 1), q.w - ((d >> 2) & 1)};
+            bool in = true;
+            for (int k = 0; k < 3; ++k) {
+                if (si->per[k]) v[k] = ((v[k] % si->L[k]) + si->L[k]) % si->L[k];
+                in = in && v[k] >= bi[2 * k] && v[k] <= bi[2 * k + 1];
+            }
+            if (!in) continue;
+            const int j = tix[(size_t)bi[6] + ((size_t)(v[0] - bi[0]) * nbb + (v[1] - bi[2])) * nc + (v[2] - bi[4])];
+            D = std::max(D, j - (int)t + 1);
+        }
     }
     int rc;
     if ((rc = ensure_buffer(lead, &L->d_tickets, &L->cap_tickets, nt, "tickets")) ||
@@ -1276,13 +1324,21 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
                     "systolic: a periodic ring group of " + std::to_string(L->up_group) +
                         " tiles needs as many resident workgroups (grid " + std::to_string(grid) + ")");
     // Face ring: a slot is reused R tickets later, after its previous
-    // occupant and that occupant's consumer have finished.  R = D + 2 * grid
-    // keeps those two long finished by the time the slot comes round again,
+    // occupant and that occupant's consumers have finished.  R = D + 2 * grid
+    // keeps those long finished by the time the slot comes round again,
     // so the reuse wait never holds a workgroup in steady state; as grid is
     // at least one ring group, both lie in groups before the reuser's own.
     const int R = std::max(1, std::min(L->up_D + 2 * grid, nt));
-    const size_t ring_bytes = (size_t)R * Kmax * (lossy ? 12 : 9) * (4 * kNW) * 16 * sizeof(float);
-    if (ring_bytes >= ((size_t)1 << 32)) return fail(lead, FDTD_EUNSUPPORTED, "systolic: face ring too large");
+    // four face rings in one allocation (x, y, z faces of E and H; the z
+    // face's coefficients), each addressed with 32-bit offsets
+    const size_t face = (size_t)(4 * kNW) * 16 * sizeof(float);  // one component of one face
+    const size_t rf6 = (size_t)R * Kmax * 6 * face;
+    const size_t rb[4] = {rf6, rf6, rf6, (size_t)R * Kmax * (lossy ? 6 : 3) * face};
+    if (rf6 >= ((size_t)1 << 32))
+        return fail(lead, FDTD_EUNSUPPORTED,
+                    "systolic: face ring too large for 32-bit offsets (" + std::to_string(R) + " slots of " +
+                        std::to_string(Kmax) + " steps); a shorter band (FDTD_OPT_BAND_STEPS) shrinks it");
+    const size_t ring_bytes = rb[0] + rb[1] + rb[2] + rb[3];
     if (ring_bytes > L->ring_bytes || !L->d_ring) {
         if (L->d_ring) (void)hipFree(L->d_ring);
         L->d_ring = nullptr;
@@ -1368,8 +1424,12 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     A.nt = nt;
     A.tix = L->d_tix;
     A.progress = L->d_progress;
-    A.ring = L->d_ring;
-    A.ring_bytes = (unsigned)L->ring_bytes;
+    size_t roff = 0;
+    for (int f = 0; f < 4; ++f) {
+        A.ring[f] = L->d_ring + roff / sizeof(float);
+        A.ring_bytes[f] = (unsigned)rb[f];
+        roff += rb[f];
+    }
     A.R = R;
     A.Kmax = Kmax;
     A.nsteps = (int)nsteps;

@@ -3,9 +3,11 @@
 It reproduces, with numpy float32 arithmetic on whole boxes, the data flow of
 the persistent systolic kernel: the tile plan, the per-tile slot box that
 moves one cell along the x-y-z-t diagonal per step, the faces ("trails")
-published to the field arrays (x and y faces) and to a per-ticket z-face ring,
-the forward-shell loads, the neighbour progress counters and the waits on them,
-the band starts and ends, and the ring-slot reuse waits.  Tickets run as
+published to per-ticket face rings (one per face orientation), the
+forward-shell loads that assemble each face from up to four producers (edges
+and corners come from the diagonal neighbours), the neighbour progress
+counters and the waits on them, the band starts and ends (the only accesses
+of the field arrays), and the ring-slot reuse waits.  Tickets run as
 coroutines that yield at every wait; a seeded scheduler interleaves up to
 ``resident`` of them at random (tickets are dequeued in order, as by the
 kernel's atomic ticket counter).  A missing or misplaced wait shows up as a
@@ -75,14 +77,19 @@ def wrap_tile(t, L):
     return tuple(x % l if l is not None else x for x, l in zip(t, L))
 
 
+# offsets of the seven downwind (consumer) and upwind (producer) neighbours
+DOWN = [(-dx, -dy, -dz) for dx in (0, 1) for dy in (0, 1) for dz in (0, 1) if (dx, dy, dz) != (0, 0, 0)]
+
+
 def ring_depth(tickets, ticket_of, L=(None, None, None)):
-    """Smallest ring size R such that the consumer of ticket t (its -z
-    neighbour in the same band) has index < t + R."""
+    """Smallest ring size R such that every consumer of ticket t (its
+    downwind neighbours in the same band) has index < t + R."""
     R = 1
     for i, (band, a, b, c) in enumerate(tickets):
-        j = ticket_of.get((band,) + wrap_tile((a, b, c - 1), L))
-        if j is not None:
-            R = max(R, j - i + 1)
+        for d in DOWN:
+            j = ticket_of.get((band,) + wrap_tile((a + d[0], b + d[1], c + d[2]), L))
+            if j is not None:
+                R = max(R, j - i + 1)
     return R
 
 
@@ -105,12 +112,15 @@ class Machine:
         self.L = ring_tiles(shape, W, self.per)
         self.tickets, self.ranges, self.ticket_of = plan(shape, W, K, nsteps, self.per)
         # a slot is reused R tickets later, after its previous occupant and that
-        # occupant's consumer have finished their band; with R beyond the ring
-        # depth plus one ring group, both lie in groups before the reuser's own
+        # occupant's consumers have finished their band; with R beyond the ring
+        # depth plus one ring group, all lie in groups before the reuser's own
         self.group = int(np.prod([l for l in self.L if l is not None]))
         self.R = ring_depth(self.tickets, self.ticket_of, self.L) + self.group - 1 + ring_slack
         Wx, Wy, Wz = W
-        # ring: [slot][local step][9 values][Wx][Wy]; values: Ex Ey Ez Hx Hy Hz cEx cEy cEz
+        # face rings per [slot][local step][value]: x face [Wy][Wz] and y face
+        # [Wx][Wz] of Ex Ey Ez Hx Hy Hz; z face [Wx][Wy] of those and cEx cEy cEz
+        self.xring = np.full((self.R, K, 6, Wy, Wz), np.nan, dtype=F32)
+        self.yring = np.full((self.R, K, 6, Wx, Wz), np.nan, dtype=F32)
         self.ring = np.full((self.R, K, 9, Wx, Wy), np.nan, dtype=F32)
         self.progress = {}
         self.reads_before_ready = 0
@@ -183,15 +193,17 @@ class Machine:
                 if u is not None:
                     yield from self.wait(u, 2 * t0)
         # ring slot reuse: the previous occupant of the slot has finished
-        # writing it and its consumer (the -z neighbour) has finished reading it
+        # writing it and its consumers (its downwind neighbours) have finished
+        # reading it
         slot = t % self.R
         if t >= self.R:
             pb, pa, pbb, pc = self.tickets[t - self.R]
             pend = 2 * min(self.nsteps, (pb + 1) * K)
             yield from self.wait((pa, pbb, pc), pend)
-            cons = self.tile(pb, pa, pbb, pc - 1)
-            if cons is not None:
-                yield from self.wait(cons, pend)
+            for d in DOWN:
+                cons = self.tile(pb, pa + d[0], pbb + d[1], pc + d[2])
+                if cons is not None:
+                    yield from self.wait(cons, pend)
         ox, oy, oz = a * Wx, b * Wy, c * Wz
         # slot box of step t0 + 1: lower corner (ox + t0, ...), size W + 1
         lo = (ox + t0, oy + t0, oz + t0)
@@ -223,8 +235,7 @@ class Machine:
                     arr = S[src["comp"]]
                     q = (p[0] + 1, p[1] + 1, p[2] + 1)
                     arr[q] = F32(arr[q] + F32(src["waveform"][m]))
-            # publish E of the first layer of B: x and y faces to the field
-            # arrays, z face to the ring
+            # publish E of the first layer of B to the face rings
             self._publish(S, C, blo, slot, tau - t0 - 1, comps=(0, 1, 2))
             self.progress[me] = 2 * tau - 1
             yield "E"
@@ -265,50 +276,72 @@ class Machine:
         y[:-1, :-1, :-1] = x[1:, 1:, 1:]
         return y
 
+    def _faces(self, B, slot, ls, q):
+        """The three first-layer faces of B (shape wx, wy, wz) into the rings."""
+        wx, wy, wz = B.shape
+        self.xring[slot, ls, q, :wy, :wz] = B[0, :, :]
+        self.yring[slot, ls, q, :wx, :wz] = B[:, 0, :]
+        self.ring[slot, ls, q, :wx, :wy] = B[:, :, 0]
+
     def _publish(self, S, C, blo, slot, ls, comps):
         """E of the first layer of B (box index 1 on each axis, before the shift)."""
         for q in comps:
-            B = S[q][1:, 1:, 1:]
-            # x face: x = blo[0], all (y, z) of B
-            self.store_box(self.f[q], blo, B[0:1, :, :])
-            # y face: y = blo[1]
-            self.store_box(self.f[q], blo, B[:, 0:1, :])
-            # z face -> ring
-            self.ring[slot, ls, q, :B.shape[0], :B.shape[1]] = B[:, :, 0]
+            self._faces(S[q][1:, 1:, 1:], slot, ls, q)
 
     def _publish_shifted(self, S, C, blo, slot, ls):
         """H of the first layer of B after the shift (box index 0 on each axis)."""
         for q in (3, 4, 5):
-            B = S[q][:-1, :-1, :-1]
-            self.store_box(self.f[q], blo, B[0:1, :, :])
-            self.store_box(self.f[q], blo, B[:, 0:1, :])
-            self.ring[slot, ls, q, :B.shape[0], :B.shape[1]] = B[:, :, 0]
+            self._faces(S[q][:-1, :-1, :-1], slot, ls, q)
         for q in range(3):
             cq = C[q][:-1, :-1, 0]
             self.ring[slot, ls, 6 + q, :cq.shape[0], :cq.shape[1]] = cq
 
+    def _slot(self, band, a, b, c):
+        t = self.tile(band, a, b, c)
+        return self.ticket_of[(band,) + t] % self.R if t is not None else None
+
     def _load_forward(self, S, C, nlo, band, tile, ls, comps, coef=False):
-        """Load the forward shell of the box whose lower corner is nlo."""
+        """Load the forward shell of the box whose lower corner is nlo: E and
+        H from the producers' face rings, the coefficients from their arrays."""
         Wx, Wy, Wz = self.widths(tile)
         a, b, c = tile
         X, Y, Z = nlo[0] + Wx, nlo[1] + Wy, nlo[2] + Wz
-        arrs = [(S[q], self.f[q], q) for q in comps]
+        _, mx = self._box_index((X, nlo[1], nlo[2]), (1, Wy + 1, Wz + 1))
+        _, my = self._box_index((nlo[0], Y, nlo[2]), (Wx, 1, Wz + 1))
+        _, mz = self._box_index((nlo[0], nlo[1], Z), (Wx, Wy, 1))
+        # the +x neighbours: own rows and columns from (a+1, b, c); the
+        # forward row, column and corner from the first row / column of the
+        # +x+y, +x+z and +x+y+z neighbours
+        parts_x = [((0, 0), slice(0, Wy), slice(0, Wz), slice(0, Wy), slice(0, Wz)),
+                   ((1, 0), slice(Wy, Wy + 1), slice(0, Wz), slice(0, 1), slice(0, Wz)),
+                   ((0, 1), slice(0, Wy), slice(Wz, Wz + 1), slice(0, Wy), slice(0, 1)),
+                   ((1, 1), slice(Wy, Wy + 1), slice(Wz, Wz + 1), slice(0, 1), slice(0, 1))]
+        parts_y = [(0, slice(0, Wz), slice(0, Wz)), (1, slice(Wz, Wz + 1), slice(0, 1))]
+        zslot = self._slot(band, a, b, c + 1)
+        for q in comps:
+            box = S[q]
+            vx = np.zeros((Wy + 1, Wz + 1), F32)
+            for (dy, dz), ry, rz, sy, sz in parts_x:
+                sl = self._slot(band, a + 1, b + dy, c + dz)
+                if sl is not None:
+                    vx[ry, rz] = self.xring[sl, ls, q, sy, sz]
+            box[-1, :, :] = np.where(mx[0], vx, F32(0))
+            vy = np.zeros((Wx, Wz + 1), F32)
+            for dz, rz, sz in parts_y:
+                sl = self._slot(band, a, b + 1, c + dz)
+                if sl is not None:
+                    vy[:, rz] = self.yring[sl, ls, q, :Wx, sz]
+            box[:-1, -1, :] = np.where(my[:, 0, :], vy, F32(0))
+            vz = self.ring[zslot, ls, q, :Wx, :Wy] if zslot is not None else np.zeros((Wx, Wy), F32)
+            box[:-1, :-1, -1] = np.where(mz[:, :, 0], vz, F32(0))
         if coef:
-            arrs += [(C[q], self.cE[q], 6 + q) for q in range(3)]
-        zt = self.tile(band, a, b, c + 1)
-        zslot = self.ticket_of[(band,) + zt] % self.R if zt is not None else None
-        for box, src, q in arrs:
-            # x plane: all (y, z) of the box at x = X
-            box[-1:, :, :] = self.load_box(src, (X, nlo[1], nlo[2]), (1, Wy + 1, Wz + 1))
-            # y plane: x < X, y = Y
-            box[:-1, -1:, :] = self.load_box(src, (nlo[0], Y, nlo[2]), (Wx, 1, Wz + 1))
-            # z plane: x < X, y < Y, z = Z, from the +z neighbour's ring slot
-            if zslot is None:
-                vals = np.zeros((Wx, Wy), F32)
-            else:
-                vals = self.ring[zslot, ls, q, :Wx, :Wy]
-            _, mask = self._box_index((nlo[0], nlo[1], Z), (Wx, Wy, 1))
-            box[:-1, :-1, -1] = np.where(mask[:, :, 0], vals, F32(0))
+            for q in range(3):
+                box = C[q]
+                box[-1:, :, :] = self.load_box(self.cE[q], (X, nlo[1], nlo[2]), (1, Wy + 1, Wz + 1))
+                box[:-1, -1:, :] = self.load_box(self.cE[q], (nlo[0], Y, nlo[2]), (Wx, 1, Wz + 1))
+                vz = (self.ring[zslot, ls, 6 + q, :Wx, :Wy] if zslot is not None
+                      else np.zeros((Wx, Wy), F32))
+                box[:-1, :-1, -1] = np.where(mz[:, :, 0], vz, F32(0))
 
     # ---- scheduler --------------------------------------------------------
     def run(self, resident=4, seed=0):

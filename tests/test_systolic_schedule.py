@@ -187,3 +187,23 @@ def test_crop_oracle_reproduces_full_runs():
         ref = crop_oracle(w, p, 6)
         val = np.array([f[p] for f in full], np.float32)
         np.testing.assert_array_equal(ref.view(np.uint32), val.view(np.uint32), err_msg=str(p))
+
+
+def test_emulator_detects_a_missing_reuse_wait(monkeypatch):
+    """Sanity of the harness: a ring slot reused after waiting only for the
+    occupant's -z consumer (not the diagonal consumers that take the x- and
+    y-face edges) is overwritten early in some interleaving."""
+    shape, W, K, n = (12, 12, 12), (3, 3, 3), 4, 8
+    w = wl.small_case(shape, (PEC, PEC, PEC), seed=6, nsteps=n)
+    ref = _oracle(w, n)
+    cE, cH = _coeffs(w)
+    def run(seed, only_z):
+        m = emu.Machine(w.fields, cE, cH, shape, W, K, n)   # R sized for all consumers
+        if only_z:
+            monkeypatch.setattr(emu, "DOWN", [(0, 0, -1)])
+        got = m.run(resident=200, seed=seed)
+        monkeypatch.undo()
+        return any(not np.array_equal(np.nan_to_num(got[c]), ref[c]) for c in range(6))
+    bad = [s for s in range(8) if run(s, True)]
+    assert bad
+    assert not run(bad[0], False)

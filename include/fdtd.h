@@ -28,8 +28,26 @@
  *                        boundary faces through device memory, synchronising
  *                        with neighbour flags (Sections 3 and 4).
  *
- * Layout: every field and coefficient array is FP32, C order [nx][ny][nz]
- * (z fastest), one array per component (Ex, Ey, Ez, Hx, Hy, Hz).
+ * Layout: every field and coefficient array is C order [nx][ny][nz]
+ * (z fastest), one array per component (Ex, Ey, Ez, Hx, Hy, Hz); FP32, or
+ * IEEE binary16 inside the library with FP16 storage (the ABI always passes
+ * FP32).
+ *
+ * FP16 storage (fdtd_config.storage = FDTD_FP16_STORAGE; Section 4 stores the
+ * field values in 16-bit floating point): the device arrays hold binary16,
+ * field component c as v * 2^-e_c (fdtd_set_field_scale, default e_c = 0)
+ * and cE rounded from its FP32 value; every operation still computes in FP32
+ * exactly as above.  A stored value is rounded once, to nearest even (the
+ * scales are powers of two, so scaling is exact; out-of-range values become
+ * +-inf or binary16 subnormals/zero).  Rounding happens where a value is
+ * stored: on input (fdtd_set_fields), and
+ *   - plain scheme: after every E half-step, after each source addition, and
+ *     after every H half-step;
+ *   - systolic scheme: once per band of K steps (and at the end of every
+ *     call), for the whole grid; every exchange between tiles inside a band
+ *     keeps FP32.
+ * fdtd_read_fields returns the stored values times 2^e_c, exactly.  With FP16
+ * storage, conductive materials and fdtd_adjoint return FDTD_EUNSUPPORTED. 
  *
  * Boundaries: indices are periodic on every axis; a PEC axis additionally
  * holds the two E components tangential to its planes at +0 on its index-0
@@ -82,7 +100,7 @@ typedef struct {
                               both > 0, with dt*sqrt(3) < dx (Courant for eps>=1) */
     int32_t bc[3];         /* FDTD_BC_PEC or FDTD_BC_PERIODIC for x, y, z        */
     int32_t scheme;        /* FDTD_SCHEME_*                                      */
-    int32_t storage;       /* FDTD_FP32 (FDTD_FP16_STORAGE: FDTD_EUNSUPPORTED)   */
+    int32_t storage;       /* FDTD_FP32 or FDTD_FP16_STORAGE                     */
     int32_t device;        /* HIP device ordinal                                 */
     void* stream;          /* hipStream_t to run on; NULL = a stream the library
                               creates (default priority) and destroys           */
@@ -125,6 +143,14 @@ int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
 int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
                              const float* eps_z, const float* sigma_x, const float* sigma_y,
                              const float* sigma_z, int where);
+
+/* FP16 storage only (else FDTD_EINVAL): set the power-of-two scale of each
+ * field component, component c being stored as v * 2^-exp2[c], exp2[c] in
+ * [-30, 30].  The current field values are re-encoded under the new scales
+ * (exact while they stay within the binary16 range).  Choosing e_c near
+ * log2 of a component's peak magnitude keeps it away from binary16's
+ * overflow (65504) and subnormal (< 6.1e-5) ranges. */
+int fdtd_set_field_scale(fdtd_ctx* ctx, const int32_t exp2[6]);
 
 /* Set the components selected by comp_mask (bit c = component c) from
  * src[c] (nx*ny*nz floats each; src entries for unselected components are

@@ -15,6 +15,7 @@ coeff_E(eps, bc, dt, dx)           -> (cEx, cEy, cEz) in float64
 coeff_lossy(eps, sigma, bc, dt, dx) -> ((caX, caY, caZ), (cbX, cbY, cbZ)) in float64
 step(cE, cH, fields, nsteps, ...)  -> advances six fields in place (f64 or f32)
 step_lossy(ca, cb, cH, fields, ...) -> the same with conductivity
+half_E(cE, fields), half_H(cH, fields) -> one FP32 half-step in place (no sources)
 run(fields, eps, bc, dt, dx, ...)  -> convenience: coefficients + steps (sigma optional)
 
 Field tuples are always ordered (Ex, Ey, Ez, Hx, Hy, Hz); arrays are C-ordered
@@ -81,6 +82,10 @@ def _load():
             f.argtypes = [ctypes.c_int] * 3 + [P] * 6 + [S] + [P] * 6 + [
                 ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Source), ctypes.c_int]
             f.restype = None
+        lib.oracle_half_E_f32.argtypes = [ctypes.c_int] * 3 + [fp] * 9
+        lib.oracle_half_E_f32.restype = None
+        lib.oracle_half_H_f32.argtypes = [ctypes.c_int] * 3 + [ctypes.c_float] + [fp] * 6
+        lib.oracle_half_H_f32.restype = None
         lib.oracle_round_f32.argtypes = [dp, fp, ctypes.c_int64]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -205,6 +210,32 @@ def step_lossy(ca, cb, cH, fields, nsteps: int, step0: int = 0, sources=(), dtyp
     fn(nx, ny, nz, *[_ptr(c, ct) for c in ca], *[_ptr(c, ct) for c in cb], ct(cH),
        *[_ptr(f, ct) for f in fields], int(nsteps), int(step0), src, len(sources))
     del keep
+    return fields
+
+
+def _check32(arrays, shape):
+    for a in arrays:
+        if a.dtype != np.float32 or a.shape != shape or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous float32 of shape %s" % (shape,))
+
+
+def half_E(cE, fields):
+    """One FP32 E half-step in place (the first half of :func:`step`, no sources)."""
+    lib = _load()
+    nx, ny, nz = fields[0].shape
+    _check32(list(cE) + list(fields), (nx, ny, nz))
+    fp = ctypes.c_float
+    lib.oracle_half_E_f32(nx, ny, nz, *[_ptr(c, fp) for c in cE], *[_ptr(f, fp) for f in fields])
+    return fields
+
+
+def half_H(cH, fields):
+    """One FP32 H half-step in place (the second half of :func:`step`)."""
+    lib = _load()
+    nx, ny, nz = fields[0].shape
+    _check32(list(fields), (nx, ny, nz))
+    fp = ctypes.c_float
+    lib.oracle_half_H_f32(nx, ny, nz, ctypes.c_float(cH), *[_ptr(f, fp) for f in fields])
     return fields
 
 

@@ -103,13 +103,8 @@ void oracle_coeff_E(int nx, int ny, int nz, const int32_t bc[3], double dt, doub
             }                                                                             \
         }
 
-#define DEFINE_STEP(T, NAME)                                                              \
-void NAME(int nx, int ny, int nz, const T* cEx, const T* cEy, const T* cEz, T cH,         \
-          T* Ex, T* Ey, T* Ez, T* Hx, T* Hy, T* Hz, int64_t nsteps, int64_t step0,         \
-          const oracle_source* src, int nsrc)                                             \
-{                                                                                         \
-    for (int64_t s = step0; s < step0 + nsteps; ++s) {                                    \
-        /* E half-step: reads H at the backward neighbours */                             \
+/* E half-step: reads H at the backward neighbours. */
+#define E_HALF_STEP(T)                                                                    \
         _Pragma("omp parallel for schedule(static)")                                      \
         for (int i = 0; i < nx; ++i) {                                                    \
             int im = (i == 0) ? nx - 1 : i - 1;                                           \
@@ -130,7 +125,15 @@ void NAME(int nx, int ny, int nz, const T* cEx, const T* cEy, const T* cEz, T cH
                     Ez[p] = a - b;                                                        \
                 }                                                                         \
             }                                                                             \
-        }                                                                                 \
+        }
+
+#define DEFINE_STEP(T, NAME)                                                              \
+void NAME(int nx, int ny, int nz, const T* cEx, const T* cEy, const T* cEz, T cH,         \
+          T* Ex, T* Ey, T* Ez, T* Hx, T* Hy, T* Hz, int64_t nsteps, int64_t step0,         \
+          const oracle_source* src, int nsrc)                                             \
+{                                                                                         \
+    for (int64_t s = step0; s < step0 + nsteps; ++s) {                                    \
+        E_HALF_STEP(T)                                                                    \
         /* soft sources, after the E half-step */                                         \
         for (int q = 0; q < nsrc; ++q) {                                                  \
             int64_t m = s - src[q].first_step;                                            \
@@ -145,6 +148,21 @@ void NAME(int nx, int ny, int nz, const T* cEx, const T* cEy, const T* cEz, T cH
 
 DEFINE_STEP(double, oracle_step_f64)
 DEFINE_STEP(float, oracle_step_f32)
+
+/* The two half-steps on their own (no sources), for callers that act on the
+ * state between them (the FP16-storage rounding of the plain scheme). */
+void oracle_half_E_f32(int nx, int ny, int nz, const float* cEx, const float* cEy,
+                       const float* cEz, float* Ex, float* Ey, float* Ez, const float* Hx,
+                       const float* Hy, const float* Hz)
+{
+    E_HALF_STEP(float)
+}
+
+void oracle_half_H_f32(int nx, int ny, int nz, float cH, const float* Ex, const float* Ey,
+                       const float* Ez, float* Hx, float* Hy, float* Hz)
+{
+    H_HALF_STEP(float)
+}
 
 /*
  * Lossy materials (the conductivity "structural fields" of Section 4).

@@ -241,6 +241,8 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         return fail(ctx, FDTD_EINVAL, "adjoint: grad_eps is NULL or where is invalid");
     if (ctx->ca[0])
         return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: conductive (lossy) materials are not supported");
+    if (ctx->storage != FDTD_FP32)
+        return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: needs FP32 storage");
     if (spec->mon_comp < FDTD_EX || spec->mon_comp > FDTD_EZ)
         return fail(ctx, FDTD_EINVAL, "adjoint: the monitored component must be Ex, Ey or Ez");
     if (spec->nsteps < 1 || spec->nsteps > (int64_t(1) << 31) || spec->checkpoint_every < 0)

@@ -17,14 +17,25 @@ thread_local std::string g_create_error = "no error";
 
 constexpr int kThreads = 256;
 
+// binary16 <-> FP32 (round to nearest even; the scales are powers of two,
+// so scaling is exact and the conversion rounds once).  The empty asm keeps
+// the conversion a plain v_cvt_f16_f32: otherwise a preceding multiply is
+// folded into v_fma_mix with a +0 addend, which turns a -0 product into +0.
+__device__ __forceinline__ uint16_t to_h(float v)
+{
+    asm volatile("" : "+v"(v));
+    return __builtin_bit_cast(uint16_t, (_Float16)v);
+}
+__device__ __forceinline__ float from_h(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+
 // cE_c = (float)(dt / ((double)eps * dx)), zero on the index-0 plane of every
 // PEC axis tangential to component `comp` (bc[a] == 0 means PEC).  The
 // division is IEEE double, so the rounded result is the same on any
-// conforming machine.  Bad permittivity (< 1 or not finite) sets bit 0 of
-// *err.
-__global__ void build_coef_kernel(const float* __restrict__ eps, float* __restrict__ out, int comp,
-                                  int nx, int ny, int nz, int bcx, int bcy, int bcz, double dt,
-                                  double dx, int* err)
+// conforming machine.  With out16 the FP32 value is stored rounded to
+// binary16 instead.  Bad permittivity (< 1 or not finite) sets bit 0 of *err.
+__global__ void build_coef_kernel(const float* __restrict__ eps, float* __restrict__ out,
+                                  uint16_t* __restrict__ out16, int comp, int nx, int ny, int nz,
+                                  int bcx, int bcy, int bcz, double dt, double dx, int* err)
 {
     const long long n = (long long)nx * ny * nz;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
@@ -39,8 +50,36 @@ __global__ void build_coef_kernel(const float* __restrict__ eps, float* __restri
         if ((comp != 0 && bcx == FDTD_BC_PEC && i == 0) || (comp != 1 && bcy == FDTD_BC_PEC && j == 0) ||
             (comp != 2 && bcz == FDTD_BC_PEC && k == 0))
             c = 0.0;
-        out[p] = (float)c;
+        if (out16)
+            out16[p] = to_h((float)c);
+        else
+            out[p] = (float)c;
     }
+}
+
+// FP16 storage: dst = binary16(src * inv), and back, src * scale.
+__global__ void to_f16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, long long n,
+                              float inv)
+{
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x)
+        dst[p] = to_h(src[p] * inv);
+}
+
+__global__ void from_f16_kernel(const uint16_t* __restrict__ src, float* __restrict__ dst, long long n,
+                                float scale)
+{
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x)
+        dst[p] = from_h(src[p]) * scale;
+}
+
+// Re-encode binary16 values under a new scale: h * old * inv_new.
+__global__ void rescale_f16_kernel(uint16_t* __restrict__ a, long long n, float old_scale, float inv_new)
+{
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x)
+        a[p] = to_h((from_h(a[p]) * old_scale) * inv_new);
 }
 
 // Conductive coefficients of component `comp`, in IEEE double like cE:
@@ -75,21 +114,23 @@ __global__ void build_lossy_kernel(const float* __restrict__ eps, const float* _
     }
 }
 
-// Force the PEC-tangential entries of E component `comp` to +0.
-__global__ void zero_pec_kernel(float* __restrict__ f, int comp, int nx, int ny, int nz, int bcx,
+// Force the PEC-tangential entries of E component `comp` to +0 (all-zero
+// bits in both storage formats).
+template <typename T>
+__global__ void zero_pec_kernel(T* __restrict__ f, int comp, int nx, int ny, int nz, int bcx,
                                 int bcy, int bcz)
 {
     // three planes at most; one thread per element of the largest plane
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     // plane normal to x (i = 0): ny*nz entries
-    if (comp != 0 && bcx == FDTD_BC_PEC && t < (long long)ny * nz) f[t] = 0.0f;
+    if (comp != 0 && bcx == FDTD_BC_PEC && t < (long long)ny * nz) f[t] = T(0);
     // plane normal to y (j = 0): nx*nz entries
     if (comp != 1 && bcy == FDTD_BC_PEC && t < (long long)nx * nz) {
         long long i = t / nz, k = t % nz;
-        f[(i * ny) * nz + k] = 0.0f;
+        f[(i * ny) * nz + k] = T(0);
     }
     // plane normal to z (k = 0): nx*ny entries
-    if (comp != 2 && bcz == FDTD_BC_PEC && t < (long long)nx * ny) f[t * nz] = 0.0f;
+    if (comp != 2 && bcz == FDTD_BC_PEC && t < (long long)nx * ny) f[t * nz] = T(0);
 }
 
 __global__ void sources_kernel(float* Ex, float* Ey, float* Ez, const DevSource* __restrict__ src,
@@ -104,6 +145,24 @@ __global__ void sources_kernel(float* Ex, float* Ey, float* Ez, const DevSource*
         float* f = src[q].comp == 0 ? Ex : (src[q].comp == 1 ? Ey : Ez);
         long long p = ((long long)src[q].i * ny + src[q].j) * nz + src[q].k;
         f[p] = f[p] + src[q].wave[m];
+    }
+}
+
+// FP16 storage: the source cell is read, the sample added in FP32 and the
+// sum stored rounded again.
+__global__ void sources_f16_kernel(uint16_t* Ex, uint16_t* Ey, uint16_t* Ez, const DevSource* __restrict__ src,
+                                   int nsrc, long long s, int ny, int nz, float sx, float sy, float sz,
+                                   float ix, float iy, float iz)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int q = 0; q < nsrc; ++q) {
+        long long m = s - src[q].first;
+        if (m < 0 || m >= src[q].len) continue;
+        const int c = src[q].comp;
+        uint16_t* f = c == 0 ? Ex : (c == 1 ? Ey : Ez);
+        const float sc = c == 0 ? sx : (c == 1 ? sy : sz), inv = c == 0 ? ix : (c == 1 ? iy : iz);
+        long long p = ((long long)src[q].i * ny + src[q].j) * nz + src[q].k;
+        f[p] = to_h((from_h(f[p]) * sc + src[q].wave[m]) * inv);
     }
 }
 
@@ -242,9 +301,16 @@ int launch_sources(fdtd_ctx* ctx, int64_t s)
 {
     PendingTiming t;
     timing_begin(ctx, FDTD_KERNEL_SOURCES, &t);
-    hipLaunchKernelGGL(sources_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->field[0],
-                       ctx->field[1], ctx->field[2], ctx->dev_sources, ctx->dev_sources_n,
-                       (long long)s, ctx->ny, ctx->nz);
+    if (ctx->storage == FDTD_FP16_STORAGE)
+        hipLaunchKernelGGL(sources_f16_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->field16[0],
+                           ctx->field16[1], ctx->field16[2], ctx->dev_sources, ctx->dev_sources_n,
+                           (long long)s, ctx->ny, ctx->nz, ldexpf(1.0f, ctx->fexp[0]), ldexpf(1.0f, ctx->fexp[1]),
+                           ldexpf(1.0f, ctx->fexp[2]), ldexpf(1.0f, -ctx->fexp[0]), ldexpf(1.0f, -ctx->fexp[1]),
+                           ldexpf(1.0f, -ctx->fexp[2]));
+    else
+        hipLaunchKernelGGL(sources_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->field[0],
+                           ctx->field[1], ctx->field[2], ctx->dev_sources, ctx->dev_sources_n,
+                           (long long)s, ctx->ny, ctx->nz);
     timing_end(ctx, &t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "launch(sources)");
@@ -278,8 +344,6 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
         return fail(nullptr, FDTD_EINVAL, "fdtd_create: unknown scheme");
     if (cfg->storage != FDTD_FP32 && cfg->storage != FDTD_FP16_STORAGE)
         return fail(nullptr, FDTD_EINVAL, "fdtd_create: unknown storage");
-    if (cfg->storage == FDTD_FP16_STORAGE)
-        return fail(nullptr, FDTD_EUNSUPPORTED, "fdtd_create: FP16 storage is not implemented");
     if (cfg->device < 0) return fail(nullptr, FDTD_EINVAL, "fdtd_create: device must be >= 0");
 
     hipError_t e = hipSetDevice(cfg->device);
@@ -294,6 +358,7 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
     ctx->ncell = ncell;
     ctx->device = cfg->device;
     ctx->scheme = cfg->scheme;
+    ctx->storage = cfg->storage;
     ctx->band_steps = 0;  // 0 = choose per call
     ctx->workgroups = 0;
     ctx->spin_limit = int64_t(1) << 22;
@@ -317,25 +382,37 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
         }
         ctx->own_stream = true;
     }
+    const bool h16 = cfg->storage == FDTD_FP16_STORAGE;
     const size_t bytes = (size_t)ncell * sizeof(float);
+    const size_t sbytes = (size_t)ncell * (h16 ? sizeof(uint16_t) : sizeof(float));  // stored arrays
     for (int c = 0; c < 6; ++c) {
-        e = hipMalloc(&ctx->field[c], bytes);
+        void* p = nullptr;
+        e = hipMalloc(&p, sbytes);
         if (e != hipSuccess) {
             fail(nullptr, FDTD_ENOMEM, std::string("hipMalloc(field): ") + hipGetErrorString(e));
             return bail(FDTD_ENOMEM);
         }
-        e = hipMemsetAsync(ctx->field[c], 0, bytes, ctx->stream);
+        if (h16)
+            ctx->field16[c] = (uint16_t*)p;
+        else
+            ctx->field[c] = (float*)p;
+        e = hipMemsetAsync(p, 0, sbytes, ctx->stream);
         if (e != hipSuccess) {
             fail(nullptr, FDTD_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
             return bail(FDTD_EHIP);
         }
     }
     for (int c = 0; c < 3; ++c) {
-        e = hipMalloc(&ctx->coef[c], bytes);
+        void* p = nullptr;
+        e = hipMalloc(&p, sbytes);
         if (e != hipSuccess) {
             fail(nullptr, FDTD_ENOMEM, std::string("hipMalloc(coef): ") + hipGetErrorString(e));
             return bail(FDTD_ENOMEM);
         }
+        if (h16)
+            ctx->coef16[c] = (uint16_t*)p;
+        else
+            ctx->coef[c] = (float*)p;
     }
     e = hipMalloc(&ctx->dev_error, sizeof(int));
     if (e != hipSuccess) {
@@ -359,8 +436,8 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
     if (e == hipSuccess) {
         for (int c = 0; c < 3 && e == hipSuccess; ++c) {
             hipLaunchKernelGGL(build_coef_kernel, dim3(grid_for(ncell)), dim3(kThreads), 0, ctx->stream,
-                               ones, ctx->coef[c], c, ctx->nx, ctx->ny, ctx->nz, cfg->bc[0],
-                               cfg->bc[1], cfg->bc[2], cfg->dt, cfg->dx, ctx->dev_error);
+                               ones, ctx->coef[c], ctx->coef16[c], c, ctx->nx, ctx->ny, ctx->nz,
+                               cfg->bc[0], cfg->bc[1], cfg->bc[2], cfg->dt, cfg->dx, ctx->dev_error);
             e = hipGetLastError();
         }
     }
@@ -385,10 +462,13 @@ int fdtd_destroy(fdtd_ctx* ctx)
     }
     ctx->pending.clear();
     systolic_release(ctx);
-    for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < 6; ++c) {
         if (ctx->field[c]) (void)hipFree(ctx->field[c]);
+        if (ctx->field16[c]) (void)hipFree(ctx->field16[c]);
+    }
     for (int c = 0; c < 3; ++c) {
         if (ctx->coef[c]) (void)hipFree(ctx->coef[c]);
+        if (ctx->coef16[c]) (void)hipFree(ctx->coef16[c]);
         if (ctx->ca[c]) (void)hipFree(ctx->ca[c]);
     }
     for (auto& s : ctx->sources)
@@ -433,8 +513,8 @@ int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y, co
         }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(build_coef_kernel, dim3(grid_for(ctx->ncell)), dim3(kThreads), 0,
-                               ctx->stream, src, ctx->coef[c], c, ctx->nx, ctx->ny, ctx->nz,
-                               ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2], ctx->cfg.dt,
+                               ctx->stream, src, ctx->coef[c], ctx->coef16[c], c, ctx->nx, ctx->ny,
+                               ctx->nz, ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2], ctx->cfg.dt,
                                ctx->cfg.dx, ctx->dev_error);
             e = hipGetLastError();
         }
@@ -465,6 +545,8 @@ int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps
     const float* sig[3] = {sigma_x, sigma_y, sigma_z};
     for (int c = 0; c < 3; ++c)
         if (!ok_ptr(eps[c]) || !ok_ptr(sig[c])) return fail(ctx, FDTD_EINVAL, "set_lossy_materials: NULL array");
+    if (ctx->storage == FDTD_FP16_STORAGE)
+        return fail(ctx, FDTD_EUNSUPPORTED, "set_lossy_materials: conductivity needs FP32 storage");
     if (where == FDTD_HOST) {
         for (int c = 0; c < 3; ++c)
             for (int64_t p = 0; p < ctx->ncell; ++p) {
@@ -527,22 +609,72 @@ int fdtd_set_fields(fdtd_ctx* ctx, uint32_t comp_mask, const float* const src[6]
         if ((comp_mask >> c & 1u) && !src[c]) return fail(ctx, FDTD_EINVAL, "set_fields: NULL array");
     (void)hipSetDevice(ctx->device);
     const size_t bytes = (size_t)ctx->ncell * sizeof(float);
+    const bool h16 = ctx->storage == FDTD_FP16_STORAGE;
+    float* stage = nullptr;
     hipError_t e = hipSuccess;
+    if (h16 && where == FDTD_HOST && comp_mask && (e = hipMalloc(&stage, bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FDTD_ENOMEM, "set_fields: staging allocation failed");
+    }
     for (int c = 0; c < 6 && e == hipSuccess; ++c) {
         if (!(comp_mask >> c & 1u)) continue;
-        e = hipMemcpyAsync(ctx->field[c], src[c], bytes, kind_from(where, true), ctx->stream);
+        if (h16) {
+            // FP16 storage: the input rounded once under the component's scale
+            const float* in = src[c];
+            if (where == FDTD_HOST) {
+                e = hipMemcpyAsync(stage, src[c], bytes, hipMemcpyHostToDevice, ctx->stream);
+                in = stage;
+            }
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(to_f16_kernel, dim3(grid_for(ctx->ncell)), dim3(kThreads), 0, ctx->stream,
+                                   in, ctx->field16[c], (long long)ctx->ncell, ldexpf(1.0f, -ctx->fexp[c]));
+                e = hipGetLastError();
+            }
+        } else {
+            e = hipMemcpyAsync(ctx->field[c], src[c], bytes, kind_from(where, true), ctx->stream);
+        }
         if (e == hipSuccess && c < 3) {
             long long m = (long long)ctx->ny * ctx->nz;
             m = m > (long long)ctx->nx * ctx->nz ? m : (long long)ctx->nx * ctx->nz;
             m = m > (long long)ctx->nx * ctx->ny ? m : (long long)ctx->nx * ctx->ny;
-            hipLaunchKernelGGL(zero_pec_kernel, dim3((unsigned)((m + kThreads - 1) / kThreads)),
-                               dim3(kThreads), 0, ctx->stream, ctx->field[c], c, ctx->nx, ctx->ny,
-                               ctx->nz, ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2]);
+            const dim3 g((unsigned)((m + kThreads - 1) / kThreads));
+            if (h16)
+                hipLaunchKernelGGL(zero_pec_kernel<uint16_t>, g, dim3(kThreads), 0, ctx->stream, ctx->field16[c],
+                                   c, ctx->nx, ctx->ny, ctx->nz, ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2]);
+            else
+                hipLaunchKernelGGL(zero_pec_kernel<float>, g, dim3(kThreads), 0, ctx->stream, ctx->field[c], c,
+                                   ctx->nx, ctx->ny, ctx->nz, ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2]);
             e = hipGetLastError();
         }
+        // the staging buffer is reused by the next component
+        if (e == hipSuccess && stage) e = hipStreamSynchronize(ctx->stream);
     }
     if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+    if (stage) (void)hipFree(stage);
     if (e != hipSuccess) return hip_fail(ctx, e, "set_fields");
+    return FDTD_OK;
+}
+
+int fdtd_set_field_scale(fdtd_ctx* ctx, const int32_t exp2[6])
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (!exp2) return fail(ctx, FDTD_EINVAL, "set_field_scale: exp2 is NULL");
+    if (ctx->storage != FDTD_FP16_STORAGE)
+        return fail(ctx, FDTD_EINVAL, "set_field_scale: scales apply to FP16 storage only");
+    for (int c = 0; c < 6; ++c)
+        if (exp2[c] < -30 || exp2[c] > 30) return fail(ctx, FDTD_EINVAL, "set_field_scale: exponent out of [-30, 30]");
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 6 && e == hipSuccess; ++c) {
+        if (exp2[c] == ctx->fexp[c]) continue;
+        hipLaunchKernelGGL(rescale_f16_kernel, dim3(grid_for(ctx->ncell)), dim3(kThreads), 0, ctx->stream,
+                           ctx->field16[c], (long long)ctx->ncell, ldexpf(1.0f, ctx->fexp[c]),
+                           ldexpf(1.0f, -exp2[c]));
+        e = hipGetLastError();
+        ctx->fexp[c] = exp2[c];
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_field_scale");
     return FDTD_OK;
 }
 
@@ -624,11 +756,30 @@ int fdtd_read_fields(fdtd_ctx* ctx, uint32_t comp_mask, float* const dst[6], int
         if ((comp_mask >> c & 1u) && !dst[c]) return fail(ctx, FDTD_EINVAL, "read_fields: NULL array");
     (void)hipSetDevice(ctx->device);
     const size_t bytes = (size_t)ctx->ncell * sizeof(float);
+    const bool h16 = ctx->storage == FDTD_FP16_STORAGE;
+    float* stage = nullptr;
     hipError_t e = hipSuccess;
-    for (int c = 0; c < 6 && e == hipSuccess; ++c)
-        if (comp_mask >> c & 1u)
+    if (h16 && where == FDTD_HOST && comp_mask && (e = hipMalloc(&stage, bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FDTD_ENOMEM, "read_fields: staging allocation failed");
+    }
+    for (int c = 0; c < 6 && e == hipSuccess; ++c) {
+        if (!(comp_mask >> c & 1u)) continue;
+        if (h16) {
+            // FP16 storage: the stored value times the component's scale, exactly
+            float* out = where == FDTD_HOST ? stage : dst[c];
+            hipLaunchKernelGGL(from_f16_kernel, dim3(grid_for(ctx->ncell)), dim3(kThreads), 0, ctx->stream,
+                               ctx->field16[c], out, (long long)ctx->ncell, ldexpf(1.0f, ctx->fexp[c]));
+            e = hipGetLastError();
+            if (e == hipSuccess && where == FDTD_HOST)
+                e = hipMemcpyAsync(dst[c], stage, bytes, hipMemcpyDeviceToHost, ctx->stream);
+            if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+        } else {
             e = hipMemcpyAsync(dst[c], ctx->field[c], bytes, kind_from(where, false), ctx->stream);
+        }
+    }
     if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+    if (stage) (void)hipFree(stage);
     if (e != hipSuccess) return hip_fail(ctx, e, "read_fields");
     if (where == FDTD_HOST) return check_device_error(ctx);
     return FDTD_OK;

@@ -48,8 +48,15 @@ struct fdtd_ctx {
     hipStream_t stream;
     bool own_stream;
 
+    // FP32 storage: field and coef hold the arrays (field16/coef16 null).
+    // FP16 storage: field16 and coef16 hold IEEE binary16 arrays (field and
+    // coef null); field component c is stored as v * 2^-fexp[c].
+    int storage;      // FDTD_FP32 or FDTD_FP16_STORAGE
     float* field[6];  // Ex Ey Ez Hx Hy Hz
     float* coef[3];   // cEx cEy cEz (cb, the curl coefficient, with conductivity)
+    uint16_t* field16[6];
+    uint16_t* coef16[3];
+    int fexp[6];      // FP16 storage: power-of-two scale exponent per field component
     float* ca[3];     // E decay per step with conductivity; null when lossless
     float cH;
 

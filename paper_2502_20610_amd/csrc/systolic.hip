@@ -84,6 +84,7 @@ struct SimArgs {
     int L[3];    // tiles of the ring on a periodic axis
     int wr[3];   // updated cells of the ring's last (ragged) tile
     int K;       // steps per band of this simulation
+    float sc[6], isc[6];  // FP16 storage: field scale 2^e_c and its inverse
 };
 
 struct SysArgs {
@@ -93,8 +94,8 @@ struct SysArgs {
     int nt;
     const int* tix;    // ticket index of (band, tile)
     unsigned* progress;  // per ticket: last completed half-step level
-    float* ring[4];          // face rings: x, y and z faces (E, H); z-face coefficients
-    unsigned ring_bytes[4];
+    float* ring[6];  // face rings: x, y, z faces (E, H); z-, x-, y-face coefficients
+    unsigned ring_bytes[6];
     int R, Kmax;   // ring slots; the longest band (the ring's slot stride)
     int nsteps;
     unsigned* counter;
@@ -136,6 +137,23 @@ template <int POL>
 __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, POL);
+}
+
+// FP16 storage: a binary16 element read as FP32, and an FP32 value stored
+// rounded to binary16 (round to nearest even).
+template <int POL>
+__device__ __forceinline__ float bld16(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, POL));
+}
+
+template <int POL>
+__device__ __forceinline__ void bst16(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
+{
+    // the empty asm keeps the conversion a plain v_cvt_f16_f32 (a preceding
+    // multiply folded into v_fma_mix with a +0 addend would turn -0 into +0)
+    asm volatile("" : "+v"(v));
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, (int)off, 0, POL);
 }
 
 // Value of the lane (zs - 1) mod 16 / (zs + 1) mod 16 of the same DPP row.
@@ -292,7 +310,7 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     return *s_abort == 0;
 }
 
-template <int NW, bool DEV, bool PER, bool LOSSY>
+template <int NW, bool DEV, bool PER, bool LOSSY, bool F16>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void systolic_kernel(SysArgs A)
 {
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
@@ -316,7 +334,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     __shared__ float yst[NQA][YR][PZ];
     __shared__ __attribute__((aligned(16))) float zst[NQA][PY][LS];
     // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
-    __shared__ float ytr[6][LS][PZ];
+    // (with FP16 storage the y face carries the coefficients as well)
+    constexpr int NQY = F16 ? 9 : 6;
+    __shared__ float ytr[NQY][LS][PZ];
     __shared__ __attribute__((aligned(16))) float ztr[NQA][PY][LS];
     __shared__ int s_ticket;
     __shared__ int s_abort;
@@ -346,6 +366,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     const __amdgpu_buffer_rsrc_t rry = make_rsrc(A.ring[1], A.ring_bytes[1]);
     const __amdgpu_buffer_rsrc_t rrz = make_rsrc(A.ring[2], A.ring_bytes[2]);
     const __amdgpu_buffer_rsrc_t rrc = make_rsrc(A.ring[3], A.ring_bytes[3]);
+    // FP16 storage: the x and y faces' coefficients travel on rings too (the
+    // coefficient arrays are binary16, which the LDS loads cannot convert)
+    const __amdgpu_buffer_rsrc_t rrxc = make_rsrc(A.ring[4], A.ring_bytes[4]);
+    const __amdgpu_buffer_rsrc_t rryc = make_rsrc(A.ring[5], A.ring_bytes[5]);
+    constexpr unsigned step_c3 = 3u * 16u * 16u;  // floats per (slot, step) of rrxc, rryc
+    constexpr unsigned ES = F16 ? 2u : 4u;         // bytes per stored field element
     constexpr unsigned ring_comp = PY * LS;      // floats per component
     constexpr unsigned step_f = 6u * ring_comp;  // floats per (slot, local step): E and H
     constexpr unsigned step_c = (unsigned)(NQA - 6) * ring_comp;  // the z face's coefficients
@@ -535,12 +561,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             for (int j = 0; j < PXk; ++j) {
                 int x;
                 const bool okx = axis_pos<PER>(ox + t0 + 1, Xw, P.nx, perx, j - 1, x);
-                const unsigned off = (okyz && okx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
+                const unsigned off = (okyz && okx) ? ((unsigned)x * plane + yz) * ES : kOOB;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    E[q][j] = bld<SP>(rf[q], off);
-                    H[q][j] = bld<SP>(rf[3 + q], off);
-                    C[q][j] = bld<0>(rc[q], off);
+                    if (F16) {
+                        E[q][j] = bld16<SP>(rf[q], off) * P.sc[q];
+                        H[q][j] = bld16<SP>(rf[3 + q], off) * P.sc[3 + q];
+                        C[q][j] = bld16<0>(rc[q], off);
+                    } else {
+                        E[q][j] = bld<SP>(rf[q], off);
+                        H[q][j] = bld<SP>(rf[3 + q], off);
+                        C[q][j] = bld<0>(rc[q], off);
+                    }
                     if (LOSSY) CA[q][j] = bld<0>(rca[q], off);
                 }
             }
@@ -566,7 +598,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             auto off_at = [&](int k) -> unsigned {
                 int x;
                 const bool okx = axis_pos<PER>(Ux, Xw, P.nx, perx, k, x);
-                return (okyz && okx) ? ((unsigned)x * plane + yz) * 4u : kOOB;
+                return (okyz && okx) ? ((unsigned)x * plane + yz) * ES : kOOB;
             };
             // coordinates of this lane in the next box (after the one-cell move)
             const int dy1 = (dy - 1) & (PY - 1), dz1 = (dz - 1) & (PZ - 1);
@@ -604,8 +636,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const bool fwy = dy1 == wyr, fwz = dz1 == wzr;
                 const int sx = fwy ? (fwz ? sl_up[7] : sl_up[3]) : (fwz ? sl_up[5] : sl_up[1]);
                 const bool okxr = okyz1 && okxf && dy1 <= wyr && dz1 <= wzr && sx >= 0;
-                const unsigned oxr = (sls_of(sx) * step_f + (unsigned)(fwy ? 1 : dy1 + 1) * LS +
-                                      (unsigned)(fwz ? 1 : dz1 + 1)) * 4u;
+                const unsigned xin = (unsigned)(fwy ? 1 : dy1 + 1) * LS + (unsigned)(fwz ? 1 : dz1 + 1);
+                const unsigned oxr = (sls_of(sx) * step_f + xin) * 4u;
+                const unsigned oxc = (sls_of(sx) * step_c3 + xin) * 4u;
                 // y face: rows of the wavefront are x registers, lanes are z;
                 // the +y neighbour's (or, on the forward z lane, the +y+z
                 // neighbour's) first y row
@@ -619,7 +652,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const bool fwzl = dz1 == wzr;
                 const int sy = fwzl ? sl_up[6] : sl_up[2];
                 const bool okyr = oky_f && okz_l && okx && dz1 <= wzr && sy >= 0;
-                const unsigned oyr = (sls_of(sy) * step_f + (unsigned)j * LS + (unsigned)(fwzl ? 1 : dz1 + 1)) * 4u;
+                const unsigned yin = (unsigned)j * LS + (unsigned)(fwzl ? 1 : dz1 + 1);
+                const unsigned oyr = (sls_of(sy) * step_f + yin) * 4u;
+                const unsigned oyc = (sls_of(sy) * step_c3 + yin) * 4u;
                 // z face: rows are y, lanes are x, from the +z neighbour's ring slot
                 const int yy = 4 * w + r;
                 int xr, yr;
@@ -635,6 +670,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     if (q < 6) {
                         dma_dword<DEV>(rrx, lx, okxr ? oxr + (unsigned)q * cb : kOOB);
                         if (ydo) dma_dword<DEV>(rry, ly, okyr ? oyr + (unsigned)q * cb : kOOB);
+                    } else if (q < 9 && F16) {
+                        dma_dword<DEV>(rrxc, lx, okxr ? oxc + (unsigned)(q - 6) * cb : kOOB);
+                        if (ydo) dma_dword<DEV>(rryc, ly, okyr ? oyc + (unsigned)(q - 6) * cb : kOOB);
                     } else if (q < 9) {
                         dma_dword<false>(rc[q - 6], lx, oxf);
                         if (ydo) dma_dword<false>(rc[q - 6], ly, oyf);
@@ -660,8 +698,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const int dzl = (zs - oz - tau + 1) & (PZ - 1);
                 const bool oky_ = has_yc && j < WXk;
                 const unsigned oy_ = (sls * step_f + (unsigned)j * LS + (unsigned)dzl) * 4u;
+                const unsigned oyc_ = (sls * step_c3 + (unsigned)j * LS + (unsigned)dzl) * 4u;
 #pragma unroll
-                for (int q = Q0; q < Q0 + NQ; ++q) bst<SP>(rry, oky_ ? oy_ + (unsigned)q * cb : kOOB, ytr[q][j][zs]);
+                for (int q = Q0; q < Q0 + NQ; ++q) {
+                    if (q < 6)
+                        bst<SP>(rry, oky_ ? oy_ + (unsigned)q * cb : kOOB, ytr[q][j][zs]);
+                    else
+                        bst<SP>(rryc, oky_ ? oyc_ + (unsigned)(q - 6) * cb : kOOB, ytr[q][j][zs]);
+                }
                 // (dropped offsets when there is no consumer: no branch)
                 const unsigned oz_ = (sls * step_f + (unsigned)j * LS + (unsigned)zs) * 4u;
                 const unsigned oc_ = (sls * step_c + (unsigned)j * LS + (unsigned)zs) * 4u;
@@ -837,11 +881,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // H (and, on the z face, the coefficients) of the first layer
 #pragma unroll
             for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)(3 + q) * cb : kOOB, H[q][0]);
+            if (F16) {
+                const unsigned oxc_ = (sls * step_c3 + (unsigned)dy * LS + (unsigned)dz) * 4u;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) bst<SP>(rrxc, has_xc ? oxc_ + (unsigned)q * cb : kOOB, C[q][0]);
+            }
             if (dy == 1) {
 #pragma unroll
                 for (int j = 0; j < WXk; ++j)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) ytr[3 + q][j][zs] = H[q][j];
+                    for (int q = 0; q < 3; ++q) {
+                        ytr[3 + q][j][zs] = H[q][j];
+                        if (F16) ytr[6 + q][j][zs] = C[q][j];
+                    }
             }
             if (dz == 1) {
 #pragma unroll
@@ -853,7 +905,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         if (LOSSY) ztr[9 + q][dy1][j] = CA[q][j];
                     }
             }
-            store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, 3>(), std::integral_constant<int, NQA - 3>());
+            store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, NQY - 3>(),
+                        std::integral_constant<int, NQA - 3>());
             if (tau == t1 && inB) {
                 // band end: the whole subdomain goes back to the field arrays
 #pragma unroll
@@ -861,8 +914,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     const unsigned o = j < wxr ? off_at(j) : kOOB;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        bst<SP>(rf[q], o, E[q][j]);
-                        bst<SP>(rf[3 + q], o, H[q][j]);
+                        if (F16) {
+                            bst16<SP>(rf[q], o, E[q][j] * P.isc[q]);
+                            bst16<SP>(rf[3 + q], o, H[q][j] * P.isc[3 + q]);
+                        } else {
+                            bst<SP>(rf[q], o, E[q][j]);
+                            bst<SP>(rf[3 + q], o, H[q][j]);
+                        }
                     }
                 }
             }
@@ -1265,11 +1323,16 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
     fdtd_ctx* lead = cs[0];
     if (nsteps > (int64_t(1) << 24)) return fail(lead, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
-    // one kernel variant per launch: all members conductive or none
+    // one kernel variant per launch: all members conductive or none, and
+    // all with the same storage format
     const bool lossy = lead->ca[0] != nullptr;
-    for (int i = 1; i < n; ++i)
+    const bool h16 = lead->storage == FDTD_FP16_STORAGE;
+    for (int i = 1; i < n; ++i) {
         if ((cs[i]->ca[0] != nullptr) != lossy)
             return fail(lead, FDTD_EUNSUPPORTED, "systolic batch: conductive and lossless grids cannot share a launch");
+        if ((cs[i]->storage == FDTD_FP16_STORAGE) != h16)
+            return fail(lead, FDTD_EUNSUPPORTED, "systolic batch: FP32 and FP16 storage cannot share a launch");
+    }
     // band length per simulation: the lead's option for all, else each
     // simulation's own choice of the cost model
     int Kmax = 1;
@@ -1296,13 +1359,18 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
     const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
     const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
+    // variants: [sync][periodic][FP32, conductive, FP16 storage]
     using Kern = void (*)(SysArgs);
-    static const Kern kernels[2][2][2] = {
-        {{systolic_kernel<kNW, false, false, false>, systolic_kernel<kNW, false, false, true>},
-         {systolic_kernel<kNW, false, true, false>, systolic_kernel<kNW, false, true, true>}},
-        {{systolic_kernel<kNW, true, false, false>, systolic_kernel<kNW, true, false, true>},
-         {systolic_kernel<kNW, true, true, false>, systolic_kernel<kNW, true, true, true>}}};
-    const Kern kern = kernels[dev][anyper][lossy];
+    static const Kern kernels[2][2][3] = {
+        {{systolic_kernel<kNW, false, false, false, false>, systolic_kernel<kNW, false, false, true, false>,
+          systolic_kernel<kNW, false, false, false, true>},
+         {systolic_kernel<kNW, false, true, false, false>, systolic_kernel<kNW, false, true, true, false>,
+          systolic_kernel<kNW, false, true, false, true>}},
+        {{systolic_kernel<kNW, true, false, false, false>, systolic_kernel<kNW, true, false, true, false>,
+          systolic_kernel<kNW, true, false, false, true>},
+         {systolic_kernel<kNW, true, true, false, false>, systolic_kernel<kNW, true, true, true, false>,
+          systolic_kernel<kNW, true, true, false, true>}}};
+    const Kern kern = kernels[dev][anyper][h16 ? 2 : (lossy ? 1 : 0)];
     hipError_t e;
     if (L->sm_count == 0) {
         hipDeviceProp_t prop;
@@ -1333,12 +1401,13 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     // face's coefficients), each addressed with 32-bit offsets
     const size_t face = (size_t)(4 * kNW) * 16 * sizeof(float);  // one component of one face
     const size_t rf6 = (size_t)R * Kmax * 6 * face;
-    const size_t rb[4] = {rf6, rf6, rf6, (size_t)R * Kmax * (lossy ? 6 : 3) * face};
+    const size_t rc3 = (size_t)R * Kmax * 3 * face;
+    const size_t rb[6] = {rf6, rf6, rf6, lossy ? rf6 : rc3, h16 ? rc3 : 0, h16 ? rc3 : 0};
     if (rf6 >= ((size_t)1 << 32))
         return fail(lead, FDTD_EUNSUPPORTED,
                     "systolic: face ring too large for 32-bit offsets (" + std::to_string(R) + " slots of " +
                         std::to_string(Kmax) + " steps); a shorter band (FDTD_OPT_BAND_STEPS) shrinks it");
-    const size_t ring_bytes = rb[0] + rb[1] + rb[2] + rb[3];
+    const size_t ring_bytes = rb[0] + rb[1] + rb[2] + rb[3] + rb[4] + rb[5];
     if (ring_bytes > L->ring_bytes || !L->d_ring) {
         if (L->d_ring) (void)hipFree(L->d_ring);
         L->d_ring = nullptr;
@@ -1375,14 +1444,20 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
         const fdtd_ctx* c = cs[i];
         SimArgs& P = L->h_sims[i];
         memset(&P, 0, sizeof(P));
-        for (int q = 0; q < 6; ++q) P.f[q] = c->field[q];
-        for (int q = 0; q < 3; ++q) P.cE[q] = c->coef[q];
+        // (with FP16 storage the record holds the binary16 arrays: the
+        // kernel only forms buffer descriptors from these addresses)
+        for (int q = 0; q < 6; ++q) P.f[q] = h16 ? (float*)c->field16[q] : c->field[q];
+        for (int q = 0; q < 3; ++q) P.cE[q] = h16 ? (const float*)c->coef16[q] : c->coef[q];
         for (int q = 0; q < 3; ++q) P.ca[q] = c->ca[q];
+        for (int q = 0; q < 6; ++q) {
+            P.sc[q] = ldexpf(1.0f, c->fexp[q]);
+            P.isc[q] = ldexpf(1.0f, -c->fexp[q]);
+        }
         P.cH = c->cH;
         P.nx = c->nx;
         P.ny = c->ny;
         P.nz = c->nz;
-        P.fbytes = (unsigned)((uint64_t)c->ncell * 4u);
+        P.fbytes = (unsigned)((uint64_t)c->ncell * (h16 ? 2u : 4u));
         P.band = L->d_band + L->up_band_off[i];
         P.step0 = c->step_count;
         P.src = c->dev_sources;
@@ -1425,7 +1500,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     A.tix = L->d_tix;
     A.progress = L->d_progress;
     size_t roff = 0;
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 6; ++f) {
         A.ring[f] = L->d_ring + roff / sizeof(float);
         A.ring_bytes[f] = (unsigned)rb[f];
         roff += rb[f];

@@ -38,7 +38,7 @@ EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_lossy_
            "fdtd_set_fields",
            "fdtd_add_source", "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_synchronize",
            "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
-           "fdtd_kernel_stats", "fdtd_get_info")
+           "fdtd_kernel_stats", "fdtd_get_info", "fdtd_set_field_scale")
 
 
 class FdtdError(RuntimeError):
@@ -96,6 +96,7 @@ def load_library():
         "fdtd_kernel_stats": ([vp, ctypes.c_int, ctypes.POINTER(i64),
                                ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "fdtd_get_info": ([vp, ctypes.c_int, ctypes.POINTER(i64)], ctypes.c_int),
+        "fdtd_set_field_scale": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -126,11 +127,12 @@ def _pointer(a, ncell: int):
 
 
 class Simulation:
-    """One FDTD context.  ``shape`` = (nx, ny, nz); ``bc`` per axis 0 = PEC, 1 = periodic."""
+    """One FDTD context.  ``shape`` = (nx, ny, nz); ``bc`` per axis 0 = PEC, 1 = periodic;
+    ``storage`` "fp32" or "fp16" (binary16 device arrays, FP32 arithmetic)."""
 
     def __init__(self, shape: Sequence[int], dt: float = 0.5, dx: float = 1.0,
                  bc: Sequence[int] = (0, 0, 0), scheme: str = "plain", device: int = 0,
-                 stream: Optional[int] = None):
+                 stream: Optional[int] = None, storage: str = "fp32"):
         self._lib = load_library()
         self.shape = tuple(int(s) for s in shape)
         self.ncell = self.shape[0] * self.shape[1] * self.shape[2]
@@ -141,7 +143,8 @@ class Simulation:
         for a in range(3):
             cfg.bc[a] = int(bc[a])
         cfg.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-        cfg.storage = FP32
+        cfg.storage = {"fp32": FP32, "fp16": FP16_STORAGE}[storage] if isinstance(storage, str) \
+            else int(storage)
         cfg.device = int(device)
         cfg.stream = ctypes.c_void_p(stream) if stream else None
         h = ctypes.c_void_p()
@@ -192,6 +195,11 @@ class Simulation:
         else:
             self._check(self._lib.fdtd_set_lossy_materials(self._h, *[q[0] for q in ptrs],
                                                            ptrs[0][1]))
+
+    def set_field_scale(self, exp2):
+        """FP16 storage: component c is stored as v * 2^-exp2[c]."""
+        arr = (ctypes.c_int32 * 6)(*[int(e) for e in exp2])
+        self._check(self._lib.fdtd_set_field_scale(self._h, arr))
 
     def set_fields(self, fields, mask: Optional[int] = None):
         """``fields``: six arrays (None entries skipped) in (Ex..Hz) order."""
@@ -357,12 +365,14 @@ def step_batch(sims: Sequence["Simulation"], nsteps: int):
 
 
 def run_workload(w, scheme: str = "plain", nsteps: Optional[int] = None, device: int = 0,
-                 options=None):
+                 options=None, storage: str = "fp32", field_exp2=None):
     """Run a workloads.Workload through the library and return the six fields (host)."""
-    sim = Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, device=device)
+    sim = Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, device=device, storage=storage)
     try:
         for k, v in (options or {}).items():
             sim.set_option(k, v)
+        if field_exp2 is not None:
+            sim.set_field_scale(field_exp2)
         sim.set_materials(w.eps)
         if w.fields is not None:
             sim.set_fields(w.fields)

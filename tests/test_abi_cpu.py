@@ -90,7 +90,6 @@ def _cfg(**kw):
     (dict(bc=(0, 2, 0)), fdtd.FDTD_EINVAL),
     (dict(scheme=7), fdtd.FDTD_EINVAL),
     (dict(storage=5), fdtd.FDTD_EINVAL),
-    (dict(storage=1), fdtd.FDTD_EUNSUPPORTED),
     (dict(device=-1), fdtd.FDTD_EINVAL),
 ])
 def test_create_rejects_invalid_config_without_gpu(kw, code):

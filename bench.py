@@ -35,18 +35,32 @@ PLAIN_E_BYTES, PLAIN_H_BYTES = 48, 36   # algorithmic bytes per cell, per half-s
 PLAIN_BYTES_PER_UPDATE = PLAIN_E_BYTES + PLAIN_H_BYTES
 
 
-def systolic_bytes_per_update(tile, band, conductive=False):
+def systolic_bytes_per_update(tile, band, conductive=False, fp16=False):
     """Algorithmic HBM bytes per cell update of the systolic scheme (Section 4
-    accounting): every step a tile of V = Wx*Wy*Wz updated cells takes in its
-    leading faces (E, H and the coefficient: 36 B per cell; 48 B with the
-    conductive decay) and puts out its trailing faces (E and H: 24 B per
-    cell), A = WyWz + WxWz + WxWy cells each; once per band of K steps the
-    whole state goes out and comes back in (60 B per cell; 72 B with the
-    conductive decay)."""
+    accounting: faces of the fields and of the structural coefficients in and
+    out every step, the whole state once per band of K steps), for this
+    design's exchange.  Every step a tile of V = Wx*Wy*Wz updated cells takes
+    in its three leading faces and puts out its three trailing faces:
+
+    - x face (WyWz cells) and y face (WxWz): E and H (24 B per cell) through
+      the face rings both ways, the coefficients (12 B; 24 B with the
+      conductive decay) read from their arrays; with FP16 storage the
+      coefficients travel through the rings too (in and out);
+    - z face (WxWy): E, H and the coefficients through the ring, in and out.
+
+    Once per band the whole state goes out and comes back in: E and H out
+    and in, the coefficients in (60 B per cell in FP32, 72 B when conductive,
+    30 B with FP16 storage)."""
     wx, wy, wz = tile
-    area = wy * wz + wx * wz + wx * wy
-    lead = 48 if conductive else 36
-    return (lead + 24) * area / (wx * wy * wz) + (lead + 24.0) / band
+    axy, v = wx * wy, wx * wy * wz
+    c = 24 if conductive else 12            # coefficient bytes per cell (FP32)
+    if fp16:
+        per_step = (wy * wz + wx * wz + axy) * (24 + c) * 2
+        band_bytes = 2 * 12 + 6
+    else:
+        per_step = (wy * wz + wx * wz) * (24 + c + 24) + axy * (24 + c) * 2
+        band_bytes = 2 * 24 + c
+    return per_step / v + band_bytes / band
 
 
 def counter_traffic(kernel: str, source: str, launch: dict):
@@ -85,11 +99,12 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %r" % name)
 
 
-def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None):
+def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None, storage="fp32"):
     import torch
     from paper_2502_20610_amd import fdtd
     stream = torch.cuda.current_stream()
-    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, stream=stream.cuda_stream)
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, stream=stream.cuda_stream,
+                          storage=storage)
     try:
         for k, v in (options or {}).items():
             sim.set_option(k, v)
@@ -298,6 +313,8 @@ def main():
                          "per grid and the plain scheme")
     ap.add_argument("--batch-dims", default="64,192",
                     help="lo,hi: per-axis sizes of the batched grids (multiples of 16)")
+    ap.add_argument("--storage", default="fp32", choices=("fp32", "fp16"),
+                    help="field storage: fp32, or fp16 (binary16 arrays, FP32 arithmetic)")
     ap.add_argument("--sigma", type=float, default=0.0,
                     help="conductive variant: a graded absorbing shell (16 cells) with this peak "
                          "conductivity around the workload (0 = lossless)")
@@ -351,7 +368,7 @@ def main():
                     opts[fdtd.OPT_BAND_STEPS] = args.band
                 if args.workgroups:
                     opts[fdtd.OPT_WORKGROUPS] = args.workgroups
-            t, stats = run_scheme(w, scheme, args.steps, args.warmup, opts, sigma)
+            t, stats = run_scheme(w, scheme, args.steps, args.warmup, opts, sigma, args.storage)
         except fdtd.FdtdError as e:
             if e.code == fdtd.FDTD_EUNSUPPORTED:
                 log("%s unavailable: %s" % (scheme, e))
@@ -369,11 +386,13 @@ def main():
         avg_s = ms / 1e3 / max(n, 1)
         steps_per_launch = args.steps / max(n, 1)
         band = stats["info"]["band_steps"]
-        b_alg = systolic_bytes_per_update(stats["info"]["tile"], band, sigma is not None)
+        b_alg = systolic_bytes_per_update(stats["info"]["tile"], band, sigma is not None,
+                                          args.storage == "fp16")
         updates = cells * steps_per_launch
         achieved = b_alg * updates / avg_s / 1e9
         flops = FLOPS_PER_CELL * updates / avg_s / 1e12
-        launch = {"workload": w.name + ("_conductive" if sigma is not None else ""),
+        launch = {"workload": w.name + ("_conductive" if sigma is not None else "")
+                  + ("_fp16" if args.storage == "fp16" else ""),
                   "steps": int(round(steps_per_launch)), "band": band}
         traffic = counter_traffic("systolic_kernel", "paper_2502_20610_amd/csrc/systolic.hip",
                                   dict(launch, cells=cells))
@@ -391,9 +410,12 @@ def main():
         n, ms = stats[fdtd.KERNEL_PLAIN_E]
         avg_s = ms / 1e3 / max(n, 1)
         e_bytes = PLAIN_E_BYTES + (12 if sigma is not None else 0)
+        if args.storage == "fp16":
+            e_bytes //= 2
         achieved = e_bytes * cells / avg_s / 1e9
         traffic = counter_traffic("plain_E_kernel", "paper_2502_20610_amd/csrc/plain.hip",
-                                  {"workload": w.name + ("_conductive" if sigma is not None else ""),
+                                  {"workload": w.name + ("_conductive" if sigma is not None else "")
+                                   + ("_fp16" if args.storage == "fp16" else ""),
                                    "steps": 1, "cells": cells})
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "plain_E_kernel",
@@ -401,7 +423,8 @@ def main():
 
     out = {
         "metric": "cell updates/s, systolic vs plain Yee FDTD, %dx%dx%d FP32" % w.shape
-                  + (", conductive" if sigma is not None else ""),
+                  + (", conductive" if sigma is not None else "")
+                  + (", FP16 storage" if args.storage == "fp16" else ""),
         "value": cups, "unit": "cell updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -415,7 +438,7 @@ def main():
         if scheme == "systolic":
             entry.update(st["info"])
             b = systolic_bytes_per_update(st["info"]["tile"], st["info"]["band_steps"],
-                                          sigma is not None)
+                                          sigma is not None, args.storage == "fp16")
             entry["alg_bytes_per_update"] = b
             entry["alg_roofline_frac"] = c * b / (HBM_PEAK_GBS * 1e9)
             entry["effective_bw_frac_84B"] = c * PLAIN_BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9)
@@ -425,6 +448,8 @@ def main():
             entry["E_avg_ms"] = mse / max(ne, 1)
             entry["H_avg_ms"] = msh / max(nh, 1)
             pb = PLAIN_BYTES_PER_UPDATE + (12 if sigma is not None else 0)
+            if args.storage == "fp16":
+                pb //= 2
             entry["alg_bytes_per_update"] = pb
             entry["alg_roofline_frac"] = c * pb / (HBM_PEAK_GBS * 1e9)
         out[scheme] = entry
@@ -432,6 +457,8 @@ def main():
         out["systolic_over_plain"] = out["systolic"]["cups"] / out["plain"]["cups"]
     if sigma is not None:
         out["config"]["conductive"] = {"shell_cells": 16, "sigma_max": args.sigma}
+    if args.storage == "fp16":
+        out["config"]["storage"] = "fp16"   # arithmetic stays FP32
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

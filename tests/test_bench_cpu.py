@@ -12,13 +12,19 @@ import bench  # noqa: E402
 
 
 def test_systolic_bytes_per_update():
-    # Section 4 accounting: (36 in + 24 out) * A / V + 60 / K
-    assert bench.systolic_bytes_per_update((31, 15, 15), 64) == pytest.approx(10.873, abs=1e-3)
-    assert bench.systolic_bytes_per_update((15, 15, 15), 32) == pytest.approx(12.0 + 60 / 32)
-    # conductive: 11-wide tile along x, ca travels with the leading faces
-    area = 15 * 15 + 2 * 11 * 15
+    # x and y faces: E, H in and out (48 B) + the coefficient read (12 B);
+    # z face: E, H and the coefficient in and out (72 B); band: 60 B / K
+    assert bench.systolic_bytes_per_update((15, 15, 15), 32) == pytest.approx(
+        (2 * 225 * 60 + 225 * 72) / 3375 + 60 / 32)          # 12.8 + 1.875
+    assert bench.systolic_bytes_per_update((31, 15, 15), 64) == pytest.approx(
+        ((225 + 465) * 60 + 465 * 72) / 6975 + 60 / 64)
+    # conductive: 11-wide tile along x, ca read with cE and carried on the z ring
     assert bench.systolic_bytes_per_update((11, 15, 15), 16, True) == pytest.approx(
-        72 * area / (11 * 15 * 15) + 72 / 16)
+        ((225 + 165) * 72 + 165 * 96) / (11 * 15 * 15) + 72 / 16)
+    # FP16 storage: all faces through the rings in FP32 (72 B per face cell),
+    # the band's state in binary16 (E, H out and in, cE in: 30 B)
+    assert bench.systolic_bytes_per_update((15, 15, 15), 48, fp16=True) == pytest.approx(
+        3 * 225 * 72 / 3375 + 30 / 48)
     # the plain two-launch scheme moves 84 B per update
     assert bench.PLAIN_BYTES_PER_UPDATE == 84
 

@@ -75,7 +75,7 @@ struct SimArgs {
     const float* ca[3];  // conductive decay per cell (conductive variant only)
     float cH;
     int nx, ny, nz;
-    unsigned fbytes;   // bytes of one field array
+    unsigned esize;    // bytes per stored element (4, or 2 with FP16 storage)
     const int* band;   // per band: alo ahi blo bhi clo chi tix_off pad (tix_off into the launch's table)
     long long step0;
     const DevSource* src;
@@ -399,19 +399,29 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int t0 = t0_ * P.K;
         const int t1 = min(A.nsteps, t0 + P.K);
         const int* bi = P.band + 8 * bnd;
+        const unsigned plane = (unsigned)P.ny * (unsigned)P.nz;
+        const bool perx = PER && P.per[0], pery = PER && P.per[1], perz = PER && P.per[2];
+        // Field and coefficient descriptors start at the first x-plane the
+        // ticket can touch: on a PEC x axis every position it reads or writes
+        // lies in [ox + t0, ox + t1 + 16), so offsets stay far below the
+        // 32-bit limit even for arrays of 4 GiB.  A periodic x axis wraps over
+        // the whole array, which it addresses from its start (such grids are
+        // limited to arrays below 4 GiB).
+        const int xlo = perx ? 0 : max(0, a * WXk + t0);
+        const unsigned long long ebase = (unsigned long long)xlo * plane;
+        const unsigned rbytes = (unsigned)min(((unsigned long long)P.nx * plane - ebase) * ES,
+                                              0xFFFFFF00ull);
         __amdgpu_buffer_rsrc_t rf[6], rc[3];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) rf[q] = make_rsrc(P.f[q], P.fbytes);
+        for (int q = 0; q < 6; ++q) rf[q] = make_rsrc((const char*)P.f[q] + ebase * ES, rbytes);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) rc[q] = make_rsrc(P.cE[q], P.fbytes);
+        for (int q = 0; q < 3; ++q) rc[q] = make_rsrc((const char*)P.cE[q] + ebase * ES, rbytes);
         __amdgpu_buffer_rsrc_t rca[3];
         if (LOSSY) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) rca[q] = make_rsrc(P.ca[q], P.fbytes);
+            for (int q = 0; q < 3; ++q) rca[q] = make_rsrc((const char*)P.ca[q] + ebase * 4ull, rbytes);
         }
-        const unsigned plane = (unsigned)P.ny * (unsigned)P.nz;
         const float cH = P.cH;
-        const bool perx = PER && P.per[0], pery = PER && P.per[1], perz = PER && P.per[2];
         if (tid < min(P.nsrc, kLdsSrc)) {
             const DevSource sq = P.src[tid];
             s_src[tid][0] = sq.comp;
@@ -561,7 +571,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             for (int j = 0; j < PXk; ++j) {
                 int x;
                 const bool okx = axis_pos<PER>(ox + t0 + 1, Xw, P.nx, perx, j - 1, x);
-                const unsigned off = (okyz && okx) ? ((unsigned)x * plane + yz) * ES : kOOB;
+                const unsigned off = (okyz && okx) ? ((unsigned)(x - xlo) * plane + yz) * ES : kOOB;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     if (F16) {
@@ -598,7 +608,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             auto off_at = [&](int k) -> unsigned {
                 int x;
                 const bool okx = axis_pos<PER>(Ux, Xw, P.nx, perx, k, x);
-                return (okyz && okx) ? ((unsigned)x * plane + yz) * ES : kOOB;
+                return (okyz && okx) ? ((unsigned)(x - xlo) * plane + yz) * ES : kOOB;
             };
             // coordinates of this lane in the next box (after the one-cell move)
             const int dy1 = (dy - 1) & (PY - 1), dz1 = (dz - 1) & (PZ - 1);
@@ -632,7 +642,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 // further along +y (+z).
                 int xf;
                 const bool okxf = axis_pos<PER>(Ux, Xw, P.nx, perx, wxr, xf);
-                const unsigned oxf = (okyz1 && okxf) ? ((unsigned)xf * plane + yz1) * 4u : kOOB;
+                const unsigned oxf = (okyz1 && okxf) ? ((unsigned)(xf - xlo) * plane + yz1) * 4u : kOOB;
                 const bool fwy = dy1 == wyr, fwz = dz1 == wzr;
                 const int sx = fwy ? (fwz ? sl_up[7] : sl_up[3]) : (fwz ? sl_up[5] : sl_up[1]);
                 const bool okxr = okyz1 && okxf && dy1 <= wyr && dz1 <= wzr && sx >= 0;
@@ -647,7 +657,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 int x;
                 const bool okx = j < WXk && axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
                 const unsigned oyf = (oky_f && okz_l && okx)
-                                         ? (((unsigned)x * (unsigned)P.ny + (unsigned)yf) * (unsigned)P.nz + (unsigned)zl) * 4u
+                                         ? (((unsigned)(x - xlo) * (unsigned)P.ny + (unsigned)yf) * (unsigned)P.nz + (unsigned)zl) * 4u
                                          : kOOB;
                 const bool fwzl = dz1 == wzr;
                 const int sy = fwzl ? sl_up[6] : sl_up[2];
@@ -1319,7 +1329,9 @@ int upload_plan(fdtd_ctx* lead, SystolicState* L, fdtd_ctx* const* cs, int n)
 
 // One persistent launch advancing the contexts cs[0..n) by nsteps each, on
 // cs[0]'s stream (the others' streams wait for it and it for them).
-int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
+// kcap: the longest band an automatic choice may take (lowered when the face
+// rings of a longer band would not fit their 32-bit offsets).
+int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand)
 {
     fdtd_ctx* lead = cs[0];
     if (nsteps > (int64_t(1) << 24)) return fail(lead, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
@@ -1342,7 +1354,8 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
             if (!cs[i]->sys) return fail(lead, FDTD_ENOMEM, "systolic: host allocation failed");
         }
         SystolicState* si = cs[i]->sys;
-        const int K = lead->band_steps > 0 ? default_band(cs, 1, nsteps) : default_band(cs + i, 1, nsteps);
+        const int K = lead->band_steps > 0 ? default_band(cs, 1, nsteps)
+                                           : std::min(kcap, default_band(cs + i, 1, nsteps));
         Kmax = std::max(Kmax, K);
         if (si->nsteps != (int)nsteps || si->K != K || si->wx != tile_x(cs[i])) {
             int rc = build_plan(cs[i], si, (int)nsteps, K);
@@ -1403,6 +1416,12 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
     const size_t rf6 = (size_t)R * Kmax * 6 * face;
     const size_t rc3 = (size_t)R * Kmax * 3 * face;
     const size_t rb[6] = {rf6, rf6, rf6, lossy ? rf6 : rc3, h16 ? rc3 : 0, h16 ? rc3 : 0};
+    if (rf6 >= ((size_t)1 << 32) && lead->band_steps == 0 && Kmax > 1) {
+        // an automatic band: take the longest one whose rings fit
+        const size_t per_step = (size_t)R * 6 * face;
+        const int fit = (int)std::min<size_t>((((size_t)1 << 32) - 1) / per_step, (size_t)Kmax - 1);
+        return launch(cs, n, nsteps, std::max(1, fit));
+    }
     if (rf6 >= ((size_t)1 << 32))
         return fail(lead, FDTD_EUNSUPPORTED,
                     "systolic: face ring too large for 32-bit offsets (" + std::to_string(R) + " slots of " +
@@ -1457,7 +1476,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps)
         P.nx = c->nx;
         P.ny = c->ny;
         P.nz = c->nz;
-        P.fbytes = (unsigned)((uint64_t)c->ncell * (h16 ? 2u : 4u));
+        P.esize = h16 ? 2u : 4u;
         P.band = L->d_band + L->up_band_off[i];
         P.step0 = c->step_count;
         P.src = c->dev_sources;
@@ -1550,8 +1569,16 @@ int systolic_supported(const fdtd_ctx* ctx, std::string* why)
             *why = "the systolic scheme needs at least 16 cells on a periodic axis";
             return 0;
         }
-    if ((uint64_t)ctx->ncell * 4u > 0xFFFFFF00ull) {
-        *why = "field arrays above 4 GiB are not supported by the systolic scheme";
+    // 32-bit buffer offsets: a ticket addresses at most kMaxBand + 16
+    // x-planes from its own base on a PEC x axis, the whole array on a
+    // periodic one
+    const uint64_t es = ctx->storage == FDTD_FP16_STORAGE ? 2u : 4u;
+    const uint64_t plane = (uint64_t)ctx->ny * ctx->nz;
+    const bool perx = ctx->cfg.bc[0] == FDTD_BC_PERIODIC;
+    const uint64_t span = perx ? (uint64_t)ctx->nx : std::min<uint64_t>(ctx->nx, kMaxBand + 16);
+    if (span * plane * es > 0xFFFFFF00ull) {
+        *why = perx ? "field arrays of 4 GiB or more need a PEC x axis on the systolic scheme"
+                    : "an x-plane of this grid is too large for the systolic scheme's 32-bit offsets";
         return 0;
     }
     return 1;

@@ -103,3 +103,67 @@ def test_fullsize_sampled_bitwise(scheme, band):
     assert not bad, "%d/%d samples differ, first %s" % (len(bad), len(pts), bad[0])
     # the check is not vacuous: most sampled cells are non-zero
     assert np.count_nonzero(got) > got.size // 2
+
+
+def test_max_grid_auto_band_fits_the_rings_and_is_exact():
+    """The largest grid the ABI accepts, 1024^3 = 2^30 cells, 128 steps with the
+    automatic band: the cost model would take 64-step bands, whose face rings
+    would pass the 4 GB of a buffer descriptor's 32-bit offsets, so the launch
+    takes the longest band that fits instead.  Sampled cells (walls, corners,
+    interior, dipoles) bit for bit against the crop oracle."""
+    import torch
+    w = wl.c3_large_dielectric(shape=(1024, 1024, 1024), nsteps=128)
+    nsteps = 128
+    rng = np.random.default_rng(9)
+    pts = [(0, 0, 0), (1023, 1023, 1023), (0, 1023, 512), (1023, 0, 1), (512, 511, 1023),
+           (700, 3, 300)] + [(s["i"], s["j"], s["k"]) for s in w.sources]
+    pts += [tuple(int(rng.integers(0, 1024)) for _ in range(3)) for _ in range(3)]
+    dev = torch.device("cuda:0")
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic")
+    try:
+        sim.set_materials(torch.from_numpy(w.eps).to(dev))
+        # seeded noise in the dependency cone of every sample (device-side
+        # fields; the crop oracle rebuilds each cone from the same host arrays)
+        fields = [torch.zeros(w.shape, dtype=torch.float32, device=dev) for _ in range(6)]
+        r = nsteps + 2
+        host_patches = []
+        for p in pts:
+            sl = tuple(slice(max(0, p[a] - r), min(1024, p[a] + r + 1)) for a in range(3))
+            vals = [rng.uniform(-1e-2, 1e-2, size=tuple(s.stop - s.start for s in sl)).astype(np.float32)
+                    for _ in range(6)]
+            host_patches.append((sl, vals))
+            for f, v in zip(fields, vals):
+                f[sl] = torch.from_numpy(v).to(dev)
+        torch.cuda.synchronize()
+        sim.set_fields(fields)   # PEC-tangential entries are zeroed by the library
+        for s in w.sources:
+            sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+        sim.step(nsteps)
+        band = sim.info(fdtd.INFO_SYSTOLIC_BAND)
+        slots = sim.info(fdtd.INFO_RING_SLOTS)
+        assert band < 64 and slots * band * 6 * 1024 < 2 ** 32, (band, slots)
+        idx = torch.tensor(pts, dtype=torch.long, device=dev)
+        got = []
+        for c in range(6):
+            sim.read_fields(mask=1 << c, out=[fields[c]] * 6)
+            sim.synchronize()
+            got.append(fields[c][idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy())
+        got = np.stack(got, axis=1)
+        del fields
+    finally:
+        sim.close()
+    # the same initial state on the host, for the crop oracle (patches applied
+    # in the same order, later ones overwriting earlier ones)
+    host = [np.zeros(w.shape, np.float32) for _ in range(6)]
+    for sl, vals in host_patches:
+        for f, v in zip(host, vals):
+            f[sl] = v
+    wl.zero_pec(host, w.bc)
+    w.fields = tuple(host)
+    bad = []
+    for n, p in enumerate(pts):
+        ref = _crop_oracle(w, p, nsteps)
+        if not np.array_equal(ref.view(np.uint32), got[n].view(np.uint32)):
+            bad.append((p, got[n], ref))
+    assert not bad, "%d/%d samples differ, first %s" % (len(bad), len(pts), bad[0])
+    assert np.count_nonzero(got) > got.size // 2

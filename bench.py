@@ -148,7 +148,7 @@ def cpu_baseline(w, budget_s: float = 15.0):
     """The FP32 oracle, as it stands, on a bounded centre crop of the workload."""
     import oracle
     nx, ny, nz = w.shape
-    cx, cy, cz = min(nx, 192), min(ny, 192), min(nz, 128)
+    cx, cy, cz = min(nx, 256), min(ny, 256), min(nz, 192)
     ox, oy, oz = (nx - cx) // 2, (ny - cy) // 2, (nz - cz) // 2
     eps = np.ascontiguousarray(w.eps[ox:ox + cx, oy:oy + cy, oz:oz + cz])
     shape = (cx, cy, cz)

@@ -168,7 +168,11 @@ int fdtd_add_source(fdtd_ctx* ctx, int comp, int32_t i, int32_t j, int32_t k,
 
 /* Advance nsteps (>= 0) full Yee steps.  Asynchronous: work is queued on the
  * context's stream.  The systolic scheme never falls back to another scheme;
- * configurations it does not cover return FDTD_EUNSUPPORTED. */
+ * configurations it does not cover return FDTD_EUNSUPPORTED: a periodic axis
+ * of fewer than 16 cells, a periodic x axis with arrays of 4 GiB or more, a
+ * periodic ring group (the tiles that differ only along periodic axes) larger
+ * than the resident grid, or an explicit band whose face rings would not fit
+ * 32-bit offsets. */
 int fdtd_step(fdtd_ctx* ctx, int64_t nsteps);
 
 /* Advance n independent contexts (grids of any sizes and boundaries, their
@@ -254,7 +258,11 @@ int fdtd_adjoint(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int wh
 enum {
     FDTD_OPT_SCHEME = 0,      /* switch scheme on a live context (state kept) */
     FDTD_OPT_BAND_STEPS = 1,  /* systolic: steps each tile stays resident:
-                                 1..64, larger values act as 64; 0 = auto  */
+                                 1..64, larger values act as 64; 0 = auto
+                                 (a cost model per grid, shortened when the
+                                 face rings of a longer band would pass the
+                                 4 GB of 32-bit offsets; an explicit value
+                                 that does not fit is FDTD_EUNSUPPORTED)    */
     FDTD_OPT_WORKGROUPS = 2,  /* systolic: persistent grid size, 0 = auto       */
     FDTD_OPT_SPIN_LIMIT = 3,  /* systolic: polls before a wait times out        */
     FDTD_OPT_PROFILE = 4      /* 1 = time every kernel launch with HIP events    */

@@ -144,7 +144,7 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None
         sim.close()
 
 
-def cpu_baseline(w, budget_s: float = 15.0):
+def cpu_baseline(w, budget_s: float = 25.0):
     """The FP32 oracle, as it stands, on a bounded centre crop of the workload."""
     import oracle
     nx, ny, nz = w.shape

@@ -192,6 +192,15 @@ __device__ __forceinline__ void dma_dword(__amdgpu_buffer_rsrc_t desc, unsigned 
                      :: "s"(lds), "v"(voff), "s"(desc) : "memory");
 }
 
+// An LDS address made opaque at this point of the program, so that the
+// per-component destinations derived from it are formed where they are used
+// instead of being kept live (in scalar registers) across the step loop.
+__device__ __forceinline__ unsigned lds_here(unsigned base)
+{
+    asm volatile("" : "+s"(base));
+    return base;
+}
+
 // Workgroup barrier for LDS traffic only: waits for this wavefront's LDS
 // operations, not for its outstanding global loads (__syncthreads() would
 // also drain those, which would stall on the prefetched faces).
@@ -673,10 +682,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                                  axis_pos<PER>(Uy, Yw, P.ny, pery, yy, yr);
                 const unsigned ozf = (sls_of(sl_up[4]) * step_f + (unsigned)yy * LS + (unsigned)zs) * 4u;
                 const unsigned ozc = (sls_of(sl_up[4]) * step_c + (unsigned)yy * LS + (unsigned)zs) * 4u;
+                const unsigned lxb = lds_offset(&xst[0][4 * w][0]);
+                const unsigned lyb = lds_offset(&yst[0][ydo ? 4 * w : 0][0]);
+                const unsigned lzb = lds_offset(&zst[0][4 * w][0]);
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) {
-                    const unsigned ly = lds_offset(&yst[q][ydo ? 4 * w : 0][0]);
-                    const unsigned lx = lds_offset(&xst[q][4 * w][0]);
+                    const unsigned ly = lds_here(lyb) + (unsigned)q * (unsigned)sizeof(yst[0]);
+                    const unsigned lx = lds_here(lxb) + (unsigned)q * (unsigned)sizeof(xst[0]);
+                    const unsigned lz = lds_here(lzb) + (unsigned)q * (unsigned)sizeof(zst[0]);
                     if (q < 6) {
                         dma_dword<DEV>(rrx, lx, okxr ? oxr + (unsigned)q * cb : kOOB);
                         if (ydo) dma_dword<DEV>(rry, ly, okyr ? oyr + (unsigned)q * cb : kOOB);
@@ -691,9 +704,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         if (ydo) dma_dword<false>(rca[q - 9], ly, oyf);
                     }
                     if (q < 6)
-                        dma_dword<DEV>(rrz, lds_offset(&zst[q][4 * w][0]), okz ? ozf + (unsigned)q * cb : kOOB);
+                        dma_dword<DEV>(rrz, lz, okz ? ozf + (unsigned)q * cb : kOOB);
                     else
-                        dma_dword<DEV>(rrc, lds_offset(&zst[q][4 * w][0]), okz ? ozc + (unsigned)(q - 6) * cb : kOOB);
+                        dma_dword<DEV>(rrc, lz, okz ? ozc + (unsigned)(q - 6) * cb : kOOB);
                 }
             };
             // Write the staged first-layer faces for components [Q0, Q0+NQ)

@@ -121,6 +121,9 @@ def test_null_context_calls_are_safe():
     assert lib.fdtd_synchronize(None) == fdtd.FDTD_EINVAL
     assert lib.fdtd_set_option(None, 0, 0) == fdtd.FDTD_EINVAL
     assert lib.fdtd_adjoint(None, None, None, 0) == fdtd.FDTD_EINVAL
+    assert lib.fdtd_set_field_scale(None, (ctypes.c_int32 * 6)()) == fdtd.FDTD_EINVAL
+    assert lib.fdtd_step_batch(None, 1, 1) == fdtd.FDTD_EINVAL
+    assert lib.fdtd_set_lossy_materials(None, *([None] * 6), 0) == fdtd.FDTD_EINVAL
     assert isinstance(lib.fdtd_last_error(None), bytes)
 
 

@@ -6,6 +6,9 @@ wall gets an artificial PEC plane at its own lower end (tangential E zeroed)
 so that its periodic wrap reproduces the wall; crops that start at the lower
 wall keep the real wall; interior crops wrap periodically.  Every artificial
 boundary is more than n cells from the cell and cannot reach it.
+
+With FP16 storage on the systolic scheme the grid is rounded once per band,
+cell by cell, so the crop takes the same rounding at the same steps.
 """
 import numpy as np
 
@@ -14,8 +17,9 @@ import oracle
 PEC, PER = 0, 1
 
 
-def crop_oracle(w, p, nsteps):
-    """FP32 oracle values of all six components at cell p after nsteps."""
+def crop_oracle(w, p, nsteps, fp16_band=None):
+    """FP32 oracle values of all six components at cell p after nsteps (with
+    fp16_band: the FP16-storage systolic schedule with that band length)."""
     r = nsteps + 2
     lo, hi, bc, art = [], [], [], []
     for a in range(3):
@@ -43,7 +47,13 @@ def crop_oracle(w, p, nsteps):
         q = (s["i"] - lo[0], s["j"] - lo[1], s["k"] - lo[2])
         if all(0 <= q[a] < hi[a] - lo[a] for a in range(3)):
             srcs.append(dict(s, i=q[0], j=q[1], k=q[2]))
-    out = oracle.run(fields, [eps] * 3, tuple(bc), w.dt, w.dx, nsteps, sources=srcs,
-                     dtype=np.float32)
+    if fp16_band:
+        from oracle import f16
+        cE16 = f16.coeff_E16([eps] * 3, tuple(bc), w.dt, w.dx)
+        out = f16.run_systolic(fields, cE16, np.float32(w.dt / w.dx), [nsteps], [fp16_band],
+                               sources=srcs)
+    else:
+        out = oracle.run(fields, [eps] * 3, tuple(bc), w.dt, w.dx, nsteps, sources=srcs,
+                         dtype=np.float32)
     loc = tuple(p[a] - lo[a] for a in range(3))
     return np.array([o[loc] for o in out], dtype=np.float32)

@@ -50,12 +50,14 @@ def _samples(w, rng):
     return pts
 
 
-@pytest.mark.parametrize("scheme,band", [("systolic", 4), ("systolic", 16), ("systolic", 0),
-                                         ("plain", 0)])
-def test_fullsize_sampled_bitwise(scheme, band):
+@pytest.mark.parametrize("scheme,band,storage", [("systolic", 4, "fp32"), ("systolic", 16, "fp32"),
+                                                 ("systolic", 0, "fp32"), ("plain", 0, "fp32"),
+                                                 ("systolic", 0, "fp16")])
+def test_fullsize_sampled_bitwise(scheme, band, storage):
     """band 0 = the band the library picks for this grid (the benchmark's
     launch: 48 steps here), over two bands (each sample's crop then spans
-    197^3 cells)."""
+    197^3 cells).  With FP16 storage (the benchmark's --storage fp16 launch)
+    the crops take the band-end rounding too."""
     import torch
     w = wl.c3_large_dielectric(nsteps=8)
     auto = scheme == "systolic" and band == 0
@@ -73,7 +75,7 @@ def test_fullsize_sampled_bitwise(scheme, band):
     wl.zero_pec(fields, w.bc)
     w.fields = tuple(fields)
     dev = torch.device("cuda:0")
-    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme)
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, storage=storage)
     try:
         if band:
             sim.set_option(fdtd.OPT_BAND_STEPS, band)
@@ -82,8 +84,9 @@ def test_fullsize_sampled_bitwise(scheme, band):
         for s in w.sources:
             sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
         sim.step(nsteps)
+        used_band = sim.info(fdtd.INFO_SYSTOLIC_BAND)
         if auto:
-            assert sim.info(fdtd.INFO_SYSTOLIC_BAND) == 48
+            assert used_band == 48
         idx = torch.tensor(pts, dtype=torch.long, device=dev)
         got = []
         for c in range(6):
@@ -97,7 +100,7 @@ def test_fullsize_sampled_bitwise(scheme, band):
         sim.close()
     bad = []
     for n, p in enumerate(pts):
-        ref = _crop_oracle(w, p, nsteps)
+        ref = _crop_oracle(w, p, nsteps, fp16_band=used_band if storage == "fp16" else None)
         if not np.array_equal(ref.view(np.uint32), got[n].view(np.uint32)):
             bad.append((p, got[n], ref))
     assert not bad, "%d/%d samples differ, first %s" % (len(bad), len(pts), bad[0])

@@ -207,3 +207,19 @@ def test_emulator_detects_a_missing_reuse_wait(monkeypatch):
     bad = [s for s in range(8) if run(s, True)]
     assert bad
     assert not run(bad[0], False)
+
+
+def test_crop_oracle_reproduces_full_fp16_runs():
+    """The same crop construction under the FP16-storage systolic schedule
+    (rounding of the whole grid every K steps is cell by cell, so a crop sees
+    the same rounding)."""
+    from oracle import f16
+    from tests.crop_oracle import crop_oracle
+    w = wl.random_dielectric((40, 36, 44), (PEC, PEC, PEC), 10, 3, 6, side=(2, 10), noise=0.1,
+                             dipoles=[(20, 18, 22)])
+    cE16 = f16.coeff_E16(w.eps3(), w.bc, w.dt, w.dx)
+    full = f16.run_systolic(w.fields, cE16, np.float32(w.dt / w.dx), [6], [4], sources=w.sources)
+    for p in [(0, 0, 0), (39, 35, 43), (0, 35, 20), (20, 18, 22), (21, 18, 21), (13, 7, 7)]:
+        ref = crop_oracle(w, p, 6, fp16_band=4)
+        val = np.array([f[p] for f in full], np.float32)
+        np.testing.assert_array_equal(ref.view(np.uint32), val.view(np.uint32), err_msg=str(p))

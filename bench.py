@@ -157,18 +157,61 @@ def cpu_baseline(w, budget_s: float = 25.0):
     cE = [oracle.round_f32(c) for c in oracle.coeff_E([eps] * 3, (0, 0, 0), w.dt, w.dx)]
     cH = np.float32(w.dt / w.dx)
     f = tuple(np.array(a) for a in fields)
+    oracle.step(cE, cH, f, 1, dtype=np.float32)          # thread start-up
     t0 = time.perf_counter()
-    oracle.step(cE, cH, f, 2, dtype=np.float32)
-    per = (time.perf_counter() - t0) / 2
-    n = int(max(2, min(5000, budget_s / max(per, 1e-6))))
+    oracle.step(cE, cH, f, 4, step0=1, dtype=np.float32)
+    per = (time.perf_counter() - t0) / 4
+    n = int(max(2, min(20000, budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
-    oracle.step(cE, cH, f, n, step0=2, dtype=np.float32)
+    oracle.step(cE, cH, f, n, step0=5, dtype=np.float32)
     t = time.perf_counter() - t0
     cells = cx * cy * cz
-    return {"value": cells * n / t, "unit": "cell updates/s", "cores": oracle.num_threads(),
+    threads = oracle.num_threads()
+    # the same oracle on one thread, over a few steps
+    oracle.set_threads(1)
+    try:
+        n1 = int(max(2, min(200, 4.0 / max(per * threads, 1e-6))))
+        t1 = time.perf_counter()
+        oracle.step(cE, cH, f, n1, step0=5 + n, dtype=np.float32)
+        t1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": cells * n / t, "unit": "cell updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "FP32 oracle, %dx%dx%d centre crop of the workload's permittivity, PEC, "
-                      "%d steps (%.1f s)" % (cx, cy, cz, n, t)}
+                      "%d steps (%.1f s)" % (cx, cy, cz, n, t),
+            "cpu_model": model,
+            "single_thread": {"value": cells * n1 / t1, "unit": "cell updates/s",
+                              "sample": "the same crop, %d steps on one thread (%.1f s)" % (n1, t1)}}
+
+
+def copy_bandwidth(gib: int = 2, reps: int = 5):
+    """Achievable HBM bandwidth of a plain device copy (read + write), for the
+    roofline beside the 8 TB/s peak: best of a few copies of `gib` GiB."""
+    import torch
+    n = gib * (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = max(best, 2.0 * n * 4 / (a.elapsed_time(b) / 1e3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
 
 
 def sweep(args):
@@ -421,6 +464,9 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "plain_E_kernel",
                 "launches": n, "avg_launch_ms": avg_s * 1e3}
 
+    copy_gbps = copy_bandwidth()
+    roof["copy_GBps"] = copy_gbps
+    roof["frac_of_copy"] = roof["achieved"] / copy_gbps
     out = {
         "metric": "cell updates/s, systolic vs plain Yee FDTD, %dx%dx%d FP32" % w.shape
                   + (", conductive" if sigma is not None else "")

@@ -134,3 +134,13 @@ def test_systolic_refuses_short_periodic_axis_without_fallback():
     assert e.value.code == fdtd.FDTD_EUNSUPPORTED
     assert sim.current_step == 0
     sim.close()
+
+
+@pytest.mark.parametrize("shape,bc", [((40, 36, 34), (PEC, PEC, PEC)), ((35, 20, 31), (PER, PEC, PER))])
+def test_systolic_fence_synchronisation_variant(monkeypatch, shape, bc):
+    """The alternative synchronisation (cached accesses, agent-scope release
+    and acquire fences around the progress counters, FDTD_SYSTOLIC_SYNC=fence)
+    gives the same bits as the device-scope default."""
+    monkeypatch.setenv("FDTD_SYSTOLIC_SYNC", "fence")
+    w = wl.small_case(shape, bc, seed=sum(shape), nsteps=19, dipoles=[tuple(s // 2 for s in shape)])
+    assert_bitwise(run_sys(w, band=6), oracle_f32(w), "fence variant %s" % (shape,))

@@ -2,8 +2,8 @@
 
 The systolic scheme performs exactly the update equations of the plain
 scheme, in an order that respects every dependency, so its FP32 result must
-be the same value bit for bit (the paper's claim that the scheme does the
-exact same update).  Cases cover several tiles per axis with ragged tails,
+be the same value bit for bit (Section 1: the scheme reorders the work and
+leaves the update itself unchanged).  Cases cover several tiles per axis with ragged tails,
 band lengths from 1 to more than the step count, sources on tile edges and
 corners, grids smaller than one tile, fewer persistent workgroups than
 tiles (schedule stress), calls split across bands, scheme switches on a live

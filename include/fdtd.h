@@ -172,7 +172,12 @@ int fdtd_add_source(fdtd_ctx* ctx, int comp, int32_t i, int32_t j, int32_t k,
  * of fewer than 16 cells, a periodic x axis with arrays of 4 GiB or more, a
  * periodic ring group (the tiles that differ only along periodic axes) larger
  * than the resident grid, or an explicit band whose face rings would not fit
- * 32-bit offsets. */
+ * 32-bit offsets.  A systolic launch on a grid with periodic axes needs each
+ * ring group resident at once; other persistent launches running at the same
+ * time on other streams (another context's systolic step, say) can hold the
+ * workgroup slots it needs, and then it waits until they finish or until its
+ * spin limit expires (FDTD_ETIMEOUT).  Launches on grids without periodic
+ * axes make progress with any residency. */
 int fdtd_step(fdtd_ctx* ctx, int64_t nsteps);
 
 /* Advance n independent contexts (grids of any sizes and boundaries, their

@@ -300,6 +300,49 @@ def batch_bench(nsims: int, steps: int, dims=(64, 192)):
     print(json.dumps(out), flush=True)
 
 
+def host_io_bench(args):
+    """A whole systolic run of the 1024x1024x512 workload from host (pageable
+    numpy) arrays: set_materials, set_fields, add_source, the workload's 500
+    steps, read_fields of all six components.  Reports the PCIe-inclusive rate
+    and the share of each phase; the headline `value` never includes these
+    transfers."""
+    import torch
+    from paper_2502_20610_amd import fdtd
+    w = make_workload(args.workload)
+    rng = np.random.default_rng(11)
+    fields = [rng.uniform(-1e-3, 1e-3, w.shape).astype(np.float32) for _ in range(6)]
+    nsteps = w.nsteps
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic")
+    try:
+        torch.cuda.synchronize()
+        t = [time.perf_counter()]
+        sim.set_materials(w.eps)
+        sim.set_fields(fields)
+        for s in w.sources:
+            sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"], s.get("first_step", 0))
+        sim.synchronize()
+        t.append(time.perf_counter())
+        sim.step(nsteps)
+        sim.synchronize()
+        t.append(time.perf_counter())
+        out = sim.read_fields()
+        t.append(time.perf_counter())
+    finally:
+        sim.close()
+    del out
+    total = t[3] - t[0]
+    up = 9 * w.cells * 4
+    down = 6 * w.cells * 4
+    res = {"metric": "cell updates/s of a whole run from host arrays (PCIe-inclusive), %dx%dx%d FP32"
+                     % w.shape,
+           "value": w.cells * nsteps / total, "unit": "cell updates/s", "higher_is_better": True,
+           "n_gpus": 1, "steps": nsteps, "upload_s": t[1] - t[0], "step_s": t[2] - t[1],
+           "download_s": t[3] - t[2], "upload_GBps": up / (t[1] - t[0]) / 1e9,
+           "download_GBps": down / (t[3] - t[2]) / 1e9,
+           "device_only_cups": w.cells * nsteps / (t[2] - t[1])}
+    print(json.dumps(res), flush=True)
+
+
 def adjoint_bench():
     """One gradient of the 256x256x128 inverse-design objective: the forward
     run (N steps with the monitor transform and checkpoints), the recompute of
@@ -347,6 +390,10 @@ def main():
     ap.add_argument("--sweep", default="",
                     help="comma-separated n: instead of the headline line, one JSON line per "
                          "bare-bones n^3 grid with both schemes (the Fig. 1 size sweep)")
+    ap.add_argument("--host-io", action="store_true",
+                    help="instead of the headline line, time a whole run from host arrays: "
+                         "materials and fields uploaded, the workload's steps, fields read back "
+                         "(the PCIe-inclusive rate)")
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the headline line, time the gradient of the 256x256x128 "
                          "inverse-design setup (forward, checkpointed recompute, reverse sweep)")
@@ -387,6 +434,9 @@ def main():
         return
     if args.adjoint:
         adjoint_bench()
+        return
+    if args.host_io:
+        host_io_bench(args)
         return
     if args.batch:
         batch_bench(args.batch, args.steps if args.steps != 128 else 2000,

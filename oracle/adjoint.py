@@ -31,6 +31,24 @@ Reverse step n, for the adjoint variables lE (of E) and lH (of H):
 
 starting from lE = lH = 0 after the last step; g accumulates dJ/dcE.  With
 cE = dt / (eps dx), dJ/deps = -g cE / eps (zero where cE is pinned to 0).
+
+With conductivity sigma (the semi-implicit conductive E half-step of the
+oracle's lossy step), the E half-step is
+
+    E^n = A (.) E^{n-1} + B (.) CH(H^{n-1/2}),
+    A = (1 - h) / (1 + h),  B = (dt / (eps dx)) / (1 + h),  h = sigma dt / (2 eps),
+
+so the reverse step gains the decay of the adjoint E and a second sum:
+
+    lE += dJ/dE^n
+    lE -= cH CE^T(lH)
+    gB += lE (.) CH(H^{n-1/2});   gA += lE (.) E^{n-1}
+    lH += CH^T(B (.) lE)
+    lE  = A (.) lE                                  (adjoint of E^{n-1})
+
+and, sigma held fixed, dJ/deps = gA dA/deps + gB dB/deps with
+dA/deps = 2 h / (eps (1 + h)^2) and dB/deps = -B / (eps (1 + h)) (zero on the
+PEC-pinned entries, where A = 1 and B = 0 do not depend on eps).
 """
 from __future__ import annotations
 
@@ -97,16 +115,30 @@ def adjoint_step(lE, lH, cE, cH):
     return lE, lH
 
 
+def adjoint_step_lossy(lE, lH, ca, cb, cH):
+    """Transpose of one source-free conductive forward step (E half-step with
+    decay ca and curl coefficient cb, then the H half-step)."""
+    t = curl_e_T(lH)
+    lE = tuple(e - cH * d for e, d in zip(lE, t))
+    u = curl_h_T(tuple(b * e for b, e in zip(cb, lE)))
+    lH = tuple(h + d for h, d in zip(lH, u))
+    lE = tuple(a * e for a, e in zip(ca, lE))
+    return lE, lH
+
+
 def _box(lo, hi):
     return tuple(slice(a, b) for a, b in zip(lo, hi))
 
 
 def forward_dft(fields, cE, cH, nsteps, mon_lo, mon_hi, comp, omega, dt, step0=0, sources=(),
-                keep_h=None):
+                keep_h=None, ca=None):
     """Run nsteps FP64 steps (one oracle call per step) from a copy of ``fields``.
 
-    Returns (F, final fields, kept), F being the complex monitor transform; if
-    ``keep_h`` is a box (lo, hi), kept[n-1] holds CH(H^{n-1/2}) over that box."""
+    With ``ca`` given the step is the conductive one, ``cE`` then being its
+    curl coefficient cb.  Returns (F, final fields, kept), F being the complex
+    monitor transform; if ``keep_h`` is a box (lo, hi), kept[n-1] holds
+    CH(H^{n-1/2}) over that box, followed by E^{n-1} there when ``ca`` is
+    given."""
     f = tuple(np.array(a, dtype=np.float64, order="C", copy=True) for a in fields)
     mb = _box(mon_lo, mon_hi)
     F = np.zeros(f[comp][mb].shape, np.complex128)
@@ -114,37 +146,57 @@ def forward_dft(fields, cE, cH, nsteps, mon_lo, mon_hi, comp, omega, dt, step0=0
     for n in range(1, nsteps + 1):
         if keep_h is not None:
             kb = _box(*keep_h)
-            kept.append(tuple(c[kb].copy() for c in curl_h(f[3:])))
-        oracle.step(cE, cH, f, 1, step0=step0 + n - 1, sources=sources, dtype=np.float64)
+            rec = [c[kb].copy() for c in curl_h(f[3:])]
+            if ca is not None:
+                rec += [e[kb].copy() for e in f[:3]]
+            kept.append(tuple(rec))
+        if ca is None:
+            oracle.step(cE, cH, f, 1, step0=step0 + n - 1, sources=sources, dtype=np.float64)
+        else:
+            oracle.step_lossy(ca, cE, cH, f, 1, step0=step0 + n - 1, sources=sources,
+                              dtype=np.float64)
         F += f[comp][mb] * np.exp(-1j * omega * n * dt)
     return F, f, kept
 
 
-def objective(fields, eps, bc, dt, dx, nsteps, mon_lo, mon_hi, comp, omega, step0=0, sources=()):
-    """J = sum |F|^2 of an FP64 forward run."""
-    cE = oracle.coeff_E(eps, bc, dt, dx)
+def _coefficients(eps, bc, dt, dx, sigma):
+    """(ca or None, curl coefficient) of the forward step, FP64."""
+    if sigma is None:
+        return None, oracle.coeff_E(eps, bc, dt, dx)
+    return oracle.coeff_lossy(eps, sigma, bc, dt, dx)
+
+
+def objective(fields, eps, bc, dt, dx, nsteps, mon_lo, mon_hi, comp, omega, step0=0, sources=(),
+              sigma=None):
+    """J = sum |F|^2 of an FP64 forward run (conductive when ``sigma`` is given)."""
+    ca, cE = _coefficients(eps, bc, dt, dx, sigma)
     F, _, _ = forward_dft(fields, cE, dt / dx, nsteps, mon_lo, mon_hi, comp, omega, dt,
-                          step0, sources)
+                          step0, sources, ca=ca)
     return float(np.sum(np.abs(F) ** 2))
 
 
 def gradient(fields, eps, bc, dt, dx, nsteps, mon_lo, mon_hi, comp, omega, des_lo, des_hi,
-             step0=0, sources=()):
-    """(J, dJ/deps_c over the design box for c = x, y, z) by the adjoint method, FP64."""
-    cE = oracle.coeff_E(eps, bc, dt, dx)
+             step0=0, sources=(), sigma=None):
+    """(J, dJ/deps_c over the design box for c = x, y, z) by the adjoint method,
+    FP64; with ``sigma`` (three conductivity arrays, held fixed) the forward
+    run is the conductive one."""
+    ca, cE = _coefficients(eps, bc, dt, dx, sigma)
+    lossy = ca is not None
     cH = dt / dx
     shape = fields[0].shape
-    F, _, _ = forward_dft(fields, cE, cH, nsteps, mon_lo, mon_hi, comp, omega, dt, step0, sources)
+    F, _, _ = forward_dft(fields, cE, cH, nsteps, mon_lo, mon_hi, comp, omega, dt, step0, sources,
+                          ca=ca)
     J = float(np.sum(np.abs(F) ** 2))
-    # CH(H^{n-1/2}) is needed over the whole grid by the reverse sweep's
-    # gradient term, but only its design-box part is kept
+    # CH(H^{n-1/2}) (and E^{n-1} when conductive) is needed over the whole grid
+    # by the reverse sweep's gradient terms, but only its design-box part is kept
     db = _box(des_lo, des_hi)
     _, _, kept = forward_dft(fields, cE, cH, nsteps, mon_lo, mon_hi, comp, omega, dt, step0,
-                             sources, keep_h=(des_lo, des_hi))
+                             sources, keep_h=(des_lo, des_hi), ca=ca)
     mb = _box(mon_lo, mon_hi)
     lE = tuple(np.zeros(shape) for _ in range(3))
     lH = tuple(np.zeros(shape) for _ in range(3))
-    g = [np.zeros(kept[0][0].shape) for _ in range(3)]
+    g = [np.zeros(kept[0][0].shape) for _ in range(3)]    # dJ/dcE, or dJ/dB
+    gA = [np.zeros(kept[0][0].shape) for _ in range(3)]   # dJ/dA (conductive)
     for n in range(nsteps, 0, -1):
         # dJ/dE_c^n(r) = 2 Re(conj(F(r)) exp(-i w n dt)) on the monitor box
         lE = tuple(np.array(a) for a in lE)
@@ -153,12 +205,22 @@ def gradient(fields, eps, bc, dt, dx, nsteps, mon_lo, mon_hi, comp, omega, des_l
         lE = tuple(e - cH * d for e, d in zip(lE, t))
         for c in range(3):
             g[c] += lE[c][db] * kept[n - 1][c]
+            if lossy:
+                gA[c] += lE[c][db] * kept[n - 1][3 + c]
         u = curl_h_T(tuple(cc * e for cc, e in zip(cE, lE)))
         lH = tuple(h + d for h, d in zip(lH, u))
+        if lossy:
+            lE = tuple(a * e for a, e in zip(ca, lE))
     grad = []
     for c in range(3):
         ce = cE[c][db]
-        e = np.asarray(eps[c], np.float64)[db]
-        grad.append(np.where(ce != 0.0, -g[c] * ce / e, 0.0))
-    del shape
+        e = np.asarray(eps[c], np.float32).astype(np.float64)[db]
+        if not lossy:
+            grad.append(np.where(ce != 0.0, -g[c] * ce / e, 0.0))
+            continue
+        sg = np.asarray(sigma[c], np.float32).astype(np.float64)[db]
+        h = sg * dt / (2.0 * e)
+        dA = 2.0 * h / (e * (1.0 + h) ** 2)
+        dB = -ce / (e * (1.0 + h))
+        grad.append(np.where(ce != 0.0, gA[c] * dA + g[c] * dB, 0.0))
     return J, tuple(grad)

@@ -137,8 +137,8 @@ int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
  * schemes run it (the systolic tile is then 11 cells wide along x, since ca
  * travels with the tile as three more per-cell coefficients);
  * fdtd_step_batch refuses (FDTD_EUNSUPPORTED) a batch that mixes
- * conductive and lossless contexts, and fdtd_adjoint returns
- * FDTD_EUNSUPPORTED for a context with conductivity.  A later
+ * conductive and lossless contexts; fdtd_adjoint differentiates the
+ * conductive update with respect to eps, sigma held fixed.  A later
  * fdtd_set_materials makes the context lossless again. */
 int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
                              const float* eps_z, const float* sigma_x, const float* sigma_y,
@@ -227,8 +227,14 @@ const char* fdtd_last_error(const fdtd_ctx* ctx);
  * runs the transposed half-steps backwards in time and accumulates
  * dJ/dcE = sum_n lambda_E^n (.) CH(H^{n-1/2}) over the design box, and
  * dJ/deps = -dJ/dcE * cE / eps (0 on the tangential entries of PEC walls,
- * whose cE is pinned at 0).  The forward run is stored every
- * checkpoint_every steps and recomputed segment by segment for the sweep. */
+ * whose cE is pinned at 0).  With conductivity (fdtd_set_lossy_materials)
+ * the update differentiated is the conductive one, sigma held fixed: the
+ * reverse sweep also decays the adjoint E by ca each step and accumulates
+ * dJ/dca = sum_n lambda_E^n (.) E^{n-1}, and
+ * dJ/deps = (dx / dt) cb ((1 - ca) dJ/dca - cb dJ/dcb)
+ * from the FP32 coefficients (0 where cb is pinned at 0).  The forward run
+ * is stored every checkpoint_every steps and recomputed segment by segment
+ * for the sweep. */
 typedef struct {
     uint32_t struct_size;   /* = sizeof(fdtd_adjoint_spec)                      */
     int32_t mon_comp;       /* monitored component: FDTD_EX, FDTD_EY or FDTD_EZ */
@@ -250,8 +256,8 @@ typedef struct {
  * memory.  On return the context holds the state after the forward run
  * (current step advanced by nsteps).  Device memory for the checkpoints
  * ((nsteps / checkpoint_every + 2) copies of the six fields), the adjoint
- * fields and the per-segment design-box history is allocated for the call
- * and freed before it returns.
+ * fields and the per-segment design-box history (3 arrays per step, 6 with
+ * conductivity) is allocated for the call and freed before it returns.
  * Errors: FDTD_EINVAL for a bad spec (component, empty or out-of-grid
  * boxes, nsteps < 1, checkpoint_every < 0, struct_size), FDTD_ENOMEM when
  * the working memory does not fit; the context is unchanged in both cases.

@@ -16,9 +16,19 @@
 //     lH += CE(cE (.) lE)         (transpose of the E half-step)
 // and dJ/deps = -g cE / eps = -g cE^2 dx / dt.
 //
+// With conductivity the E half-step is E^n = A (.) E^{n-1} + B (.) CH(H^{n-1/2})
+// (A the per-step decay, B the curl coefficient, both per cell: the
+// semi-implicit conductive update).  The reverse step then decays the adjoint
+// E by A before the new terms are added, weights the transposed curl by B,
+// and keeps a second sum gA += lE (.) E^{n-1} for dJ/dA.  With sigma held
+// fixed, dA/deps = (1 - A) B dx / dt and dB/deps = -B^2 dx / dt, so
+//     dJ/deps = (dx / dt) B ((1 - A) gA - B gB),
+// gB being the sum g above (zero where B is pinned to 0).
+//
 // The forward run stores the six fields every S steps; the reverse sweep
-// recomputes each segment from its checkpoint to record CH(H^{n-1/2}) over
-// the design box, then runs the segment's reverse steps.  The monitor
+// recomputes each segment from its checkpoint to record CH(H^{n-1/2}) (and
+// E^{n-1} with conductivity) over the design box, then runs the segment's
+// reverse steps.  The monitor
 // transform and the gradient accumulate in FP64; the adjoint fields are FP32.
 #include "fdtd_internal.h"
 
@@ -75,10 +85,13 @@ __global__ void adj_src_kernel(float* __restrict__ lE, Box b, int ny, int nz,
 }
 
 // out[c][q] = CH(H)_c at the design-box cells (backward differences, the
-// E half-step's curl, with the grid's periodic index arithmetic).
+// E half-step's curl, with the grid's periodic index arithmetic); with
+// conductivity also out[3 + c][q] = E_c there.
+template <bool LOSSY>
 __global__ void adj_curl_box_kernel(const float* __restrict__ Hx, const float* __restrict__ Hy,
-                                    const float* __restrict__ Hz, Box b, int nx, int ny, int nz,
-                                    float* __restrict__ out)
+                                    const float* __restrict__ Hz, const float* __restrict__ Ex,
+                                    const float* __restrict__ Ey, const float* __restrict__ Ez,
+                                    Box b, int nx, int ny, int nz, float* __restrict__ out)
 {
     const long long nb = b.cells();
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nb;
@@ -92,10 +105,17 @@ __global__ void adj_curl_box_kernel(const float* __restrict__ Hx, const float* _
         out[q] = (Hz[p] - Hz[at(i, jm, k)]) - (Hy[p] - Hy[at(i, j, km)]);
         out[nb + q] = (Hx[p] - Hx[at(i, j, km)]) - (Hz[p] - Hz[at(im, j, k)]);
         out[2 * nb + q] = (Hy[p] - Hy[at(im, j, k)]) - (Hx[p] - Hx[at(i, jm, k)]);
+        if (LOSSY) {
+            out[3 * nb + q] = Ex[p];
+            out[4 * nb + q] = Ey[p];
+            out[5 * nb + q] = Ez[p];
+        }
     }
 }
 
-// g[c][q] += lE_c(r) * ch[c][q] over the design box.
+// g[c][q] += lE_c(r) * ch[c][q] over the design box; with conductivity also
+// g[3 + c][q] += lE_c(r) * ch[3 + c][q] (the recorded E^{n-1}).
+template <bool LOSSY>
 __global__ void adj_grad_kernel(const float* __restrict__ lEx, const float* __restrict__ lEy,
                                 const float* __restrict__ lEz, Box b, int ny, int nz,
                                 const float* __restrict__ ch, double* __restrict__ g)
@@ -109,13 +129,23 @@ __global__ void adj_grad_kernel(const float* __restrict__ lEx, const float* __re
         g[q] += (double)lEx[p] * (double)ch[q];
         g[nb + q] += (double)lEy[p] * (double)ch[nb + q];
         g[2 * nb + q] += (double)lEz[p] * (double)ch[2 * nb + q];
+        if (LOSSY) {
+            g[3 * nb + q] += (double)lEx[p] * (double)ch[3 * nb + q];
+            g[4 * nb + q] += (double)lEy[p] * (double)ch[4 * nb + q];
+            g[5 * nb + q] += (double)lEz[p] * (double)ch[5 * nb + q];
+        }
     }
 }
 
-// dJ/deps_c = -g_c cE_c^2 dx / dt over the design box (0 where cE is pinned).
+// dJ/deps_c = -g_c cE_c^2 dx / dt over the design box (0 where cE is pinned);
+// with conductivity (ca non-null, cE then being B)
+// dJ/deps_c = (dx / dt) B ((1 - A) gA_c - B gB_c).
+template <bool LOSSY>
 __global__ void adj_eps_kernel(const double* __restrict__ g, const float* __restrict__ cEx,
-                               const float* __restrict__ cEy, const float* __restrict__ cEz, Box b,
-                               int ny, int nz, double dx_dt, float* __restrict__ out)
+                               const float* __restrict__ cEy, const float* __restrict__ cEz,
+                               const float* __restrict__ cax, const float* __restrict__ cay,
+                               const float* __restrict__ caz, Box b, int ny, int nz, double dx_dt,
+                               float* __restrict__ out)
 {
     const long long nb = b.cells();
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nb;
@@ -124,18 +154,26 @@ __global__ void adj_eps_kernel(const double* __restrict__ g, const float* __rest
         box_cell(b, q, i, j, k);
         const long long p = ((long long)i * ny + j) * nz + k;
         const float* ce[3] = {cEx, cEy, cEz};
+        const float* ca[3] = {cax, cay, caz};
         for (int c = 0; c < 3; ++c) {
             const double v = (double)ce[c][p];
-            out[c * nb + q] = v == 0.0 ? 0.0f : (float)(-g[c * nb + q] * v * v * dx_dt);
+            double d = -g[c * nb + q] * v * v * dx_dt;
+            if (LOSSY) d += (1.0 - (double)ca[c][p]) * v * dx_dt * g[(3 + c) * nb + q];
+            out[c * nb + q] = v == 0.0 ? 0.0f : (float)d;
         }
     }
 }
 
-// lE -= cH CH(lH): the transpose of the H half-step.  Same layout as the plain
-// E kernel: one (j, k) column per thread, streaming along x.
+// lE -= cH CH(lH): the transpose of the H half-step; with conductivity the
+// adjoint E first decays, lE = A (.) lE - cH CH(lH) (the transpose of the
+// previous reverse step's E half-step, carried here so that one pass over lE
+// does both).  Same layout as the plain E kernel: one (j, k) column per
+// thread, streaming along x.
+template <bool LOSSY>
 __global__ __launch_bounds__(kBX* kBY) void adj_E_kernel(
     float* __restrict__ Ex, float* __restrict__ Ey, float* __restrict__ Ez,
     const float* __restrict__ Hx, const float* __restrict__ Hy, const float* __restrict__ Hz,
+    const float* __restrict__ cax, const float* __restrict__ cay, const float* __restrict__ caz,
     float cH, int nx, int ny, int nz, int xchunk)
 {
     const int k = blockIdx.x * kBX + threadIdx.x;
@@ -156,9 +194,18 @@ __global__ __launch_bounds__(kBX* kBY) void adj_E_kernel(
         const long long b = (long long)i * plane;
         const long long p = b + row;
         const float hx = Hx[p], hy = Hy[p], hz = Hz[p];
-        Ex[p] -= cH * ((hz - Hz[b + row_jm]) - (hy - Hy[b + row_km]));
-        Ey[p] -= cH * ((hx - Hx[b + row_km]) - (hz - hz_im));
-        Ez[p] -= cH * ((hy - hy_im) - (hx - Hx[b + row_jm]));
+        const float dx_ = (hz - Hz[b + row_jm]) - (hy - Hy[b + row_km]);
+        const float dy_ = (hx - Hx[b + row_km]) - (hz - hz_im);
+        const float dz_ = (hy - hy_im) - (hx - Hx[b + row_jm]);
+        if (LOSSY) {
+            Ex[p] = cax[p] * Ex[p] - cH * dx_;
+            Ey[p] = cay[p] * Ey[p] - cH * dy_;
+            Ez[p] = caz[p] * Ez[p] - cH * dz_;
+        } else {
+            Ex[p] -= cH * dx_;
+            Ey[p] -= cH * dy_;
+            Ez[p] -= cH * dz_;
+        }
         hy_im = hy;
         hz_im = hz;
     }
@@ -219,8 +266,8 @@ struct Work {
     float* ckpt = nullptr;   // (nseg + 1) x 6 fields
     float* lam = nullptr;    // 6 adjoint fields
     double* F = nullptr;     // monitor transform, re/im
-    float* hist = nullptr;   // S x 3 x design cells: CH(H^{n-1/2})
-    double* g = nullptr;     // 3 x design cells: dJ/dcE
+    float* hist = nullptr;   // S x (3 or 6) x design cells: CH(H^{n-1/2}) (and E^{n-1})
+    double* g = nullptr;     // (3 or 6) x design cells: dJ/dcE (and dJ/dA)
     float* out = nullptr;    // 3 x design cells (host destination only)
     ~Work()
     {
@@ -239,8 +286,6 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         return fail(ctx, FDTD_EINVAL, "adjoint: spec is NULL or struct_size does not match");
     if (!grad_eps || (where != FDTD_HOST && where != FDTD_DEVICE))
         return fail(ctx, FDTD_EINVAL, "adjoint: grad_eps is NULL or where is invalid");
-    if (ctx->ca[0])
-        return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: conductive (lossy) materials are not supported");
     if (ctx->storage != FDTD_FP32)
         return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: needs FP32 storage");
     if (spec->mon_comp < FDTD_EX || spec->mon_comp > FDTD_EZ)
@@ -264,14 +309,16 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
     const int64_t seglen_max = std::min<int64_t>(S, N);
     const size_t nc = (size_t)ctx->ncell;
     const long long nmon = mon.cells(), ndes = des.cells();
+    const bool lossy = ctx->ca[0] != nullptr;
+    const int nrec = lossy ? 6 : 3;  // recorded design-box arrays per step
 
     Work w;
     hipError_t e;
     if ((e = hipMalloc(&w.ckpt, (size_t)(nseg + 1) * 6 * nc * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&w.lam, 6 * nc * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&w.F, 2 * (size_t)nmon * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.hist, (size_t)seglen_max * 3 * (size_t)ndes * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&w.g, 3 * (size_t)ndes * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&w.hist, (size_t)seglen_max * nrec * (size_t)ndes * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&w.g, nrec * (size_t)ndes * sizeof(double))) != hipSuccess ||
         (where == FDTD_HOST && (e = hipMalloc(&w.out, 3 * (size_t)ndes * sizeof(float))) != hipSuccess)) {
         (void)hipGetLastError();
         return fail(ctx, FDTD_ENOMEM, std::string("adjoint working memory: ") + hipGetErrorString(e));
@@ -321,7 +368,7 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
     float* lE[3] = {w.lam, w.lam + nc, w.lam + 2 * nc};
     float* lH[3] = {w.lam + 3 * nc, w.lam + 4 * nc, w.lam + 5 * nc};
     if ((e = hipMemsetAsync(w.lam, 0, 6 * nc * sizeof(float), st)) != hipSuccess ||
-        (e = hipMemsetAsync(w.g, 0, 3 * (size_t)ndes * sizeof(double), st)) != hipSuccess)
+        (e = hipMemsetAsync(w.g, 0, nrec * (size_t)ndes * sizeof(double), st)) != hipSuccess)
         return hip_fail(ctx, e, "adjoint: clear");
     dim3 grid;
     int xchunk;
@@ -334,10 +381,11 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
             return hip_fail(ctx, e, "adjoint: restore checkpoint");
         ctx->step_count = s0 + n0;
         for (int64_t l = 0; l < len; ++l) {
-            // CH(H^{n-1/2}) for step n = n0 + l + 1, before that step runs
-            hipLaunchKernelGGL(adj_curl_box_kernel, dim3(box_grid(ndes)), dim3(256), 0, st, ctx->field[3],
-                               ctx->field[4], ctx->field[5], des, ctx->nx, ctx->ny, ctx->nz,
-                               w.hist + (size_t)l * 3 * ndes);
+            // CH(H^{n-1/2}) (and E^{n-1}) for step n = n0 + l + 1, before that step runs
+            hipLaunchKernelGGL((lossy ? adj_curl_box_kernel<true> : adj_curl_box_kernel<false>),
+                               dim3(box_grid(ndes)), dim3(256), 0, st, ctx->field[3], ctx->field[4],
+                               ctx->field[5], ctx->field[0], ctx->field[1], ctx->field[2], des, ctx->nx,
+                               ctx->ny, ctx->nz, w.hist + (size_t)l * nrec * ndes);
             if (l + 1 < len) {
                 int rc = plain_step(ctx, 1);
                 if (rc) return rc;
@@ -347,12 +395,15 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
             const int64_t n = n0 + l + 1;
             double cr, ci;
             phase(n, &cr, &ci);
+            // lE = A lE - cH CH(lH), then the monitor samples of step n
+            hipLaunchKernelGGL((lossy ? adj_E_kernel<true> : adj_E_kernel<false>), grid, block, 0, st,
+                               lE[0], lE[1], lE[2], lH[0], lH[1], lH[2], ctx->ca[0], ctx->ca[1],
+                               ctx->ca[2], ctx->cH, ctx->nx, ctx->ny, ctx->nz, xchunk);
             hipLaunchKernelGGL(adj_src_kernel, dim3(box_grid(nmon)), dim3(256), 0, st, lE[comp], mon, ctx->ny,
                                ctx->nz, (const double*)w.F, cr, ci);
-            hipLaunchKernelGGL(adj_E_kernel, grid, block, 0, st, lE[0], lE[1], lE[2], lH[0], lH[1], lH[2],
-                               ctx->cH, ctx->nx, ctx->ny, ctx->nz, xchunk);
-            hipLaunchKernelGGL(adj_grad_kernel, dim3(box_grid(ndes)), dim3(256), 0, st, lE[0], lE[1], lE[2],
-                               des, ctx->ny, ctx->nz, (const float*)(w.hist + (size_t)l * 3 * ndes), w.g);
+            hipLaunchKernelGGL((lossy ? adj_grad_kernel<true> : adj_grad_kernel<false>),
+                               dim3(box_grid(ndes)), dim3(256), 0, st, lE[0], lE[1], lE[2], des, ctx->ny,
+                               ctx->nz, (const float*)(w.hist + (size_t)l * nrec * ndes), w.g);
             hipLaunchKernelGGL(adj_H_kernel, grid, block, 0, st, lE[0], lE[1], lE[2], ctx->coef[0],
                                ctx->coef[1], ctx->coef[2], lH[0], lH[1], lH[2], ctx->nx, ctx->ny, ctx->nz,
                                xchunk);
@@ -365,8 +416,9 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         return hip_fail(ctx, e, "adjoint: restore final state");
     ctx->step_count = s0 + N;
     float* dst = where == FDTD_DEVICE ? grad_eps : w.out;
-    hipLaunchKernelGGL(adj_eps_kernel, dim3(box_grid(ndes)), dim3(256), 0, st, (const double*)w.g,
-                       ctx->coef[0], ctx->coef[1], ctx->coef[2], des, ctx->ny, ctx->nz,
+    hipLaunchKernelGGL((lossy ? adj_eps_kernel<true> : adj_eps_kernel<false>), dim3(box_grid(ndes)),
+                       dim3(256), 0, st, (const double*)w.g, ctx->coef[0], ctx->coef[1], ctx->coef[2],
+                       ctx->ca[0], ctx->ca[1], ctx->ca[2], des, ctx->ny, ctx->nz,
                        ctx->cfg.dx / ctx->cfg.dt, dst);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(ctx, e, "launch(adjoint gradient)");
     if (where == FDTD_HOST &&

@@ -303,11 +303,14 @@ class DesignProblem:
     """An inverse-design objective for :func:`design_objective`: a base
     permittivity map (numpy float32, all three components share it), the
     boundaries and step sizes, the sources, and the fdtd_adjoint arguments
-    (monitor and design boxes, omega, nsteps, checkpoint_every).  Every
-    evaluation starts from zero fields at step 0."""
+    (monitor and design boxes, omega, nsteps, checkpoint_every).  An optional
+    conductivity map ``sigma`` (shared by the three components, held fixed)
+    makes the materials conductive.  Every evaluation starts from zero fields
+    at step 0."""
 
-    def __init__(self, eps, bc, dt, dx, sources, adjoint_args, device: int = 0):
+    def __init__(self, eps, bc, dt, dx, sources, adjoint_args, device: int = 0, sigma=None):
         self.eps = np.ascontiguousarray(eps, dtype=np.float32)
+        self.sigma = None if sigma is None else np.ascontiguousarray(sigma, dtype=np.float32)
         self.bc, self.dt, self.dx = tuple(bc), float(dt), float(dx)
         self.sources = list(sources)
         self.args = dict(adjoint_args)
@@ -320,7 +323,7 @@ class DesignProblem:
         eps[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = eps_design
         sim = Simulation(eps.shape, self.dt, self.dx, self.bc, scheme="plain", device=self.device)
         try:
-            sim.set_materials(eps)
+            sim.set_materials(eps, sigma=self.sigma)
             for s in self.sources:
                 sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"],
                                s.get("first_step", 0))

@@ -9,7 +9,10 @@ gradient sums; the oracle is FP64 throughout.  Checks:
   oracle's gradient;
 - the context holds the forward run's final state afterwards (bitwise equal
   to a plain run) and the device-output path equals the host-output path;
-- invalid specifications are refused without changing the context.
+- invalid specifications are refused without changing the context;
+- the same bars with conductive materials (sigma held fixed): random
+  conductivity, a small conductivity that stresses the (1 - ca) factor, and
+  an absorbing shell around a dielectric design block.
 """
 import numpy as np
 import pytest
@@ -172,3 +175,134 @@ def test_design_objective_autograd():
     fd = (Jfd(1e-4) - Jfd(-1e-4)) / 2e-4
     got = x.grad.numpy()[cell[0] - 6, cell[1] - 4, cell[2] - 4]
     assert abs(got - fd) <= 1e-3 * abs(fd), (got, fd)
+
+
+# ---- conductive materials (sigma held fixed, gradient in eps) -------------
+
+def _sigma(shape, seed, lo=0.0, hi=0.3):
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(lo, hi, shape).astype(np.float32) for _ in range(3)]
+
+
+def _sim_lossy(w, sig):
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="plain")
+    sim.set_materials(w.eps, sigma=sig)
+    if w.fields is not None:
+        sim.set_fields(w.fields)
+    for s in w.sources:
+        sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+    return sim
+
+
+def _fd_lossy(w, sig, c, cell, spec, h=1e-4):
+    """Central difference of the conductive FP64 objective in eps_c at one
+    cell, sigma fixed (coefficients rebuilt in FP64 from the perturbed eps)."""
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    _, base = oracle.coeff_lossy(eps3, sig, w.bc, w.dt, w.dx)
+
+    def J(d):
+        ca, cb = [], []
+        for q in range(3):
+            e = np.asarray(eps3[q], np.float32).astype(np.float64)
+            if q == c:
+                e[cell] += d
+            hh = np.asarray(sig[q], np.float32).astype(np.float64) * w.dt / (2.0 * e)
+            pinned = base[q] == 0.0
+            ca.append(np.where(pinned, 1.0, (1.0 - hh) / (1.0 + hh)))
+            cb.append(np.where(pinned, 0.0, (w.dt / (e * w.dx)) / (1.0 + hh)))
+        F, _, _ = adj.forward_dft(w.fields_or_zeros(), tuple(cb), w.dt / w.dx, spec["n"],
+                                  spec["mon_lo"], spec["mon_hi"], spec["comp"], spec["omega"],
+                                  w.dt, sources=w.sources, ca=tuple(ca))
+        return float(np.sum(np.abs(F) ** 2))
+    return (J(h) - J(-h)) / (2 * h)
+
+
+@pytest.mark.parametrize("name,shape,bc,n,ck,dlo,dhi,mlo,mhi", CASES)
+def test_conductive_adjoint_matches_oracle(name, shape, bc, n, ck, dlo, dhi, mlo, mhi):
+    w = wl.small_case(shape, bc, seed=len(name) + 40, nsteps=n, dipoles=[(3, 4, 5)])
+    sig = _sigma(w.shape, len(name) + 41)
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    J_ref, g_ref = adj.gradient(w.fields, eps3, w.bc, w.dt, w.dx, n, mlo, mhi, 2, 0.4, dlo, dhi,
+                                sources=w.sources, sigma=sig)
+    sim = _sim_lossy(w, sig)
+    J, g = sim.adjoint(n, 2, mlo, mhi, 0.4, dlo, dhi, checkpoint_every=ck)
+    assert sim.current_step == n
+    ref_state = oracle.run(w.fields, eps3, w.bc, w.dt, w.dx, n, sources=w.sources,
+                           dtype=np.float32, sigma=sig)
+    assert_bitwise(sim.read_fields(), ref_state, "state after conductive adjoint")
+    sim.close()
+    assert abs(J - J_ref) <= 1e-5 * J_ref, (J, J_ref)
+    assert _rel(g, np.stack(g_ref)) < 1e-4
+
+
+def test_conductive_adjoint_small_sigma():
+    """sigma of order 1e-3 (ca within 1e-4 of 1): the (1 - ca) factor of the
+    gradient is taken from the FP32 ca, which this case stresses."""
+    w = wl.small_case((14, 12, 10), (PEC, PEC, PEC), seed=47, nsteps=80, dipoles=[(3, 4, 5)])
+    sig = _sigma(w.shape, 48, 5e-4, 2e-3)
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    args = (80, 2, (10, 1, 1), (11, 11, 9), 0.4, (4, 3, 3), (8, 7, 6))
+    J_ref, g_ref = adj.gradient(w.fields, eps3, w.bc, w.dt, w.dx, 80, args[2], args[3], 2, 0.4,
+                                args[5], args[6], sources=w.sources, sigma=sig)
+    sim = _sim_lossy(w, sig)
+    J, g = sim.adjoint(*args, checkpoint_every=30)
+    sim.close()
+    assert abs(J - J_ref) <= 1e-5 * J_ref, (J, J_ref)
+    assert _rel(g, np.stack(g_ref)) < 1e-4
+
+
+def test_conductive_adjoint_absorbing_shell_finite_differences():
+    """A 48x48x32 PEC box lined with a graded conducting shell (6 cells,
+    sigma up to 0.4), a dielectric design block between a dipole and a
+    monitor plane, 400 steps: J and the gradient against the FP64 oracle,
+    and eight cells against FP64 central differences within 1e-3."""
+    shape = (48, 48, 32)
+    w = wl.random_dielectric(shape, (PEC, PEC, PEC), 6, 61, 400, side=(4, 12),
+                             dipoles=[(14, 24, 16)])
+    dlo, dhi = (20, 18, 12), (30, 30, 20)
+    rng = np.random.default_rng(62)
+    eps = np.array(w.eps)
+    eps[20:30, 18:30, 12:20] = rng.uniform(2.08, 12.25, (10, 12, 8)).astype(np.float32)
+    w.eps = eps
+    shell = wl.graded_shell(shape, thickness=6, sigma_max=0.4)
+    # a weakly conducting design block too, so both sums of the gradient matter there
+    shell[20:30, 18:30, 12:20] = rng.uniform(0.0, 0.05, (10, 12, 8)).astype(np.float32)
+    sig = [shell] * 3
+    spec = dict(n=400, mon_lo=(36, 16, 8), mon_hi=(37, 32, 24), comp=2, omega=0.36305)
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    J_ref, g_ref = adj.gradient(w.fields_or_zeros(), eps3, w.bc, w.dt, w.dx, 400, spec["mon_lo"],
+                                spec["mon_hi"], 2, spec["omega"], dlo, dhi, sources=w.sources,
+                                sigma=sig)
+    sim = _sim_lossy(w, sig)
+    J, g = sim.adjoint(400, 2, spec["mon_lo"], spec["mon_hi"], spec["omega"], dlo, dhi,
+                       checkpoint_every=150)
+    sim.close()
+    assert abs(J - J_ref) <= 1e-5 * J_ref
+    gr = np.stack(g_ref)
+    assert _rel(g, gr) < 1e-4
+    big = np.argwhere(np.abs(gr) > 1e-2 * np.abs(gr).max())
+    pick = big[rng.choice(len(big), 8, replace=False)]
+    for c, a, b, k in pick:
+        cell = (dlo[0] + a, dlo[1] + b, dlo[2] + k)
+        fd = _fd_lossy(w, sig, int(c), cell, spec)
+        assert abs(g[c, a, b, k] - fd) <= 1e-3 * abs(fd), (c, cell, g[c, a, b, k], fd)
+
+
+def test_conductive_design_objective_autograd():
+    import torch
+    w = wl.small_case((16, 14, 12), (PEC, PEC, PEC), seed=23, nsteps=60, dipoles=[(3, 7, 6)])
+    args = dict(nsteps=60, mon_comp=2, mon_lo=(12, 2, 2), mon_hi=(13, 12, 10), omega=0.4,
+                des_lo=(6, 4, 4), des_hi=(10, 9, 8), checkpoint_every=20)
+    sig = _sigma(w.shape, 24)[0]
+    prob = fdtd.DesignProblem(w.eps, w.bc, w.dt, w.dx, w.sources, args, sigma=sig)
+    x0 = np.array(w.eps[6:10, 4:9, 4:8])
+    x = torch.tensor(x0, dtype=torch.float32, requires_grad=True)
+    J = fdtd.design_objective(x, prob)
+    J.backward()
+    w.fields = None
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    J_ref, g_ref = adj.gradient(w.fields_or_zeros(), eps3, w.bc, w.dt, w.dx, 60, args["mon_lo"],
+                                args["mon_hi"], 2, 0.4, args["des_lo"], args["des_hi"],
+                                sources=w.sources, sigma=[sig] * 3)
+    assert abs(float(J.detach()) - J_ref) <= 1e-5 * J_ref
+    assert _rel(x.grad.numpy(), np.stack(g_ref).sum(axis=0)) < 1e-4

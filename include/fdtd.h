@@ -232,9 +232,14 @@ const char* fdtd_last_error(const fdtd_ctx* ctx);
  * reverse sweep also decays the adjoint E by ca each step and accumulates
  * dJ/dca = sum_n lambda_E^n (.) E^{n-1}, and
  * dJ/deps = (dx / dt) cb ((1 - ca) dJ/dca - cb dJ/dcb)
- * from the FP32 coefficients (0 where cb is pinned at 0).  The forward run
- * is stored every checkpoint_every steps and recomputed segment by segment
- * for the sweep. */
+ * from the FP32 coefficients (0 where cb is pinned at 0).
+ *
+ * The run is cut into segments of checkpoint_every steps.  The forward run
+ * records the design-box history of the last segment as it goes and stores
+ * the state at the start of every earlier segment, which the sweep
+ * recomputes.  checkpoint_every = 0 picks one segment (no checkpoint, no
+ * recompute) when the whole history fits in half the device memory free at
+ * the call, else 200.  The result does not depend on the segmenting. */
 typedef struct {
     uint32_t struct_size;   /* = sizeof(fdtd_adjoint_spec)                      */
     int32_t mon_comp;       /* monitored component: FDTD_EX, FDTD_EY or FDTD_EZ */
@@ -242,10 +247,11 @@ typedef struct {
     int32_t mon_hi[3];
     int32_t des_lo[3];      /* design box [des_lo, des_hi) per axis             */
     int32_t des_hi[3];
-    int32_t checkpoint_every;  /* steps between stored states; 0 = 200         */
+    int32_t checkpoint_every;  /* steps per segment; 0 = automatic             */
     double omega;           /* angular frequency (radians per unit time)        */
     int64_t nsteps;         /* steps of the forward run, >= 1                   */
     double objective;       /* out: J (FP64)                                    */
+    int64_t recomputed_steps;  /* out: forward steps run again by the sweep    */
 } fdtd_adjoint_spec;
 
 /* Run spec->nsteps steps forward from the current state (plain scheme, the
@@ -255,9 +261,10 @@ typedef struct {
  * component after component; `where` says whether grad_eps is host or device
  * memory.  On return the context holds the state after the forward run
  * (current step advanced by nsteps).  Device memory for the checkpoints
- * ((nsteps / checkpoint_every + 2) copies of the six fields), the adjoint
- * fields and the per-segment design-box history (3 arrays per step, 6 with
- * conductivity) is allocated for the call and freed before it returns.
+ * (one copy of the six fields per segment when there are several segments,
+ * none with one), the adjoint fields and one segment's design-box history
+ * (3 arrays per step, 6 with conductivity) is allocated for the call and
+ * freed before it returns.
  * Errors: FDTD_EINVAL for a bad spec (component, empty or out-of-grid
  * boxes, nsteps < 1, checkpoint_every < 0, struct_size), FDTD_ENOMEM when
  * the working memory does not fit; the context is unchanged in both cases.

@@ -25,10 +25,13 @@
 //     dJ/deps = (dx / dt) B ((1 - A) gA - B gB),
 // gB being the sum g above (zero where B is pinned to 0).
 //
-// The forward run stores the six fields every S steps; the reverse sweep
-// recomputes each segment from its checkpoint to record CH(H^{n-1/2}) (and
-// E^{n-1} with conductivity) over the design box, then runs the segment's
-// reverse steps.  The monitor
+// The run is cut into segments of S steps.  The forward run stores the six
+// fields at the start of every segment but the last, and records the last
+// segment's CH(H^{n-1/2}) (and E^{n-1} with conductivity) over the design box
+// as it goes; the reverse sweep runs that segment's reverse steps at once,
+// then, for each earlier segment, recomputes it from its checkpoint to record
+// the same history and runs its reverse steps.  When the whole history fits
+// in device memory, S = N: one segment, no checkpoint and no recompute.  The monitor
 // transform and the gradient accumulate in FP64; the adjoint fields are FP32.
 #include "fdtd_internal.h"
 
@@ -263,7 +266,7 @@ void column_grid(const fdtd_ctx* ctx, dim3* grid, int* xchunk)
 
 // Device buffers of one adjoint call, freed on every exit path.
 struct Work {
-    float* ckpt = nullptr;   // (nseg + 1) x 6 fields
+    float* ckpt = nullptr;   // checkpoints of segments 0..nseg-2, then the final state
     float* lam = nullptr;    // 6 adjoint fields
     double* F = nullptr;     // monitor transform, re/im
     float* hist = nullptr;   // S x (3 or 6) x design cells: CH(H^{n-1/2}) (and E^{n-1})
@@ -304,20 +307,39 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         des.n[a] = spec->des_hi[a] - spec->des_lo[a];
     }
     const int64_t N = spec->nsteps;
-    const int64_t S = spec->checkpoint_every ? spec->checkpoint_every : 200;
-    const int64_t nseg = (N + S - 1) / S;
-    const int64_t seglen_max = std::min<int64_t>(S, N);
     const size_t nc = (size_t)ctx->ncell;
     const long long nmon = mon.cells(), ndes = des.cells();
     const bool lossy = ctx->ca[0] != nullptr;
     const int nrec = lossy ? 6 : 3;  // recorded design-box arrays per step
+    const size_t step_hist = (size_t)nrec * (size_t)ndes * sizeof(float);
+    int64_t S = spec->checkpoint_every;
+    if (S == 0) {
+        // automatic: the whole history when it takes at most half the free
+        // device memory, else a checkpoint every 200 steps
+        size_t free_b = 0, total_b = 0;
+        (void)hipSetDevice(ctx->device);
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            free_b = 0;
+        }
+        S = (double)N * (double)step_hist <= 0.5 * (double)free_b ? N : 200;
+    }
+    S = std::min<int64_t>(S, N);
+    const int64_t nseg = (N + S - 1) / S;
+    const int64_t last0 = (nseg - 1) * S;  // steps done when the last segment starts
+    const int64_t nckpt = nseg > 1 ? nseg : 0;  // nseg - 1 checkpoints and the final state
+
+    // sizes in double first: a request this large cannot be met, and the
+    // size_t products below must not wrap
+    if ((double)nckpt * 6.0 * (double)nc * sizeof(float) + (double)S * (double)step_hist > 4.0e18)
+        return fail(ctx, FDTD_ENOMEM, "adjoint working memory: request too large");
 
     Work w;
     hipError_t e;
-    if ((e = hipMalloc(&w.ckpt, (size_t)(nseg + 1) * 6 * nc * sizeof(float))) != hipSuccess ||
+    if ((nckpt && (e = hipMalloc(&w.ckpt, (size_t)nckpt * 6 * nc * sizeof(float))) != hipSuccess) ||
         (e = hipMalloc(&w.lam, 6 * nc * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&w.F, 2 * (size_t)nmon * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&w.hist, (size_t)seglen_max * nrec * (size_t)ndes * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&w.hist, (size_t)S * step_hist)) != hipSuccess ||
         (e = hipMalloc(&w.g, nrec * (size_t)ndes * sizeof(double))) != hipSuccess ||
         (where == FDTD_HOST && (e = hipMalloc(&w.out, 3 * (size_t)ndes * sizeof(float))) != hipSuccess)) {
         (void)hipGetLastError();
@@ -346,8 +368,16 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
     if ((e = hipMemsetAsync(w.F, 0, 2 * (size_t)nmon * sizeof(double), st)) != hipSuccess)
         return hip_fail(ctx, e, "adjoint: clear transform");
     for (int64_t n = 1; n <= N; ++n) {
-        if ((n - 1) % S == 0 && (e = copy_state(w.ckpt + (size_t)((n - 1) / S) * 6 * nc, true)) != hipSuccess)
-            return hip_fail(ctx, e, "adjoint: checkpoint");
+        if (n - 1 < last0) {
+            if ((n - 1) % S == 0 && (e = copy_state(w.ckpt + (size_t)((n - 1) / S) * 6 * nc, true)) != hipSuccess)
+                return hip_fail(ctx, e, "adjoint: checkpoint");
+        } else {
+            // last segment: CH(H^{n-1/2}) (and E^{n-1}) recorded before step n
+            hipLaunchKernelGGL((lossy ? adj_curl_box_kernel<true> : adj_curl_box_kernel<false>),
+                               dim3(box_grid(ndes)), dim3(256), 0, st, ctx->field[3], ctx->field[4],
+                               ctx->field[5], ctx->field[0], ctx->field[1], ctx->field[2], des, ctx->nx,
+                               ctx->ny, ctx->nz, w.hist + (size_t)(n - 1 - last0) * nrec * ndes);
+        }
         int rc = plain_step(ctx, 1);
         if (rc) return rc;
         double cr, ci;
@@ -355,7 +385,7 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         hipLaunchKernelGGL(adj_dft_kernel, dim3(box_grid(nmon)), dim3(256), 0, st, ctx->field[comp], mon,
                            ctx->ny, ctx->nz, cr, ci, w.F);
     }
-    if ((e = copy_state(w.ckpt + (size_t)nseg * 6 * nc, true)) != hipSuccess)
+    if (nckpt && (e = copy_state(w.ckpt + (size_t)(nseg - 1) * 6 * nc, true)) != hipSuccess)
         return hip_fail(ctx, e, "adjoint: final state");
     std::vector<double> Fh(2 * (size_t)nmon);
     if ((e = hipMemcpyAsync(Fh.data(), w.F, Fh.size() * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
@@ -374,13 +404,17 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
     int xchunk;
     column_grid(ctx, &grid, &xchunk);
     const dim3 block(kBX, kBY);
+    int64_t recomputed = 0;
     for (int64_t m = nseg - 1; m >= 0; --m) {
         const int64_t n0 = m * S;  // steps done at the checkpoint
         const int64_t len = std::min<int64_t>(S, N - n0);
-        if ((e = copy_state(w.ckpt + (size_t)m * 6 * nc, false)) != hipSuccess)
-            return hip_fail(ctx, e, "adjoint: restore checkpoint");
-        ctx->step_count = s0 + n0;
-        for (int64_t l = 0; l < len; ++l) {
+        // the last segment's history was recorded by the forward run
+        if (m < nseg - 1) {
+            if ((e = copy_state(w.ckpt + (size_t)m * 6 * nc, false)) != hipSuccess)
+                return hip_fail(ctx, e, "adjoint: restore checkpoint");
+            ctx->step_count = s0 + n0;
+        }
+        for (int64_t l = 0; m < nseg - 1 && l < len; ++l) {
             // CH(H^{n-1/2}) (and E^{n-1}) for step n = n0 + l + 1, before that step runs
             hipLaunchKernelGGL((lossy ? adj_curl_box_kernel<true> : adj_curl_box_kernel<false>),
                                dim3(box_grid(ndes)), dim3(256), 0, st, ctx->field[3], ctx->field[4],
@@ -389,6 +423,7 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
             if (l + 1 < len) {
                 int rc = plain_step(ctx, 1);
                 if (rc) return rc;
+                ++recomputed;
             }
         }
         for (int64_t l = len - 1; l >= 0; --l) {
@@ -411,8 +446,9 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(ctx, e, "launch(adjoint sweep)");
     }
 
-    // ---- the state after the forward run, and the gradient
-    if ((e = copy_state(w.ckpt + (size_t)nseg * 6 * nc, false)) != hipSuccess)
+    // ---- the state after the forward run (still in place with one
+    // segment), and the gradient
+    if (nckpt && (e = copy_state(w.ckpt + (size_t)(nseg - 1) * 6 * nc, false)) != hipSuccess)
         return hip_fail(ctx, e, "adjoint: restore final state");
     ctx->step_count = s0 + N;
     float* dst = where == FDTD_DEVICE ? grad_eps : w.out;
@@ -426,6 +462,7 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         return hip_fail(ctx, e, "adjoint: copy gradient");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "adjoint: synchronize");
     spec->objective = J;
+    spec->recomputed_steps = recomputed;
     return FDTD_OK;
 }
 

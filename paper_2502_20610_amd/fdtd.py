@@ -61,7 +61,8 @@ class AdjointSpec(ctypes.Structure):
                 ("mon_lo", ctypes.c_int32 * 3), ("mon_hi", ctypes.c_int32 * 3),
                 ("des_lo", ctypes.c_int32 * 3), ("des_hi", ctypes.c_int32 * 3),
                 ("checkpoint_every", ctypes.c_int32), ("omega", ctypes.c_double),
-                ("nsteps", ctypes.c_int64), ("objective", ctypes.c_double)]
+                ("nsteps", ctypes.c_int64), ("objective", ctypes.c_double),
+                ("recomputed_steps", ctypes.c_int64)]
 
 
 _lib = None
@@ -152,6 +153,7 @@ class Simulation:
         if rc != FDTD_OK:
             raise FdtdError(rc, self._lib.fdtd_last_error(None).decode())
         self._h = h
+        self.adjoint_recomputed_steps = None
 
     # -- helpers ------------------------------------------------------------
     def _check(self, rc: int) -> int:
@@ -275,7 +277,10 @@ class Simulation:
         """Run ``nsteps`` forward with the monitor transform, then the reverse
         sweep.  Returns (J, grad) with grad of shape (3, *design box) holding
         dJ/deps_x, dJ/deps_y, dJ/deps_z; with ``out`` (a torch CUDA tensor of
-        that shape) the gradient is written there on the device."""
+        that shape) the gradient is written there on the device.
+        ``checkpoint_every`` is the segment length (0: automatic); the number
+        of forward steps the sweep ran again is left in
+        ``self.adjoint_recomputed_steps``."""
         spec = AdjointSpec()
         spec.struct_size = ctypes.sizeof(AdjointSpec)
         spec.mon_comp = int(mon_comp)
@@ -292,10 +297,12 @@ class Simulation:
                 raise ValueError("out must be a contiguous float32 CUDA tensor of shape %s" % (shape,))
             self._check(self._lib.fdtd_adjoint(self._h, ctypes.byref(spec),
                                                ctypes.c_void_p(out.data_ptr()), DEVICE))
+            self.adjoint_recomputed_steps = int(spec.recomputed_steps)
             return spec.objective, out
         g = np.zeros(shape, np.float32)
         self._check(self._lib.fdtd_adjoint(self._h, ctypes.byref(spec),
                                            ctypes.c_void_p(g.ctypes.data), HOST))
+        self.adjoint_recomputed_steps = int(spec.recomputed_steps)
         return spec.objective, g
 
 

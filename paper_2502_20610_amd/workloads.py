@@ -211,7 +211,7 @@ def c5_adjoint(nsteps: int = 4000, seed: int = 5):
                  [dipole(EZ, 64, 128, 64, wave)])
     omega = 2.0 * math.pi / (12.0 * math.sqrt(2.08))
     args = dict(nsteps=nsteps, mon_comp=EZ, mon_lo=(192, 96, 32), mon_hi=(193, 160, 96),
-                omega=omega, des_lo=(96, 96, 56), des_hi=(160, 160, 72), checkpoint_every=200)
+                omega=omega, des_lo=(96, 96, 56), des_hi=(160, 160, 72), checkpoint_every=0)
     return w, args
 
 

@@ -1,15 +1,16 @@
 """Throughput benchmark of the FDTD hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|bare:N]
-                    [--schemes systolic,plain] [--no-cpu-baseline]
+                    [--schemes systolic,plain,plain_fused] [--no-cpu-baseline]
 
 A "step" is one full Yee time step (E half-step, sources, H half-step) over
 the whole grid of the workload.  The default workload is the 1024x1024x512
 PEC box with 2000 random dielectric boxes and three dipoles, FP32.  Inputs
 are resident in HBM before the timed region; the timed region is K steps
 bracketed by stream synchronisation.  Prints ONE JSON line for the headline
-scheme (systolic when available, else plain), with the other scheme's
-figures alongside, a roofline object for the dominant kernel (per-launch
+scheme (systolic when available, else plain), with the two plain schemes'
+figures alongside (one launch per half-step, and the fused one launch per
+step), a roofline object for the dominant kernel (per-launch
 device time from HIP events recorded on the library's stream inside the
 timed region) and the oracle timed on the host cores over a bounded sample.
 """
@@ -33,6 +34,8 @@ VALU_FP32_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 FLOPS_PER_CELL = 36            # 6 components x 6 flops (Section 2)
 PLAIN_E_BYTES, PLAIN_H_BYTES = 48, 36   # algorithmic bytes per cell, per half-step kernel
 PLAIN_BYTES_PER_UPDATE = PLAIN_E_BYTES + PLAIN_H_BYTES
+# fused plain step: E, H and cE in, E and H out
+PLAIN_FUSED_BYTES_PER_UPDATE = 60
 
 
 def systolic_bytes_per_update(tile, band, conductive=False, fp16=False):
@@ -130,7 +133,8 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         stats = {k: sim.kernel_stats(k) for k in (fdtd.KERNEL_PLAIN_E, fdtd.KERNEL_PLAIN_H,
-                                                   fdtd.KERNEL_SOURCES, fdtd.KERNEL_SYSTOLIC)}
+                                                   fdtd.KERNEL_SOURCES, fdtd.KERNEL_SYSTOLIC,
+                                                   fdtd.KERNEL_PLAIN_FUSED)}
         if scheme == "systolic":
             stats["info"] = {"grid": sim.info(fdtd.INFO_SYSTOLIC_GRID),
                              "band_steps": sim.info(fdtd.INFO_SYSTOLIC_BAND),
@@ -390,7 +394,7 @@ def main():
     ap.add_argument("--steps", type=int, default=128)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--schemes", default="systolic,plain")
+    ap.add_argument("--schemes", default="systolic,plain,plain_fused")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--band", type=int, default=0, help="systolic band length (0 = default)")
     ap.add_argument("--workgroups", type=int, default=0, help="systolic grid size (0 = auto)")
@@ -558,9 +562,17 @@ def main():
                 pb //= 2
             entry["alg_bytes_per_update"] = pb
             entry["alg_roofline_frac"] = c * pb / (HBM_PEAK_GBS * 1e9)
+        if scheme == "plain_fused":
+            nf, msf = st[fdtd.KERNEL_PLAIN_FUSED]
+            entry["avg_ms"] = msf / max(nf, 1)
+            pb = PLAIN_FUSED_BYTES_PER_UPDATE + (12 if sigma is not None else 0)
+            entry["alg_bytes_per_update"] = pb
+            entry["alg_roofline_frac"] = c * pb / (HBM_PEAK_GBS * 1e9)
         out[scheme] = entry
     if "plain" in results and "systolic" in results:
         out["systolic_over_plain"] = out["systolic"]["cups"] / out["plain"]["cups"]
+    if "plain_fused" in results and "systolic" in results:
+        out["systolic_over_plain_fused"] = out["systolic"]["cups"] / out["plain_fused"]["cups"]
     if sigma is not None:
         out["config"]["conductive"] = {"shell_cells": 16, "sigma_max": args.sigma}
     if args.storage == "fp16":

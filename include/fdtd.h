@@ -27,6 +27,13 @@
  *                        the x-y-z-t diagonal per step and exchange only their
  *                        boundary faces through device memory, synchronising
  *                        with neighbour flags (Sections 3 and 4).
+ *   FDTD_SCHEME_PLAIN_FUSED one kernel launch per step over the whole grid:
+ *                        E and H are read from one set of arrays and the new
+ *                        step is written to a second set, allocated on first
+ *                        use (six more arrays; the two sets then trade places
+ *                        every step).  FP32 storage only (else
+ *                        FDTD_EUNSUPPORTED from fdtd_step); conductivity is
+ *                        covered.
  *
  * Layout: every field and coefficient array is C order [nx][ny][nz]
  * (z fastest), one array per component (Ex, Ey, Ez, Hx, Hy, Hz); FP32, or
@@ -88,7 +95,7 @@ enum {
 };
 
 enum { FDTD_BC_PEC = 0, FDTD_BC_PERIODIC = 1 };
-enum { FDTD_SCHEME_PLAIN = 0, FDTD_SCHEME_SYSTOLIC = 1 };
+enum { FDTD_SCHEME_PLAIN = 0, FDTD_SCHEME_SYSTOLIC = 1, FDTD_SCHEME_PLAIN_FUSED = 2 };
 enum { FDTD_FP32 = 0, FDTD_FP16_STORAGE = 1 };
 enum { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_HY = 4, FDTD_HZ = 5 };
 enum { FDTD_HOST = 0, FDTD_DEVICE = 1 };
@@ -295,7 +302,8 @@ enum {
     FDTD_KERNEL_PLAIN_H = 1,   /* plain H half-step                        */
     FDTD_KERNEL_SOURCES = 2,   /* plain-scheme point-source injection      */
     FDTD_KERNEL_SYSTOLIC = 3,  /* persistent systolic kernel               */
-    FDTD_KERNEL_COUNT = 4
+    FDTD_KERNEL_PLAIN_FUSED = 4, /* fused plain step (one launch per step) */
+    FDTD_KERNEL_COUNT = 5
 };
 
 /* With FDTD_OPT_PROFILE on, the number of launches of a kernel and their

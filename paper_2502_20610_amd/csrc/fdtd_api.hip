@@ -340,7 +340,8 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
     for (int a = 0; a < 3; ++a)
         if (cfg->bc[a] != FDTD_BC_PEC && cfg->bc[a] != FDTD_BC_PERIODIC)
             return fail(nullptr, FDTD_EINVAL, "fdtd_create: bc must be FDTD_BC_PEC or FDTD_BC_PERIODIC");
-    if (cfg->scheme != FDTD_SCHEME_PLAIN && cfg->scheme != FDTD_SCHEME_SYSTOLIC)
+    if (cfg->scheme != FDTD_SCHEME_PLAIN && cfg->scheme != FDTD_SCHEME_SYSTOLIC &&
+        cfg->scheme != FDTD_SCHEME_PLAIN_FUSED)
         return fail(nullptr, FDTD_EINVAL, "fdtd_create: unknown scheme");
     if (cfg->storage != FDTD_FP32 && cfg->storage != FDTD_FP16_STORAGE)
         return fail(nullptr, FDTD_EINVAL, "fdtd_create: unknown storage");
@@ -465,6 +466,7 @@ int fdtd_destroy(fdtd_ctx* ctx)
     for (int c = 0; c < 6; ++c) {
         if (ctx->field[c]) (void)hipFree(ctx->field[c]);
         if (ctx->field16[c]) (void)hipFree(ctx->field16[c]);
+        if (ctx->alt[c]) (void)hipFree(ctx->alt[c]);
     }
     for (int c = 0; c < 3; ++c) {
         if (ctx->coef[c]) (void)hipFree(ctx->coef[c]);
@@ -717,6 +719,7 @@ int fdtd_step(fdtd_ctx* ctx, int64_t nsteps)
     if (nsteps == 0) return FDTD_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->scheme == FDTD_SCHEME_PLAIN) return plain_step(ctx, nsteps);
+    if (ctx->scheme == FDTD_SCHEME_PLAIN_FUSED) return plain_fused_step(ctx, nsteps);
     std::string why;
     if (!systolic_supported(ctx, &why)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: " + why);
     return systolic_step(ctx, nsteps);
@@ -816,7 +819,7 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
     if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
     switch (option) {
     case FDTD_OPT_SCHEME:
-        if (value != FDTD_SCHEME_PLAIN && value != FDTD_SCHEME_SYSTOLIC)
+        if (value != FDTD_SCHEME_PLAIN && value != FDTD_SCHEME_SYSTOLIC && value != FDTD_SCHEME_PLAIN_FUSED)
             return fail(ctx, FDTD_EINVAL, "set_option: unknown scheme");
         ctx->scheme = (int)value;
         return FDTD_OK;

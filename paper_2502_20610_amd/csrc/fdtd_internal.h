@@ -58,6 +58,7 @@ struct fdtd_ctx {
     uint16_t* coef16[3];
     int fexp[6];      // FP16 storage: power-of-two scale exponent per field component
     float* ca[3];     // E decay per step with conductivity; null when lossless
+    float* alt[6];    // second field set of the fused plain step (allocated on first use)
     float cH;
 
     std::vector<fdtd::SourceRec> sources;
@@ -101,6 +102,9 @@ void timing_end(fdtd_ctx* ctx, PendingTiming* t);
 
 // Plain scheme: advance n steps starting at ctx->step_count (plain.hip).
 int plain_step(fdtd_ctx* ctx, int64_t nsteps);
+// Fused plain scheme: one launch per step into the second field set, whose
+// pointers then trade places with ctx->field (plain.hip).
+int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps);
 
 // Systolic scheme (systolic.hip).
 int systolic_supported(const fdtd_ctx* ctx, std::string* why);

@@ -15,6 +15,8 @@
 // plain scheme therefore rounds the fields after every half-step.
 #include "fdtd_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 constexpr int kBX = 64;  // threads along z (one wavefront)
@@ -140,6 +142,218 @@ __global__ __launch_bounds__(kBX* kBY) void plain_H_kernel(
     }
 }
 
+// ---- fused step: one launch per step, from (E, H) into other arrays
+//
+// A block of kFY + 1 wavefronts (one y row each) x 64 lanes (along z) streams
+// along x over a chunk of planes.  It owns kFY rows x 64 lanes of columns,
+// so every wavefront access is one aligned 256-byte run.  H' of the owned
+// cells also needs E' of the +y and +z neighbours.  The extra wavefront
+// computes E' of the next block's first row and, on its lanes 0..kFY-1, Ex'
+// and Ey' of the cell after each owned row (the next tile's first cell) --
+// both again from the inputs, as the neighbouring block does for its own
+// cells.  (Tiles of 63 lanes with lane 63 as the halo need no extra cells,
+// but their unaligned rows straddle cache lines and ran at half the rate.)
+// For each plane i the block
+// computes E' (sources included), stages it in LDS, and then H' of plane
+// i - 1 from E' of planes i - 1 and i; one plane past the chunk supplies the
+// chunk's last H'.  The inputs are only read and the outputs are other
+// arrays, so blocks never see each other's results.  Same operations, in the
+// same order, as the E half-step, the source additions (in table order) and
+// the H half-step of the two-launch step.  Algorithmic traffic: E, H and cE
+// in, E and H out -- 60 B per cell update.
+//
+// The loads of plane i + 1 are issued before the work on plane i, and the
+// barrier between the LDS write and the LDS reads waits for LDS traffic only,
+// so they stay in flight across it.  Blocks are numbered so that each XCD
+// (workgroups are dealt to the eight XCDs in turn) takes a contiguous range
+// of (z, y, x-chunk) tiles: neighbouring tiles, which share the cache lines
+// of their edge columns, then meet in one L2.
+constexpr int kFY = 7;   // owned rows per block
+constexpr int kFZ = 64;  // owned lanes per wavefront
+constexpr int kXCD = 8;  // XCDs of the device
+
+__device__ __forceinline__ void fused_lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <bool LOSSY>
+__global__ __launch_bounds__(64 * (kFY + 1)) void plain_fused_kernel(
+    const float* __restrict__ Ex, const float* __restrict__ Ey, const float* __restrict__ Ez,
+    const float* __restrict__ Hx, const float* __restrict__ Hy, const float* __restrict__ Hz,
+    float* __restrict__ oEx, float* __restrict__ oEy, float* __restrict__ oEz,
+    float* __restrict__ oHx, float* __restrict__ oHy, float* __restrict__ oHz,
+    const float* __restrict__ cEx, const float* __restrict__ cEy, const float* __restrict__ cEz,
+    const float* __restrict__ cax, const float* __restrict__ cay, const float* __restrict__ caz,
+    float cH, int nx, int ny, int nz, int gz, int gy, int ntiles, int xchunk,
+    const fdtd::DevSource* __restrict__ src, int nsrc, long long step)
+{
+    // E' of the last three planes (x, y, z components): a plane is read in
+    // the iteration after it is written and overwritten two iterations
+    // later, so one barrier per plane separates every write from the reads
+    // of the buffer's previous contents
+    __shared__ float st[3][3][kFY + 1][64];
+    __shared__ float sth[3][2][kFY];  // Ex', Ey' of the cell after each owned row
+    // tile of this block: launch order dealt round the XCDs, tile order
+    // contiguous per XCD (the launch has a multiple of kXCD blocks)
+    const int per_xcd = (int)(gridDim.x / kXCD);
+    const int tile = (int)(blockIdx.x % kXCD) * per_xcd + (int)(blockIdx.x / kXCD);
+    if (tile >= ntiles) return;  // whole block: before any barrier
+    const int tz = tile % gz, ty = (tile / gz) % gy, tx = tile / (gz * gy);
+    const int L = threadIdx.x, R = threadIdx.y;
+    const int k0 = tz * kFZ, j0 = ty * kFY;
+    const int i0 = tx * xchunk;
+    const int i1 = min(nx, i0 + xchunk);
+    const int k = (k0 + L) % nz, j = (j0 + R) % ny;  // halo and spare lanes wrap
+    const bool own = R < kFY && j0 + R < ny && k0 + L < nz;
+    const int km = k == 0 ? nz - 1 : k - 1;
+    const int jm = j == 0 ? ny - 1 : j - 1;
+    // lane r < kFY of the extra wavefront: Ex', Ey' at (row r, z = kh), whose
+    // -z neighbour is the last lane of row r (needed when that lane is owned)
+    const bool halo = R == kFY && L < kFY && k0 + 63 < nz;
+    const int kh = (k0 + 64) % nz, khm = (k0 + 63) % nz;
+    const int jr = (j0 + L) % ny;
+    const int jrm = jr == 0 ? ny - 1 : jr - 1;
+    const long long rowh = (long long)jr * nz + kh;
+    const long long rowh_jm = (long long)jrm * nz + kh;
+    const long long rowh_km = (long long)jr * nz + khm;
+    const long long plane = (long long)ny * nz;
+    const long long row = (long long)j * nz + k;
+    const long long row_jm = (long long)jm * nz + k;
+    const long long row_km = (long long)j * nz + km;
+    const int im0 = i0 == 0 ? nx - 1 : i0 - 1;
+    float hy_im = Hy[im0 * plane + row];
+    float hz_im = Hz[im0 * plane + row];
+    float hz_im_h = halo ? Hz[im0 * plane + rowh] : 0.f;  // Hz(i - 1) at the halo cell
+    // inputs of one plane at this lane's cell (and at its halo cell)
+    struct In {
+        float hx, hy, hz, hz_jm, hx_jm, hy_km, hx_km, cx, cy, cz, ex, ey, ez, ax, ay, az;
+        float h_ex, h_ey, h_cx, h_cy, h_hx, h_hy, h_hz, h_hz_jm, h_hx_km, h_hy_km, h_ax, h_ay;
+    };
+    auto load = [&](int ii) {
+        const long long b = (long long)ii * plane;
+        const long long p = b + row;
+        In v{};
+        v.hx = Hx[p];
+        v.hy = Hy[p];
+        v.hz = Hz[p];
+        v.hz_jm = Hz[b + row_jm];
+        v.hx_jm = Hx[b + row_jm];
+        v.hy_km = Hy[b + row_km];
+        v.hx_km = Hx[b + row_km];
+        v.cx = cEx[p];
+        v.cy = cEy[p];
+        v.cz = cEz[p];
+        v.ex = Ex[p];
+        v.ey = Ey[p];
+        v.ez = Ez[p];
+        if (LOSSY) {
+            v.ax = cax[p];
+            v.ay = cay[p];
+            v.az = caz[p];
+        }
+        if (halo) {
+            const long long q = b + rowh;
+            v.h_ex = Ex[q];
+            v.h_ey = Ey[q];
+            v.h_cx = cEx[q];
+            v.h_cy = cEy[q];
+            v.h_hx = Hx[q];
+            v.h_hy = Hy[q];
+            v.h_hz = Hz[q];
+            v.h_hz_jm = Hz[b + rowh_jm];
+            v.h_hx_km = Hx[b + rowh_km];
+            v.h_hy_km = Hy[b + rowh_km];
+            if (LOSSY) {
+                v.h_ax = cax[q];
+                v.h_ay = cay[q];
+            }
+        }
+        return v;
+    };
+    In cur = load(i0);
+    float pex = 0.f, pey = 0.f, pez = 0.f;  // E' of the previous plane
+    float phx = 0.f, phy = 0.f, phz = 0.f;  // H of the previous plane
+    for (int i = i0; i <= i1; ++i) {
+        const int ii = i == nx ? 0 : i;
+        In nxt = cur;
+        if (i < i1) nxt = load(i + 1 == nx ? 0 : i + 1);
+        float ex = cur.ex, ey = cur.ey, ez = cur.ez;
+        if (LOSSY) {
+            ex = cur.ax * ex;
+            ey = cur.ay * ey;
+            ez = cur.az * ez;
+        }
+        ex = (ex + cur.cx * (cur.hz - cur.hz_jm)) - cur.cx * (cur.hy - cur.hy_km);
+        ey = (ey + cur.cy * (cur.hx - cur.hx_km)) - cur.cy * (cur.hz - hz_im);
+        ez = (ez + cur.cz * (cur.hy - hy_im)) - cur.cz * (cur.hx - cur.hx_jm);
+        // the halo cell's Ex', Ey'
+        float ex_h = 0.f, ey_h = 0.f;
+        if (halo) {
+            ex_h = LOSSY ? cur.h_ax * cur.h_ex : cur.h_ex;
+            ey_h = LOSSY ? cur.h_ay * cur.h_ey : cur.h_ey;
+            ex_h = (ex_h + cur.h_cx * (cur.h_hz - cur.h_hz_jm)) - cur.h_cx * (cur.h_hy - cur.h_hy_km);
+            ey_h = (ey_h + cur.h_cy * (cur.h_hx - cur.h_hx_km)) - cur.h_cy * (cur.h_hz - hz_im_h);
+        }
+        // point sources of this step on plane ii (the table and the plane
+        // are the same for the whole block), in table order per cell
+        for (int q = 0; q < nsrc; ++q) {
+            if (src[q].i != ii) continue;
+            const long long m = step - src[q].first;
+            if (m < 0 || m >= src[q].len) continue;
+            const int c = src[q].comp;
+            if (src[q].j == j && src[q].k == k) {
+                const float w = src[q].wave[m];
+                ex = c == 0 ? ex + w : ex;
+                ey = c == 1 ? ey + w : ey;
+                ez = c == 2 ? ez + w : ez;
+            }
+            if (halo && src[q].j == jr && src[q].k == kh) {
+                const float w = src[q].wave[m];
+                ex_h = c == 0 ? ex_h + w : ex_h;
+                ey_h = c == 1 ? ey_h + w : ey_h;
+            }
+        }
+        const int bcur = (i - i0) % 3;
+        st[bcur][0][R][L] = ex;
+        st[bcur][1][R][L] = ey;
+        st[bcur][2][R][L] = ez;
+        if (halo) {
+            sth[bcur][0][L] = ex_h;
+            sth[bcur][1][L] = ey_h;
+        }
+        fused_lds_barrier();
+        if (i > i0 && own) {
+            // H' of plane i - 1: E' there (registers and LDS) and on plane i
+            const int pb = (i - i0 + 2) % 3;
+            const float ez_jp = st[pb][2][R + 1][L], ex_jp = st[pb][0][R + 1][L];
+            const int l1 = min(L + 1, 63);
+            const float ey_kp = L == 63 ? sth[pb][1][R] : st[pb][1][R][l1];
+            const float ex_kp = L == 63 ? sth[pb][0][R] : st[pb][0][R][l1];
+            const float nhx = (phx - cH * (ez_jp - pez)) + cH * (ey_kp - pey);
+            const float nhy = (phy - cH * (ex_kp - pex)) + cH * (ez - pez);
+            const float nhz = (phz - cH * (ey - pey)) + cH * (ex_jp - pex);
+            const long long po = (long long)(i - 1) * plane + row;
+            oEx[po] = pex;
+            oEy[po] = pey;
+            oEz[po] = pez;
+            oHx[po] = nhx;
+            oHy[po] = nhy;
+            oHz[po] = nhz;
+        }
+        pex = ex;
+        pey = ey;
+        pez = ez;
+        phx = cur.hx;
+        phy = cur.hy;
+        phz = cur.hz;
+        hy_im = cur.hy;
+        hz_im = cur.hz;
+        hz_im_h = cur.h_hz;
+        cur = nxt;
+    }
+}
+
 void plain_grid(const fdtd_ctx* ctx, dim3* grid, int* xchunk)
 {
     const int gx = (ctx->nz + kBX - 1) / kBX;
@@ -208,6 +422,51 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps)
         timing_end(ctx, &t);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "launch(plain H)");
+        ctx->step_count += 1;
+    }
+    return FDTD_OK;
+}
+
+int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps)
+{
+    if (ctx->storage != FDTD_FP32)
+        return fail(ctx, FDTD_EUNSUPPORTED, "fused plain step: needs FP32 storage");
+    const size_t bytes = (size_t)ctx->ncell * sizeof(float);
+    for (int c = 0; c < 6; ++c)
+        if (!ctx->alt[c]) {
+            hipError_t e = hipMalloc(&ctx->alt[c], bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->alt[c] = nullptr;
+                return fail(ctx, FDTD_ENOMEM, "fused plain step: second field set does not fit");
+            }
+        }
+    const int gz = (ctx->nz + kFZ - 1) / kFZ;
+    const int gy = (ctx->ny + kFY - 1) / kFY;
+    // enough blocks to fill the CUs several times over, with long x runs
+    const long long base = (long long)gz * gy;
+    long long nchunks = std::max<long long>(1, std::min<long long>((4096 + base - 1) / base, ctx->nx));
+    const int xchunk = (int)((ctx->nx + nchunks - 1) / nchunks);
+    const long long ntiles = base * ((ctx->nx + xchunk - 1) / xchunk);
+    if (ntiles > (1LL << 30)) return fail(ctx, FDTD_EUNSUPPORTED, "fused plain step: grid too large");
+    const dim3 grid((unsigned)((ntiles + kXCD - 1) / kXCD * kXCD));  // a multiple of kXCD
+    const dim3 block(64, kFY + 1);
+    const bool lossy = ctx->ca[0] != nullptr;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        float* const* in = ctx->field;
+        float* const* out = ctx->alt;
+        PendingTiming t;
+        timing_begin(ctx, FDTD_KERNEL_PLAIN_FUSED, &t);
+        hipLaunchKernelGGL((lossy ? plain_fused_kernel<true> : plain_fused_kernel<false>), grid, block, 0,
+                           ctx->stream, in[0], in[1], in[2], in[3], in[4], in[5], out[0], out[1], out[2],
+                           out[3], out[4], out[5], ctx->coef[0], ctx->coef[1], ctx->coef[2], ctx->ca[0],
+                           ctx->ca[1], ctx->ca[2], ctx->cH, ctx->nx, ctx->ny, ctx->nz, gz, gy,
+                           (int)ntiles, xchunk, (const DevSource*)ctx->dev_sources, ctx->dev_sources_n,
+                           (long long)ctx->step_count);
+        timing_end(ctx, &t);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(ctx, e, "launch(fused plain step)");
+        for (int c = 0; c < 6; ++c) std::swap(ctx->field[c], ctx->alt[c]);
         ctx->step_count += 1;
     }
     return FDTD_OK;

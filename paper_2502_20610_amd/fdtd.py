@@ -24,14 +24,14 @@ FDTD_OK, FDTD_EINVAL, FDTD_ENOMEM, FDTD_EHIP, FDTD_ESTATE, FDTD_EUNSUPPORTED, FD
 ERROR_NAMES = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ENOMEM", -3: "FDTD_EHIP",
                -4: "FDTD_ESTATE", -5: "FDTD_EUNSUPPORTED", -6: "FDTD_ETIMEOUT"}
 BC_PEC, BC_PERIODIC = 0, 1
-SCHEME_PLAIN, SCHEME_SYSTOLIC = 0, 1
+SCHEME_PLAIN, SCHEME_SYSTOLIC, SCHEME_PLAIN_FUSED = 0, 1, 2
 FP32, FP16_STORAGE = 0, 1
 HOST, DEVICE = 0, 1
 OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE = range(5)
-KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC = range(4)
+KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC, KERNEL_PLAIN_FUSED = range(5)
 (INFO_SYSTOLIC_GRID, INFO_SYSTOLIC_BAND, INFO_SYSTOLIC_TICKETS, INFO_RING_SLOTS, INFO_TILE_X,
  INFO_TILE_Y, INFO_TILE_Z) = range(7)
-SCHEMES = {"plain": SCHEME_PLAIN, "systolic": SCHEME_SYSTOLIC}
+SCHEMES = {"plain": SCHEME_PLAIN, "systolic": SCHEME_SYSTOLIC, "plain_fused": SCHEME_PLAIN_FUSED}
 
 # every symbol the header declares
 EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_lossy_materials",

@@ -219,7 +219,7 @@ def copy_bandwidth(gib: int = 2, reps: int = 5):
 
 
 def sweep(args):
-    """Fig. 1 analog: cell updates/s of both schemes against grid size, on the
+    """Fig. 1 analog: cell updates/s of the schemes against grid size, on the
     bare-bones workload (random boxes, fields U(-1, 1), PEC walls, no sources).
     Steps per point: the smallest multiple of the band above 100 that runs
     about 0.3 s at the expected rate, so small grids are timed long enough."""
@@ -243,6 +243,8 @@ def sweep(args):
             row[scheme] = {"cups": w.cells * steps / t, "steps": steps, "s": t}
         if row.get("systolic") and row.get("plain"):
             row["systolic_over_plain"] = row["systolic"]["cups"] / row["plain"]["cups"]
+        if row.get("systolic") and row.get("plain_fused"):
+            row["systolic_over_plain_fused"] = row["systolic"]["cups"] / row["plain_fused"]["cups"]
         print(json.dumps(row), flush=True)
 
 

@@ -89,6 +89,7 @@ def _cfg(**kw):
     (dict(dt=float("nan")), fdtd.FDTD_EINVAL),
     (dict(bc=(0, 2, 0)), fdtd.FDTD_EINVAL),
     (dict(scheme=7), fdtd.FDTD_EINVAL),
+    (dict(scheme=3), fdtd.FDTD_EINVAL),
     (dict(storage=5), fdtd.FDTD_EINVAL),
     (dict(device=-1), fdtd.FDTD_EINVAL),
 ])

@@ -949,6 +949,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
             publish<DEV>(A, me, 2u * (unsigned)tau);
             if (tau == t1) break;
+            // Past a PEC wall: once the box of the next step lies wholly past
+            // the upper wall of a PEC axis (the tile only moves further out),
+            // nothing the tile would compute reaches a grid cell, and its
+            // consumers read those positions as ghosts (+0, out-of-range
+            // loads).  The band-end level releases everything that waits on
+            // it: its consumers, the next occupant of its ring slot and its
+            // own next band.  (publish has completed every load in flight.)
+            if ((!perx && ox + tau + 1 >= P.nx) || (!pery && oy + tau + 1 >= P.ny) ||
+                (!perz && oz + tau + 1 >= P.nz)) {
+                publish<DEV>(A, me, 2u * (unsigned)t1);
+                break;
+            }
             if (!earlyH) {
                 if (!ensure_up(2u * (unsigned)tau)) {
                     aborted = true;

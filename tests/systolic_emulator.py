@@ -262,6 +262,13 @@ class Machine:
                     self.store_box(self.f[q], blo, S[q][hb])
             self.progress[me] = 2 * tau
             yield "H"
+            if tau < t1 and self._gone(me, tau + 1):
+                # every cell of B_{tau+1} (and later boxes) lies past a PEC
+                # wall: nothing the tile would compute reaches a grid cell, and
+                # its consumers read those positions as ghosts (+0).  The
+                # band-end level releases everything that waits on it.
+                self.progress[me] = 2 * t1
+                return
             if tau < t1:
                 for u in ups:
                     u = self.tile(band, *u)
@@ -269,6 +276,12 @@ class Machine:
                         yield from self.wait(u, 2 * tau)
                 self._load_forward(S, C, nlo, band, (a, b, c), tau - t0 - 1, comps=(3, 4, 5),
                                    coef=True)
+
+    def _gone(self, tile, tau):
+        """True if B_tau of the tile lies wholly past the upper wall of a PEC
+        axis (its lower corner is o + tau on every axis)."""
+        return any(not p and o * w + tau >= n
+                   for o, w, n, p in zip(tile, self.W, self.shape, self.per))
 
     @staticmethod
     def _shift(x):

@@ -1198,12 +1198,15 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 // Band length (steps per residency) for a launch over the contexts cs.  An
 // explicit option wins; otherwise a cost model picks it.  Per cell update, a
 // band of K steps costs the tile slots that cover the band's skewed
-// space-time region, prod_d (n_d + K + 30) / n_d on PEC axes (15 L_d / n_d
+// space-time region, prod_d (n_d + K / 2 + 30) / n_d on PEC axes (15 L_d / n_d
 // on periodic rings), times (1 + beta / K) for the band's start and end (box
 // load, state write-back, the pipeline refill behind the band barrier of each
-// tile); beta = 10 steps was fitted to the measured rate against K on 512^3
-// and predicts 64^3..1024x1024x512 within a few percent.  Over several grids
-// the cell-weighted mean is minimised (a batched launch asks per grid).
+// tile).  The region is n_d + K + 30 wide, but tiles leaving through the
+// upper wall stop once wholly outside, which removes about half of the K
+// term.  beta = 10 steps; the model picks the measured best band on
+// 1024x1024x512 and 512^3 (64) and comes within 2% of it on 256^3.  Over
+// several grids the cell-weighted mean is minimised (a batched launch asks
+// per grid).
 int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
     if (cs[0]->band_steps > 0) return (int)std::min<int64_t>(std::min(cs[0]->band_steps, kMaxBand), nsteps);
@@ -1222,7 +1225,7 @@ int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
             for (int d = 0; d < 3; ++d) {
                 const double slots = c->cfg.bc[d] == FDTD_BC_PERIODIC
                                          ? (double)W[d] * ((nd[d] + W[d] - 1) / W[d])
-                                         : (double)nd[d] + K + 30.0;
+                                         : (double)nd[d] + 0.5 * K + 30.0;
                 f *= slots / nd[d];
             }
             cost += f * (double)c->ncell;

@@ -745,38 +745,54 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 return wait_tiles<DEV>(A, ups, nup, level, &s_abort, &s_up);
             };
 
+            // Before the tile's first cell crosses the lower wall of a PEC
+            // axis its box holds ghosts only (+0, loaded out of range), and no
+            // grid cell depends on what an update would make of them (the
+            // grid cells they touch are PEC-tangential E, whose coefficient
+            // is 0): the step skips the updates and the faces (consumers read
+            // those positions as ghosts) and keeps the waits and the forward
+            // shells, the last of which carry the first grid cells in.  With
+            // every register +0, the skipped one-slot renaming changes nothing.
+            // (Only in the variant for grids with no periodic axis: the
+            // periodic variant, short of registers already, would spill.)
+            const bool skip = !PER && (ox + tau + WXk - 1 < 0 || oy + tau + WY - 1 < 0 || oz + tau + WZ - 1 < 0);
+            // offset of this lane's cell in the x face ring block
+            const unsigned ox_ = (sls * step_f + (unsigned)dy * LS + (unsigned)dz) * 4u;
+
             // ================= E half-step (H frame: register j <-> x = ox+tau-1+j)
             const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
             if (earlyE) prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
-#pragma unroll
-            for (int j = 1; j < PXk; ++j) {
-                xch[0][j - 1][ys][zs] = H[2][j];
-                xch[1][j - 1][ys][zs] = H[0][j];
-            }
-            lds_barrier();
-            {
-                const int ysm = (ys - 1) & (PY - 1);
+            if (!skip) {
 #pragma unroll
                 for (int j = 1; j < PXk; ++j) {
-                    const float hz_ym = xch[0][j - 1][ysm][zs];
-                    const float hx_ym = xch[1][j - 1][ysm][zs];
-                    const float hy_zm = from_zm(H[1][j]);
-                    const float hx_zm = from_zm(H[0][j]);
-                    // with conductivity the old E decays by ca first (ca = 1
-                    // reproduces the lossless update)
-                    const float e0 = LOSSY ? CA[0][j] * E[0][j] : E[0][j];
-                    const float e1 = LOSSY ? CA[1][j] * E[1][j] : E[1][j];
-                    const float e2 = LOSSY ? CA[2][j] * E[2][j] : E[2][j];
-                    const float ex = (e0 + C[0][j] * (H[2][j] - hz_ym)) - C[0][j] * (H[1][j] - hy_zm);
-                    const float ey = (e1 + C[1][j] * (H[0][j] - hx_zm)) - C[1][j] * (H[2][j] - H[2][j - 1]);
-                    const float ez = (e2 + C[2][j] * (H[1][j] - H[1][j - 1])) - C[2][j] * (H[0][j] - hx_ym);
-                    E[0][j - 1] = ex;
-                    E[1][j - 1] = ey;
-                    E[2][j - 1] = ez;
+                    xch[0][j - 1][ys][zs] = H[2][j];
+                    xch[1][j - 1][ys][zs] = H[0][j];
+                }
+                lds_barrier();
+                {
+                    const int ysm = (ys - 1) & (PY - 1);
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        C[q][j - 1] = C[q][j];
-                        if (LOSSY) CA[q][j - 1] = CA[q][j];
+                    for (int j = 1; j < PXk; ++j) {
+                        const float hz_ym = xch[0][j - 1][ysm][zs];
+                        const float hx_ym = xch[1][j - 1][ysm][zs];
+                        const float hy_zm = from_zm(H[1][j]);
+                        const float hx_zm = from_zm(H[0][j]);
+                        // with conductivity the old E decays by ca first (ca = 1
+                        // reproduces the lossless update)
+                        const float e0 = LOSSY ? CA[0][j] * E[0][j] : E[0][j];
+                        const float e1 = LOSSY ? CA[1][j] * E[1][j] : E[1][j];
+                        const float e2 = LOSSY ? CA[2][j] * E[2][j] : E[2][j];
+                        const float ex = (e0 + C[0][j] * (H[2][j] - hz_ym)) - C[0][j] * (H[1][j] - hy_zm);
+                        const float ey = (e1 + C[1][j] * (H[0][j] - hx_zm)) - C[1][j] * (H[2][j] - H[2][j - 1]);
+                        const float ez = (e2 + C[2][j] * (H[1][j] - H[1][j - 1])) - C[2][j] * (H[0][j] - hx_ym);
+                        E[0][j - 1] = ex;
+                        E[1][j - 1] = ey;
+                        E[2][j - 1] = ez;
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            C[q][j - 1] = C[q][j];
+                            if (LOSSY) CA[q][j - 1] = CA[q][j];
+                        }
                     }
                 }
             }
@@ -819,23 +835,24 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
 #undef FDTD_APPLY_SOURCE
 
-            // E of the first x layer of the tile (every lane: slot [dy][dz])
-            const unsigned ox_ = (sls * step_f + (unsigned)dy * LS + (unsigned)dz) * 4u;
+            if (!skip) {
+                // E of the first x layer of the tile (every lane: slot [dy][dz])
 #pragma unroll
-            for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)q * cb : kOOB, E[q][0]);
-            if (dy == 1) {
+                for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)q * cb : kOOB, E[q][0]);
+                if (dy == 1) {
 #pragma unroll
-                for (int j = 0; j < WXk; ++j)
+                    for (int j = 0; j < WXk; ++j)
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) ytr[q][j][zs] = E[q][j];
+                        for (int q = 0; q < 3; ++q) ytr[q][j][zs] = E[q][j];
+                }
+                if (dz == 1) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+#pragma unroll
+                        for (int j = 0; j < WXk; ++j) ztr[q][dy1][j] = E[q][j];
+                }
+                store_faces(std::integral_constant<int, 0>(), std::integral_constant<int, 3>(), std::integral_constant<int, 3>());
             }
-            if (dz == 1) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
-#pragma unroll
-                    for (int j = 0; j < WXk; ++j) ztr[q][dy1][j] = E[q][j];
-            }
-            store_faces(std::integral_constant<int, 0>(), std::integral_constant<int, 3>(), std::integral_constant<int, 3>());
             // publish (which also completes an early prefetch); a late prefetch
             // waits for the upwind neighbours only after this tile's own flag
             // is out, since on a periodic ring they wait on it in turn
@@ -877,59 +894,61 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // ================= H half-step (E frame: register j <-> x = ox+tau+j)
             const bool earlyH = tau < t1 && s_up >= 2u * (unsigned)tau;
             if (earlyH) prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, NQA - 3>());
-#pragma unroll
-            for (int j = 0; j < WXk; ++j) {
-                xch[0][j][ys][zs] = E[2][j];
-                xch[1][j][ys][zs] = E[0][j];
-            }
-            lds_barrier();
-            {
-                const int ysp = (ys + 1) & (PY - 1);
+            if (!skip) {
 #pragma unroll
                 for (int j = 0; j < WXk; ++j) {
-                    const float ez_yp = xch[0][j][ysp][zs];
-                    const float ex_yp = xch[1][j][ysp][zs];
-                    const float ey_zp = from_zp(E[1][j]);
-                    const float ex_zp = from_zp(E[0][j]);
-                    const float hx = (H[0][j + 1] - cH * (ez_yp - E[2][j])) + cH * (ey_zp - E[1][j]);
-                    const float hy = (H[1][j + 1] - cH * (ex_zp - E[0][j])) + cH * (E[2][j + 1] - E[2][j]);
-                    const float hz = (H[2][j + 1] - cH * (E[1][j + 1] - E[1][j])) + cH * (ex_yp - E[0][j]);
-                    H[0][j] = hx;
-                    H[1][j] = hy;
-                    H[2][j] = hz;
+                    xch[0][j][ys][zs] = E[2][j];
+                    xch[1][j][ys][zs] = E[0][j];
                 }
-            }
-            // now H registers j <-> x = ox+tau+j as well
-
-            // H (and, on the z face, the coefficients) of the first layer
-#pragma unroll
-            for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)(3 + q) * cb : kOOB, H[q][0]);
-            if (F16) {
-                const unsigned oxc_ = (sls * step_c3 + (unsigned)dy * LS + (unsigned)dz) * 4u;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) bst<SP>(rrxc, has_xc ? oxc_ + (unsigned)q * cb : kOOB, C[q][0]);
-            }
-            if (dy == 1) {
-#pragma unroll
-                for (int j = 0; j < WXk; ++j)
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        ytr[3 + q][j][zs] = H[q][j];
-                        if (F16) ytr[6 + q][j][zs] = C[q][j];
-                    }
-            }
-            if (dz == 1) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
+                lds_barrier();
+                {
+                    const int ysp = (ys + 1) & (PY - 1);
 #pragma unroll
                     for (int j = 0; j < WXk; ++j) {
-                        ztr[3 + q][dy1][j] = H[q][j];
-                        ztr[6 + q][dy1][j] = C[q][j];
-                        if (LOSSY) ztr[9 + q][dy1][j] = CA[q][j];
+                        const float ez_yp = xch[0][j][ysp][zs];
+                        const float ex_yp = xch[1][j][ysp][zs];
+                        const float ey_zp = from_zp(E[1][j]);
+                        const float ex_zp = from_zp(E[0][j]);
+                        const float hx = (H[0][j + 1] - cH * (ez_yp - E[2][j])) + cH * (ey_zp - E[1][j]);
+                        const float hy = (H[1][j + 1] - cH * (ex_zp - E[0][j])) + cH * (E[2][j + 1] - E[2][j]);
+                        const float hz = (H[2][j + 1] - cH * (E[1][j + 1] - E[1][j])) + cH * (ex_yp - E[0][j]);
+                        H[0][j] = hx;
+                        H[1][j] = hy;
+                        H[2][j] = hz;
                     }
+                }
+                // now H registers j <-> x = ox+tau+j as well
+
+                // H (and, on the z face, the coefficients) of the first layer
+#pragma unroll
+                for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)(3 + q) * cb : kOOB, H[q][0]);
+                if (F16) {
+                    const unsigned oxc_ = (sls * step_c3 + (unsigned)dy * LS + (unsigned)dz) * 4u;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) bst<SP>(rrxc, has_xc ? oxc_ + (unsigned)q * cb : kOOB, C[q][0]);
+                }
+                if (dy == 1) {
+#pragma unroll
+                    for (int j = 0; j < WXk; ++j)
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            ytr[3 + q][j][zs] = H[q][j];
+                            if (F16) ytr[6 + q][j][zs] = C[q][j];
+                        }
+                }
+                if (dz == 1) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+#pragma unroll
+                        for (int j = 0; j < WXk; ++j) {
+                            ztr[3 + q][dy1][j] = H[q][j];
+                            ztr[6 + q][dy1][j] = C[q][j];
+                            if (LOSSY) ztr[9 + q][dy1][j] = CA[q][j];
+                        }
+                }
+                store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, NQY - 3>(),
+                            std::integral_constant<int, NQA - 3>());
             }
-            store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, NQY - 3>(),
-                        std::integral_constant<int, NQA - 3>());
             if (tau == t1 && inB) {
                 // band end: the whole subdomain goes back to the field arrays
 #pragma unroll
@@ -1197,16 +1216,15 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 
 // Band length (steps per residency) for a launch over the contexts cs.  An
 // explicit option wins; otherwise a cost model picks it.  Per cell update, a
-// band of K steps costs the tile slots that cover the band's skewed
-// space-time region, prod_d (n_d + K / 2 + 30) / n_d on PEC axes (15 L_d / n_d
+// band of K steps costs the tile-steps that cover the band's skewed
+// space-time region, prod_d (n_d + s + 30) / n_d on PEC axes (15 L_d / n_d
 // on periodic rings), times (1 + beta / K) for the band's start and end (box
 // load, state write-back, the pipeline refill behind the band barrier of each
-// tile).  The region is n_d + K + 30 wide, but tiles leaving through the
-// upper wall stop once wholly outside, which removes about half of the K
-// term.  beta = 10 steps; the model picks the measured best band on
-// 1024x1024x512 and 512^3 (64) and comes within 2% of it on 256^3.  Over
-// several grids the cell-weighted mean is minimised (a batched launch asks
-// per grid).
+// tile).  The region is n_d + K + 30 wide, but tiles leaving through an
+// upper wall stop once wholly outside (s = K / 2 remains), and on grids with
+// no periodic axis tiles entering through a lower wall start only when their
+// first cell enters (s = 0).  beta = 10 steps.  Over several grids the
+// cell-weighted mean is minimised (a batched launch asks per grid).
 int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
     if (cs[0]->band_steps > 0) return (int)std::min<int64_t>(std::min(cs[0]->band_steps, kMaxBand), nsteps);
@@ -1222,10 +1240,16 @@ int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
             const int nd[3] = {c->nx, c->ny, c->nz};
             const int W[3] = {tile_x(c), 4 * kNW - 1, WZ};
             double f = 1.0 + kBeta / K;
+            // tiles leaving through an upper PEC wall stop once wholly outside;
+            // on grids with no periodic axis those entering through a lower
+            // wall also start only when their first cell enters
+            const bool anyper = c->cfg.bc[0] == FDTD_BC_PERIODIC || c->cfg.bc[1] == FDTD_BC_PERIODIC ||
+                                c->cfg.bc[2] == FDTD_BC_PERIODIC;
+            const double skew = anyper ? 0.5 * K : 0.0;
             for (int d = 0; d < 3; ++d) {
                 const double slots = c->cfg.bc[d] == FDTD_BC_PERIODIC
                                          ? (double)W[d] * ((nd[d] + W[d] - 1) / W[d])
-                                         : (double)nd[d] + 0.5 * K + 30.0;
+                                         : (double)nd[d] + skew + 30.0;
                 f *= slots / nd[d];
             }
             cost += f * (double)c->ncell;

@@ -212,6 +212,34 @@ class Machine:
         C = [self.load_box(self.cE[q], lo, P) for q in range(3)]
         cH = self.cH
         for tau in range(t0 + 1, t1 + 1):
+            if self._below(me, tau):
+                # before the tile's first cell crosses the lower wall of a PEC
+                # axis the box holds ghosts only (+0, loaded so and never
+                # changed), which reach no grid cell: no update and no faces.
+                # The last such step still takes the forward shells, which
+                # carry the first grid cells into the box.
+                last = tau < t1 and not self._below(me, tau + 1)
+                self.progress[me] = 2 * tau - 1
+                yield "E"
+                if last:
+                    for u in ups:
+                        u = self.tile(band, *u)
+                        if u is not None:
+                            yield from self.wait(u, 2 * tau - 1)
+                    S = [self._shift(x) for x in S]
+                    C = [self._shift(x) for x in C]
+                    nlo = (ox + tau, oy + tau, oz + tau)
+                    self._load_forward(S, C, nlo, band, (a, b, c), tau - t0 - 1, comps=(0, 1, 2))
+                self.progress[me] = 2 * tau
+                yield "H"
+                if last:
+                    for u in ups:
+                        u = self.tile(band, *u)
+                        if u is not None:
+                            yield from self.wait(u, 2 * tau)
+                    self._load_forward(S, C, nlo, band, (a, b, c), tau - t0 - 1, comps=(3, 4, 5),
+                                       coef=True)
+                continue
             # box lower corner at the start of step tau is (o + tau - 1)
             blo = (ox + tau, oy + tau, oz + tau)          # B_tau lower corner
             Ex, Ey, Ez, Hx, Hy, Hz = S
@@ -276,6 +304,15 @@ class Machine:
                         yield from self.wait(u, 2 * tau)
                 self._load_forward(S, C, nlo, band, (a, b, c), tau - t0 - 1, comps=(3, 4, 5),
                                    coef=True)
+
+    def _below(self, tile, tau):
+        """True if B_tau of the tile lies wholly below the lower wall of a PEC
+        axis (its cells there are o + tau .. o + tau + W - 1), on a grid with
+        no periodic axis (the kernel variant for periodic grids runs such
+        steps in full)."""
+        if any(self.per):
+            return False
+        return any(o * w + tau + w - 1 < 0 for o, w in zip(tile, self.W))
 
     def _gone(self, tile, tau):
         """True if B_tau of the tile lies wholly past the upper wall of a PEC

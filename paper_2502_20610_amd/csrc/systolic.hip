@@ -1221,10 +1221,14 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 // on periodic rings), times (1 + beta / K) for the band's start and end (box
 // load, state write-back, the pipeline refill behind the band barrier of each
 // tile).  The region is n_d + K + 30 wide, but tiles leaving through an
-// upper wall stop once wholly outside (s = K / 2 remains), and on grids with
-// no periodic axis tiles entering through a lower wall start only when their
-// first cell enters (s = 0).  beta = 10 steps.  Over several grids the
-// cell-weighted mean is minimised (a batched launch asks per grid).
+// upper wall stop once wholly outside: s = K / 2.  Tiles entering through a
+// lower wall skip their updates until their first cell enters (on grids with
+// no periodic axis), but they still hold a workgroup and keep pace with
+// their upwind neighbours, so they stay in the count: with s = 0 the model
+// took 64-step bands everywhere, and 64 grids of 16..64 cells per axis ran
+// at 21 instead of 36 G cell updates/s.  beta = 10 steps.  Over several
+// grids the cell-weighted mean is minimised (a batched launch asks per
+// grid).
 int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
     if (cs[0]->band_steps > 0) return (int)std::min<int64_t>(std::min(cs[0]->band_steps, kMaxBand), nsteps);
@@ -1240,12 +1244,7 @@ int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
             const int nd[3] = {c->nx, c->ny, c->nz};
             const int W[3] = {tile_x(c), 4 * kNW - 1, WZ};
             double f = 1.0 + kBeta / K;
-            // tiles leaving through an upper PEC wall stop once wholly outside;
-            // on grids with no periodic axis those entering through a lower
-            // wall also start only when their first cell enters
-            const bool anyper = c->cfg.bc[0] == FDTD_BC_PERIODIC || c->cfg.bc[1] == FDTD_BC_PERIODIC ||
-                                c->cfg.bc[2] == FDTD_BC_PERIODIC;
-            const double skew = anyper ? 0.5 * K : 0.0;
+            const double skew = 0.5 * K;
             for (int d = 0; d < 3; ++d) {
                 const double slots = c->cfg.bc[d] == FDTD_BC_PERIODIC
                                          ? (double)W[d] * ((nd[d] + W[d] - 1) / W[d])

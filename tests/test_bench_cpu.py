@@ -25,8 +25,12 @@ def test_systolic_bytes_per_update():
     # the band's state in binary16 (E, H out and in, cE in: 30 B)
     assert bench.systolic_bytes_per_update((15, 15, 15), 48, fp16=True) == pytest.approx(
         3 * 225 * 72 / 3375 + 30 / 48)
-    # the plain two-launch scheme moves 84 B per update
+    # the headline launch (15^3 tile, 64-step bands): 12.8 + 0.9375
+    assert bench.systolic_bytes_per_update((15, 15, 15), 64) == pytest.approx(13.7375)
+    # the plain two-launch scheme moves 84 B per update, the fused step 60 B
+    # (E, H and cE in, E and H out)
     assert bench.PLAIN_BYTES_PER_UPDATE == 84
+    assert bench.PLAIN_FUSED_BYTES_PER_UPDATE == 60
 
 
 def test_counter_traffic_needs_matching_source_and_launch():

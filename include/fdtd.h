@@ -187,6 +187,21 @@ int fdtd_add_source(fdtd_ctx* ctx, int comp, int32_t i, int32_t j, int32_t k,
  * axes make progress with any residency. */
 int fdtd_step(fdtd_ctx* ctx, int64_t nsteps);
 
+/* Prepare a later fdtd_step(ctx, nsteps): with the systolic scheme, build the
+ * launch plan of a call of exactly nsteps steps (the (band, tile) tickets in
+ * their topological order and the band tables of Section 3's diagonal
+ * traversal), upload it with blocking copies, and allocate its face rings
+ * and progress counters; with the fused plain scheme, allocate the second
+ * field set; with the plain scheme, nothing.  No step runs and the state is
+ * unchanged.  fdtd_step keeps the plan of its last call length (and the
+ * largest rings so far), so repeated calls of one length never rebuild or
+ * reallocate; this call moves that work ahead of a first call (say, out of
+ * a timed region).  A change of the materials' kind (lossless or
+ * conductive) or of the band option rebuilds the plan at the next call.
+ * Errors as for fdtd_step (FDTD_EUNSUPPORTED for a grid the systolic scheme
+ * does not cover, FDTD_ENOMEM if the rings do not fit). */
+int fdtd_prepare(fdtd_ctx* ctx, int64_t nsteps);
+
 /* Advance n independent contexts (grids of any sizes and boundaries, their
  * own materials and sources) by nsteps each in ONE persistent systolic launch
  * over a shared queue of subdomain tickets (the paper's tile traversal of
@@ -218,6 +233,48 @@ int64_t fdtd_current_step(const fdtd_ctx* ctx);
 /* Message describing the last failure of this context (never NULL).  With a
  * NULL context, the message of the last failed fdtd_create on this thread. */
 const char* fdtd_last_error(const fdtd_ctx* ctx);
+
+/* ---- discrete invariants (FP64 reductions on the device) ----------------
+ *
+ * The update of Section 2 (Eq. (1) and its cyclic permutations, E before H)
+ * with the coefficients the context applies is
+ *     E^{n+1} = E^n + cE (.) C_h H^{n+1/2},  H^{n+3/2} = H^{n+1/2} - cH C_e E^{n+1},
+ * C_h the backward-difference curl of the E half-step, C_e = C_h^T the
+ * forward-difference curl of the H half-step.  It keeps, exactly in exact
+ * arithmetic,
+ *   - the leapfrog energy Q = sum eps|E|^2 + sum |H|^2 + cH sum E . (C_h H)
+ *     of a lossless box, eps_c = cH / cE_c being the permittivity the
+ *     coefficients encode (cH (1 + ca) / (2 cb) with conductivity, where Q
+ *     decays instead);
+ *   - without sources, the backward divergence of eps E at every node whose
+ *     index is >= 1 along each PEC axis, and the forward divergence of H at
+ *     every cell.
+ * The sums skip the E entries frozen by PEC walls (read as eps E = 0 in the
+ * divergence).  Index arithmetic is periodic as in the update. */
+enum {
+    FDTD_INV_ENERGY = 0,      /* Q                                             */
+    FDTD_INV_E_ENERGY = 1,    /* sum eps |E|^2                                 */
+    FDTD_INV_H_ENERGY = 2,    /* sum |H|^2                                     */
+    FDTD_INV_DIVE_L1 = 3,     /* sum over nodes off the PEC walls of |div eps E| */
+    FDTD_INV_DIVE_L2SQ = 4,   /* the same sum of (div eps E)^2                 */
+    FDTD_INV_DIVH_L1 = 5,     /* sum over all cells of |div H|                 */
+    FDTD_INV_DIVH_L2SQ = 6,   /* sum of (div H)^2                              */
+    FDTD_INV_COUNT = 7
+};
+
+/* Evaluate the invariants of the current state (E^n, H^{n+1/2}) in FP64 from
+ * the stored values (binary16 storage decoded exactly).  sums: FDTD_INV_COUNT
+ * doubles (required).  div_e, div_h: nx*ny*nz doubles each, or NULL: the
+ * per-node divergence of eps E (0 on the PEC-wall nodes) and the per-cell
+ * divergence of H.  `where` applies to all three outputs.  The reduction is
+ * deterministic (fixed partition and summation order), so equal states give
+ * equal sums.  A host `where` synchronises the stream (and then reports a
+ * pending device error as the other synchronising calls do); a device
+ * `where` is stream-ordered.  A scratch area for the partial sums is
+ * allocated on the first call and kept until fdtd_destroy; host per-cell
+ * outputs are staged through a temporary device array.
+ * Errors: FDTD_EINVAL for a NULL sums pointer or a bad `where`. */
+int fdtd_invariants(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h, int where);
 
 /* ---- gradient with respect to permittivity (reverse-time adjoint) -------
  *
@@ -259,13 +316,18 @@ typedef struct {
     int64_t nsteps;         /* steps of the forward run, >= 1                   */
     double objective;       /* out: J (FP64)                                    */
     int64_t recomputed_steps;  /* out: forward steps run again by the sweep    */
+    int32_t isotropic;      /* 0: three gradient blocks (dJ/deps_x, _y, _z);
+                               1: one block, dJ/deps for a permittivity that
+                               drives all three components of a cell (the
+                               sum of the three, added in FP64)            */
 } fdtd_adjoint_spec;
 
 /* Run spec->nsteps steps forward from the current state (plain scheme, the
  * sources included) while accumulating F in FP64, then the reverse sweep.
  * Writes J to spec->objective and dJ/deps_c for c = x, y, z to grad_eps:
  * three FP32 blocks of the design box, each C-ordered [dx][dy][dz], laid out
- * component after component; `where` says whether grad_eps is host or device
+ * component after component (with spec->isotropic = 1, one such block
+ * holding their sum); `where` says whether grad_eps is host or device
  * memory.  On return the context holds the state after the forward run
  * (current step advanced by nsteps).  Device memory for the checkpoints
  * (one copy of the six fields per segment when there are several segments,
@@ -273,7 +335,8 @@ typedef struct {
  * (3 arrays per step, 6 with conductivity) is allocated for the call and
  * freed before it returns.
  * Errors: FDTD_EINVAL for a bad spec (component, empty or out-of-grid
- * boxes, nsteps < 1, checkpoint_every < 0, struct_size), FDTD_ENOMEM when
+ * boxes, nsteps < 1, checkpoint_every < 0, isotropic not 0 or 1,
+ * struct_size), FDTD_ENOMEM when
  * the working memory does not fit; the context is unchanged in both cases.
  * Synchronises the context's stream. */
 int fdtd_adjoint(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where);

@@ -477,6 +477,7 @@ int fdtd_destroy(fdtd_ctx* ctx)
         if (s.wave) (void)hipFree(s.wave);
     if (ctx->dev_sources) (void)hipFree(ctx->dev_sources);
     if (ctx->dev_error) (void)hipFree(ctx->dev_error);
+    if (ctx->inv_scratch) (void)hipFree(ctx->inv_scratch);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return FDTD_OK;
@@ -725,6 +726,20 @@ int fdtd_step(fdtd_ctx* ctx, int64_t nsteps)
     return systolic_step(ctx, nsteps);
 }
 
+int fdtd_prepare(fdtd_ctx* ctx, int64_t nsteps)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (nsteps < 0) return fail(ctx, FDTD_EINVAL, "prepare: nsteps must be >= 0");
+    if (nsteps == 0) return FDTD_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->scheme == FDTD_SCHEME_PLAIN) return FDTD_OK;
+    if (ctx->scheme == FDTD_SCHEME_PLAIN_FUSED) return plain_fused_prepare(ctx);
+    std::string why;
+    if (!systolic_supported(ctx, &why)) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: " + why);
+    return systolic_prepare(ctx, nsteps);
+}
+
 int fdtd_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps)
 {
     if (!ctxs || n < 1 || n > 65536) return FDTD_EINVAL;
@@ -804,6 +819,51 @@ const char* fdtd_last_error(const fdtd_ctx* ctx)
 {
     if (!ctx) return g_create_error.c_str();
     return ctx->err.c_str();
+}
+
+int fdtd_invariants(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h, int where)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (where != FDTD_HOST && where != FDTD_DEVICE) return fail(ctx, FDTD_EINVAL, "bad `where`");
+    if (!sums) return fail(ctx, FDTD_EINVAL, "invariants: sums is NULL");
+    (void)hipSetDevice(ctx->device);
+    hipError_t e;
+    if (!ctx->inv_scratch) {
+        if ((e = hipMalloc(&ctx->inv_scratch, invariants_scratch_doubles() * sizeof(double))) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->inv_scratch = nullptr;
+            return fail(ctx, FDTD_ENOMEM, std::string("invariants: scratch allocation: ") + hipGetErrorString(e));
+        }
+    }
+    const size_t bytes = (size_t)ctx->ncell * sizeof(double);
+    double* stage[2] = {nullptr, nullptr};
+    double* want[2] = {div_e, div_h};
+    for (int q = 0; q < 2; ++q) {
+        if (!want[q] || where == FDTD_DEVICE) continue;
+        if ((e = hipMalloc(&stage[q], bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            if (stage[0]) (void)hipFree(stage[0]);
+            return fail(ctx, FDTD_ENOMEM, "invariants: staging allocation failed");
+        }
+    }
+    double* de = where == FDTD_DEVICE ? div_e : stage[0];
+    double* dh = where == FDTD_DEVICE ? div_h : stage[1];
+    rc = invariants_launch(ctx, ctx->inv_scratch, de, dh);
+    const double* dsum = ctx->inv_scratch + invariants_sums_offset();
+    e = hipSuccess;
+    if (!rc) {
+        e = hipMemcpyAsync(sums, dsum, FDTD_INV_COUNT * sizeof(double), kind_from(where, false), ctx->stream);
+        for (int q = 0; q < 2 && e == hipSuccess; ++q)
+            if (stage[q]) e = hipMemcpyAsync(want[q], stage[q], bytes, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess && where == FDTD_HOST) e = hipStreamSynchronize(ctx->stream);
+    }
+    for (int q = 0; q < 2; ++q)
+        if (stage[q]) (void)hipFree(stage[q]);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(ctx, e, "invariants");
+    if (where == FDTD_HOST) return check_device_error(ctx);
+    return FDTD_OK;
 }
 
 int fdtd_adjoint(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where)

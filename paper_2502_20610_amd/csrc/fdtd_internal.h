@@ -83,6 +83,8 @@ struct fdtd_ctx {
 
     int* dev_error;  // device error word: bit 0 bad eps, bit 1 watchdog timeout
 
+    double* inv_scratch;  // partial sums of fdtd_invariants (allocated on first use)
+
     fdtd::SystolicState* sys;
     int sys_grid;        // persistent workgroups of the last systolic launch
     int sys_ring_slots;  // face-ring slots of the last systolic launch
@@ -105,16 +107,29 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps);
 // Fused plain scheme: one launch per step into the second field set, whose
 // pointers then trade places with ctx->field (plain.hip).
 int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps);
+// Allocate the fused step's second field set (plain.hip).
+int plain_fused_prepare(fdtd_ctx* ctx);
 
 // Systolic scheme (systolic.hip).
 int systolic_supported(const fdtd_ctx* ctx, std::string* why);
 int systolic_step(fdtd_ctx* ctx, int64_t nsteps);
 int systolic_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps);
+// Build and upload the plan of a call of nsteps steps, allocate its rings.
+int systolic_prepare(fdtd_ctx* ctx, int64_t nsteps);
 void systolic_release(fdtd_ctx* ctx);
 void systolic_tile(const fdtd_ctx* ctx, int* wx, int* wy, int* wz);
 
 // Reverse-time adjoint of a monitor objective (adjoint.hip).
 int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where);
+
+// Discrete invariants (invariants.hip): the reduction runs kInvBlocks blocks
+// whose partial records, and then the FDTD_INV_COUNT final sums, live in a
+// scratch area of invariants_scratch_doubles() doubles.
+constexpr int kInvBlocks = 1024;
+size_t invariants_scratch_doubles();
+// the final sums start at scratch + invariants_sums_offset()
+size_t invariants_sums_offset();
+int invariants_launch(fdtd_ctx* ctx, double* scratch, double* div_e, double* div_h);
 
 // Launch the source-injection kernel for the step that starts at step count s.
 int launch_sources(fdtd_ctx* ctx, int64_t s);

@@ -31,6 +31,9 @@ OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE = range(
 KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC, KERNEL_PLAIN_FUSED = range(5)
 (INFO_SYSTOLIC_GRID, INFO_SYSTOLIC_BAND, INFO_SYSTOLIC_TICKETS, INFO_RING_SLOTS, INFO_TILE_X,
  INFO_TILE_Y, INFO_TILE_Z) = range(7)
+# fdtd_invariants sums, in order
+INVARIANT_NAMES = ("energy", "e_energy", "h_energy", "div_e_l1", "div_e_l2sq", "div_h_l1",
+                   "div_h_l2sq")
 SCHEMES = {"plain": SCHEME_PLAIN, "systolic": SCHEME_SYSTOLIC, "plain_fused": SCHEME_PLAIN_FUSED}
 
 # every symbol the header declares
@@ -38,7 +41,8 @@ EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_lossy_
            "fdtd_set_fields",
            "fdtd_add_source", "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_synchronize",
            "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
-           "fdtd_kernel_stats", "fdtd_get_info", "fdtd_set_field_scale")
+           "fdtd_kernel_stats", "fdtd_get_info", "fdtd_set_field_scale", "fdtd_invariants",
+           "fdtd_prepare")
 
 
 class FdtdError(RuntimeError):
@@ -62,7 +66,7 @@ class AdjointSpec(ctypes.Structure):
                 ("des_lo", ctypes.c_int32 * 3), ("des_hi", ctypes.c_int32 * 3),
                 ("checkpoint_every", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("nsteps", ctypes.c_int64), ("objective", ctypes.c_double),
-                ("recomputed_steps", ctypes.c_int64)]
+                ("recomputed_steps", ctypes.c_int64), ("isotropic", ctypes.c_int32)]
 
 
 _lib = None
@@ -98,6 +102,8 @@ def load_library():
                                ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "fdtd_get_info": ([vp, ctypes.c_int, ctypes.POINTER(i64)], ctypes.c_int),
         "fdtd_set_field_scale": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "fdtd_invariants": ([vp, vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "fdtd_prepare": ([vp, i64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -230,6 +236,10 @@ class Simulation:
     def step(self, nsteps: int):
         self._check(self._lib.fdtd_step(self._h, int(nsteps)))
 
+    def prepare(self, nsteps: int):
+        """Build and upload what a call of ``nsteps`` steps needs (fdtd_prepare)."""
+        self._check(self._lib.fdtd_prepare(self._h, int(nsteps)))
+
     def read_fields(self, mask: int = 0x3F, out=None):
         """Return a tuple of six arrays (None where not selected).  With ``out``
         (six torch CUDA tensors) the copy is device-to-device in stream order."""
@@ -272,12 +282,38 @@ class Simulation:
         self._check(self._lib.fdtd_get_info(self._h, int(key), ctypes.byref(v)))
         return int(v.value)
 
+    def invariants(self, per_cell: bool = False, device_out=None):
+        """FP64 invariants of the current state (fdtd_invariants): a dict of the
+        sums in INVARIANT_NAMES order; with ``per_cell`` also the per-node
+        divergence of eps E and per-cell divergence of H as float64 arrays of
+        the grid's shape.  ``device_out`` = (sums, div_e, div_h) torch float64
+        CUDA tensors (div entries may be None) keeps every output on the device
+        (stream-ordered); the tensors are returned as given."""
+        if device_out is not None:
+            sums, de, dh = device_out
+            ptr = [ctypes.c_void_p(t.data_ptr()) if t is not None else None for t in (sums, de, dh)]
+            self._check(self._lib.fdtd_invariants(self._h, ptr[0], ptr[1], ptr[2], DEVICE))
+            return device_out
+        sums = np.zeros(len(INVARIANT_NAMES), np.float64)
+        de = np.empty(self.shape, np.float64) if per_cell else None
+        dh = np.empty(self.shape, np.float64) if per_cell else None
+        self._check(self._lib.fdtd_invariants(
+            self._h, ctypes.c_void_p(sums.ctypes.data),
+            ctypes.c_void_p(de.ctypes.data) if per_cell else None,
+            ctypes.c_void_p(dh.ctypes.data) if per_cell else None, HOST))
+        out = dict(zip(INVARIANT_NAMES, (float(v) for v in sums)))
+        if per_cell:
+            return out, de, dh
+        return out
+
     def adjoint(self, nsteps: int, mon_comp: int, mon_lo, mon_hi, omega: float, des_lo, des_hi,
-                checkpoint_every: int = 0, out=None):
+                checkpoint_every: int = 0, out=None, isotropic: bool = False):
         """Run ``nsteps`` forward with the monitor transform, then the reverse
         sweep.  Returns (J, grad) with grad of shape (3, *design box) holding
-        dJ/deps_x, dJ/deps_y, dJ/deps_z; with ``out`` (a torch CUDA tensor of
-        that shape) the gradient is written there on the device.
+        dJ/deps_x, dJ/deps_y, dJ/deps_z (with ``isotropic``, shape (*design
+        box): the derivative for one permittivity per cell, which the library
+        sums over the components); with ``out`` (a torch CUDA tensor of that
+        shape) the gradient is written there on the device.
         ``checkpoint_every`` is the segment length (0: automatic); the number
         of forward steps the sweep ran again is left in
         ``self.adjoint_recomputed_steps``."""
@@ -290,7 +326,8 @@ class Simulation:
         spec.checkpoint_every = int(checkpoint_every)
         spec.omega = float(omega)
         spec.nsteps = int(nsteps)
-        shape = (3,) + tuple(int(des_hi[a]) - int(des_lo[a]) for a in range(3))
+        spec.isotropic = 1 if isotropic else 0
+        shape = (() if isotropic else (3,)) + tuple(int(des_hi[a]) - int(des_lo[a]) for a in range(3))
         if out is not None:
             if not _is_torch(out) or not out.is_cuda or tuple(out.shape) != shape or \
                     str(out.dtype) != "torch.float32" or not out.is_contiguous():
@@ -334,11 +371,11 @@ class DesignProblem:
             for s in self.sources:
                 sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"],
                                s.get("first_step", 0))
-            J, g = sim.adjoint(**self.args)
+            # one permittivity per cell drives all three components
+            J, g = sim.adjoint(**self.args, isotropic=True)
         finally:
             sim.close()
-        # one permittivity per cell drives all three components
-        return J, g.sum(axis=0)
+        return J, g
 
 
 def design_objective(eps_design, problem: DesignProblem):

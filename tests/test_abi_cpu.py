@@ -125,6 +125,7 @@ def test_null_context_calls_are_safe():
     assert lib.fdtd_set_field_scale(None, (ctypes.c_int32 * 6)()) == fdtd.FDTD_EINVAL
     assert lib.fdtd_step_batch(None, 1, 1) == fdtd.FDTD_EINVAL
     assert lib.fdtd_set_lossy_materials(None, *([None] * 6), 0) == fdtd.FDTD_EINVAL
+    assert lib.fdtd_invariants(None, (ctypes.c_double * 7)(), None, None, 0) == fdtd.FDTD_EINVAL
     assert isinstance(lib.fdtd_last_error(None), bytes)
 
 

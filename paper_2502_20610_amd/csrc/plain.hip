@@ -427,7 +427,7 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps)
     return FDTD_OK;
 }
 
-int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps)
+int plain_fused_prepare(fdtd_ctx* ctx)
 {
     if (ctx->storage != FDTD_FP32)
         return fail(ctx, FDTD_EUNSUPPORTED, "fused plain step: needs FP32 storage");
@@ -441,6 +441,13 @@ int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps)
                 return fail(ctx, FDTD_ENOMEM, "fused plain step: second field set does not fit");
             }
         }
+    return FDTD_OK;
+}
+
+int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps)
+{
+    int rc = plain_fused_prepare(ctx);
+    if (rc) return rc;
     const int gz = (ctx->nz + kFZ - 1) / kFZ;
     const int gy = (ctx->ny + kFY - 1) / kFY;
     // enough blocks to fill the CUs several times over, with long x runs

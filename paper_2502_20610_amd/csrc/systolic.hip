@@ -62,6 +62,7 @@ constexpr int PX = 16, PZ = 16;         // slots along x (registers) and z (lane
 constexpr int WX = PX - 1, WZ = PZ - 1; // updated cells along x and z
 constexpr int WX_LOSSY = 11;              // updated cells along x with conductivity
 constexpr unsigned kOOB = 0xFFFFFFF0u;  // buffer offset that reads 0 / drops stores
+constexpr int kErrTimeout = 2;          // error-word bit: a bounded wait expired
 
 // longest band: the per-band source samples are staged in LDS
 constexpr int kMaxBand = 64;
@@ -301,11 +302,11 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
         unsigned v;
         while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
             if (++it > A.spin_limit) {
-                atomicOr(A.error, 2);
+                atomicOr(A.error, kErrTimeout);
                 *s_abort = 1;
                 break;
             }
-            if ((it & 255) == 0 && __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            if ((it & 255) == 0 && (__hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout)) {
                 *s_abort = 1;
                 break;
             }
@@ -392,9 +393,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     for (;;) {
         __syncthreads();
         if (tid == 0) {
-            // a raised error word (another workgroup timed out) drains the grid
+            // a raised timeout bit (another workgroup's wait expired) drains
+            // the grid; the bad-permittivity bit does not stop the update (it
+            // is reported at the next synchronising call, as for the plain
+            // scheme)
             const int err = __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_ticket = err ? A.nt : (int)atomicAdd(A.counter, 1u);
+            s_ticket = (err & kErrTimeout) ? A.nt : (int)atomicAdd(A.counter, 1u);
         }
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);  // wave-uniform
@@ -1039,6 +1043,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     }
 }
 
+// A member of a batched launch takes the shared launch's timeout bit into its
+// own error word (keeping its own bits).
+__global__ void or_timeout(int* dst, const int* src)
+{
+    if (threadIdx.x == 0) {
+        const int v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout;
+        if (v) atomicOr(dst, v);
+    }
+}
+
 __global__ void fill_u32(unsigned* p, unsigned v, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1382,7 +1396,9 @@ int upload_plan(fdtd_ctx* lead, SystolicState* L, fdtd_ctx* const* cs, int n)
 // cs[0]'s stream (the others' streams wait for it and it for them).
 // kcap: the longest band an automatic choice may take (lowered when the face
 // rings of a longer band would not fit their 32-bit offsets).
-int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand)
+// With run = false the launch is only prepared: plans built and uploaded,
+// rings and counters allocated, nothing queued.
+int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool run = true)
 {
     fdtd_ctx* lead = cs[0];
     if (nsteps > (int64_t(1) << 24)) return fail(lead, FDTD_EINVAL, "systolic: at most 2^24 steps per call");
@@ -1471,7 +1487,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand)
         // an automatic band: take the longest one whose rings fit
         const size_t per_step = (size_t)R * 6 * face;
         const int fit = (int)std::min<size_t>((((size_t)1 << 32) - 1) / per_step, (size_t)Kmax - 1);
-        return launch(cs, n, nsteps, std::max(1, fit));
+        return launch(cs, n, nsteps, std::max(1, fit), run);
     }
     if (rf6 >= ((size_t)1 << 32))
         return fail(lead, FDTD_EUNSUPPORTED,
@@ -1493,6 +1509,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand)
         (void)hipGetLastError();
         return fail(lead, FDTD_ENOMEM, "systolic: ticket counter");
     }
+    if (!run) return FDTD_OK;
     // per-simulation records, through pinned staging
     if (!L->sims_done && (e = hipEventCreateWithFlags(&L->sims_done, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(lead, e, "hipEventCreate");
@@ -1586,10 +1603,11 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand)
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kNW), 0, st, A);
     timing_end(lead, &t);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(lead, e, "launch(systolic)");
-    // members see a timeout of the shared launch in their own error word, and
-    // their streams continue after the launch
+    // members see a timeout of the shared launch in their own error word (their
+    // own bits stay), and their streams continue after the launch
     for (int i = 1; i < n && e == hipSuccess; ++i) {
-        e = hipMemcpyAsync(cs[i]->dev_error, lead->dev_error, sizeof(int), hipMemcpyDeviceToDevice, st);
+        hipLaunchKernelGGL(or_timeout, dim3(1), dim3(64), 0, st, cs[i]->dev_error, (const int*)lead->dev_error);
+        e = hipGetLastError();
         if (e == hipSuccess && cs[i]->stream != st) {
             hipEvent_t ev;
             if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) == hipSuccess) {
@@ -1642,6 +1660,12 @@ int systolic_step(fdtd_ctx* ctx, int64_t nsteps)
 }
 
 int systolic_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps) { return launch(ctxs, n, nsteps); }
+
+int systolic_prepare(fdtd_ctx* ctx, int64_t nsteps)
+{
+    fdtd_ctx* one[1] = {ctx};
+    return launch(one, 1, nsteps, kMaxBand, false);
+}
 
 void systolic_tile(const fdtd_ctx* ctx, int* wx, int* wy, int* wz)
 {

@@ -38,11 +38,33 @@ PLAIN_BYTES_PER_UPDATE = PLAIN_E_BYTES + PLAIN_H_BYTES
 PLAIN_FUSED_BYTES_PER_UPDATE = 60
 
 
+def systolic_alg_bytes_per_update(tile, band, conductive=False, fp16=False):
+    """Algorithmic HBM bytes per cell update of the systolic scheme: what the
+    method itself must move (Section 4's accounting).  Every step a tile of
+    V = Wx*Wy*Wz updated cells takes in its three leading faces (A = WyWz +
+    WxWz + WxWy cells: E and H, and the structural coefficients) and puts out
+    its three trailing faces (E and H); once per band of K steps the whole
+    state goes out (E, H) and comes back in (E, H and the coefficients):
+
+        B = (in + out) * A / V + (out + in) / K,
+        in = 6 es + coefficient bytes, out = 6 es,
+
+    es being the stored field element (4 B, or 2 B with FP16 storage) and the
+    coefficients cE (3 es) plus, with conductivity, ca (12 B).  FP32 at the
+    15x15x15 tile: 60 * 0.2 + 60 / K = 12 + 60 / K."""
+    wx, wy, wz = tile
+    es = 2 if fp16 else 4
+    coef = 3 * es + (12 if conductive else 0)
+    cin, cout = 6 * es + coef, 6 * es
+    a, v = wy * wz + wx * wz + wx * wy, wx * wy * wz
+    return (cin + cout) * a / v + (cout + cin) / band
+
+
 def systolic_bytes_per_update(tile, band, conductive=False, fp16=False):
-    """Algorithmic HBM bytes per cell update of the systolic scheme (Section 4
-    accounting: faces of the fields and of the structural coefficients in and
-    out every step, the whole state once per band of K steps), for this
-    design's exchange.  Every step a tile of V = Wx*Wy*Wz updated cells takes
+    """HBM bytes per cell update of this design's exchange (reported beside
+    the algorithmic count; it moves more than the method needs, since the
+    z face's coefficients are written to a ring as well as read, and with
+    FP16 storage the x and y faces' coefficients too).  Every step a tile of V = Wx*Wy*Wz updated cells takes
     in its three leading faces and puts out its three trailing faces:
 
     - x face (WyWz cells) and y face (WxWz): E and H (24 B per cell) through
@@ -124,6 +146,9 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None
         log("%s: warmup %d steps" % (scheme, warmup))
         if warmup:
             sim.step(warmup)
+        # build what a call of `steps` steps needs (the systolic plan and face
+        # rings, the fused step's second field set) outside the timed region
+        sim.prepare(steps)
         sim.synchronize()
         sim.set_option(fdtd.OPT_PROFILE, 1)
         torch.cuda.synchronize()
@@ -371,12 +396,12 @@ def adjoint_bench(checkpoint_every: int = 0):
             sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
         sim.synchronize()
         t0 = time.perf_counter()
-        J, g = sim.adjoint(**a)
+        # all three components share the cell's permittivity
+        J, gs = sim.adjoint(**a, isotropic=True)
         t = time.perf_counter() - t0
         recomputed = sim.adjoint_recomputed_steps
     finally:
         sim.close()
-    gs = g.sum(axis=0)   # all three components share the cell's permittivity
     passes = 2 * a["nsteps"] + recomputed
     out = {"metric": "adjoint gradient time, %dx%dx%d FP32, %d steps" % (w.shape + (a["nsteps"],)),
            "value": t, "unit": "s", "higher_is_better": False, "n_gpus": 1,
@@ -495,8 +520,13 @@ def main():
         avg_s = ms / 1e3 / max(n, 1)
         steps_per_launch = args.steps / max(n, 1)
         band = stats["info"]["band_steps"]
-        b_alg = systolic_bytes_per_update(stats["info"]["tile"], band, sigma is not None,
-                                          args.storage == "fp16")
+        b_alg = systolic_alg_bytes_per_update(stats["info"]["tile"], band, sigma is not None,
+                                              args.storage == "fp16")
+        b_design = systolic_bytes_per_update(stats["info"]["tile"], band, sigma is not None,
+                                             args.storage == "fp16")
+        if band >= steps_per_launch and band < 64 and not args.band:
+            log("systolic: the band (%d steps) is capped by the call length (--steps %d)"
+                % (band, args.steps))
         updates = cells * steps_per_launch
         achieved = b_alg * updates / avg_s / 1e9
         flops = FLOPS_PER_CELL * updates / avg_s / 1e12
@@ -511,6 +541,9 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "systolic_kernel", "launches": n, "avg_launch_ms": avg_s * 1e3,
                 "alg_bytes_per_update": b_alg,
+                "design_bytes_per_update": b_design,
+                "band_steps": band,
+                "band_capped_by_call": bool(band >= steps_per_launch and band < 64),
                 "traffic_bytes_per_update": None if traffic is None else traffic / updates,
                 "traffic_GBps": None if traffic is None else traffic / avg_s / 1e9,
                 "alu_achieved_TFLOPs": flops, "alu_peak_TFLOPs": VALU_FP32_PEAK_TFLOPS,
@@ -549,9 +582,11 @@ def main():
         entry = {"cups": c, "ms_per_step": ts / args.steps * 1e3}
         if scheme == "systolic":
             entry.update(st["info"])
-            b = systolic_bytes_per_update(st["info"]["tile"], st["info"]["band_steps"],
-                                          sigma is not None, args.storage == "fp16")
+            b = systolic_alg_bytes_per_update(st["info"]["tile"], st["info"]["band_steps"],
+                                              sigma is not None, args.storage == "fp16")
             entry["alg_bytes_per_update"] = b
+            entry["design_bytes_per_update"] = systolic_bytes_per_update(
+                st["info"]["tile"], st["info"]["band_steps"], sigma is not None, args.storage == "fp16")
             entry["alg_roofline_frac"] = c * b / (HBM_PEAK_GBS * 1e9)
             entry["effective_bw_frac_84B"] = c * PLAIN_BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9)
         if scheme == "plain":

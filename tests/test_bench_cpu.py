@@ -33,6 +33,26 @@ def test_systolic_bytes_per_update():
     assert bench.PLAIN_FUSED_BYTES_PER_UPDATE == 60
 
 
+def test_systolic_algorithmic_bytes_follow_the_face_and_band_formula():
+    """(in + out) A/V + (out + in)/K with in = E, H and the coefficients (36 B
+    in FP32), out = E and H (24 B): 12 + 60/K at the 15^3 tile."""
+    assert bench.systolic_alg_bytes_per_update((15, 15, 15), 20) == pytest.approx(12.0 + 3.0)
+    assert bench.systolic_alg_bytes_per_update((15, 15, 15), 64) == pytest.approx(12.0 + 60 / 64)
+    # the paper's 31x15x15 block: A = 225 + 465 + 465
+    assert bench.systolic_alg_bytes_per_update((31, 15, 15), 64) == pytest.approx(
+        60 * 1155 / 6975 + 60 / 64)
+    # conductive: ca travels with cE (in = 48 B)
+    assert bench.systolic_alg_bytes_per_update((11, 15, 15), 16, True) == pytest.approx(
+        72 * (225 + 165 + 165) / (11 * 15 * 15) + 72 / 16)
+    # FP16 storage halves every stored element
+    assert bench.systolic_alg_bytes_per_update((15, 15, 15), 48, fp16=True) == pytest.approx(
+        30 * 0.2 + 30 / 48)
+    # never more than the design's own exchange
+    for k in (8, 20, 64):
+        assert bench.systolic_alg_bytes_per_update((15, 15, 15), k) < \
+            bench.systolic_bytes_per_update((15, 15, 15), k)
+
+
 def test_counter_traffic_needs_matching_source_and_launch():
     launch = {"workload": "c3_pec_dielectric_1024x1024x512", "steps": 128, "band": 32,
               "cells": 1024 * 1024 * 512}

@@ -142,13 +142,15 @@ __global__ void adj_grad_kernel(const float* __restrict__ lEx, const float* __re
 
 // dJ/deps_c = -g_c cE_c^2 dx / dt over the design box (0 where cE is pinned);
 // with conductivity (ca non-null, cE then being B)
-// dJ/deps_c = (dx / dt) B ((1 - A) gA_c - B gB_c).
+// dJ/deps_c = (dx / dt) B ((1 - A) gA_c - B gB_c).  With iso the three
+// components' derivatives are added in double into one block (one
+// permittivity per cell driving all three components).
 template <bool LOSSY>
 __global__ void adj_eps_kernel(const double* __restrict__ g, const float* __restrict__ cEx,
                                const float* __restrict__ cEy, const float* __restrict__ cEz,
                                const float* __restrict__ cax, const float* __restrict__ cay,
                                const float* __restrict__ caz, Box b, int ny, int nz, double dx_dt,
-                               float* __restrict__ out)
+                               int iso, float* __restrict__ out)
 {
     const long long nb = b.cells();
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nb;
@@ -158,12 +160,16 @@ __global__ void adj_eps_kernel(const double* __restrict__ g, const float* __rest
         const long long p = ((long long)i * ny + j) * nz + k;
         const float* ce[3] = {cEx, cEy, cEz};
         const float* ca[3] = {cax, cay, caz};
+        double tot = 0.0;
         for (int c = 0; c < 3; ++c) {
             const double v = (double)ce[c][p];
             double d = -g[c * nb + q] * v * v * dx_dt;
             if (LOSSY) d += (1.0 - (double)ca[c][p]) * v * dx_dt * g[(3 + c) * nb + q];
-            out[c * nb + q] = v == 0.0 ? 0.0f : (float)d;
+            if (v == 0.0) d = 0.0;
+            tot += d;
+            if (!iso) out[c * nb + q] = (float)d;
         }
+        if (iso) out[q] = (float)tot;
     }
 }
 
@@ -293,6 +299,8 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
         return fail(ctx, FDTD_EUNSUPPORTED, "adjoint: needs FP32 storage");
     if (spec->mon_comp < FDTD_EX || spec->mon_comp > FDTD_EZ)
         return fail(ctx, FDTD_EINVAL, "adjoint: the monitored component must be Ex, Ey or Ez");
+    if (spec->isotropic != 0 && spec->isotropic != 1)
+        return fail(ctx, FDTD_EINVAL, "adjoint: isotropic must be 0 or 1");
     if (spec->nsteps < 1 || spec->nsteps > (int64_t(1) << 31) || spec->checkpoint_every < 0)
         return fail(ctx, FDTD_EINVAL, "adjoint: nsteps must be in [1, 2^31], checkpoint_every >= 0");
     const int n3[3] = {ctx->nx, ctx->ny, ctx->nz};
@@ -455,10 +463,11 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
     hipLaunchKernelGGL((lossy ? adj_eps_kernel<true> : adj_eps_kernel<false>), dim3(box_grid(ndes)),
                        dim3(256), 0, st, (const double*)w.g, ctx->coef[0], ctx->coef[1], ctx->coef[2],
                        ctx->ca[0], ctx->ca[1], ctx->ca[2], des, ctx->ny, ctx->nz,
-                       ctx->cfg.dx / ctx->cfg.dt, dst);
+                       ctx->cfg.dx / ctx->cfg.dt, (int)spec->isotropic, dst);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(ctx, e, "launch(adjoint gradient)");
+    const size_t nblocks = spec->isotropic ? 1 : 3;
     if (where == FDTD_HOST &&
-        (e = hipMemcpyAsync(grad_eps, w.out, 3 * (size_t)ndes * sizeof(float), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        (e = hipMemcpyAsync(grad_eps, w.out, nblocks * (size_t)ndes * sizeof(float), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hip_fail(ctx, e, "adjoint: copy gradient");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "adjoint: synchronize");
     spec->objective = J;

@@ -127,7 +127,7 @@ def test_adjoint_device_output_equals_host_output():
 
 @pytest.mark.parametrize("bad", [
     dict(mon_comp=3), dict(mon_lo=(0, 0, 0), mon_hi=(0, 5, 5)), dict(des_hi=(13, 5, 5)),
-    dict(nsteps=0), dict(checkpoint_every=-2),
+    dict(nsteps=0), dict(checkpoint_every=-2), dict(isotropic=2),
 ])
 def test_adjoint_rejects_bad_spec(bad):
     w = wl.small_case((12, 10, 9), (PEC, PEC, PEC), seed=9, nsteps=5)
@@ -141,6 +141,36 @@ def test_adjoint_rejects_bad_spec(bad):
     assert sim.current_step == 0
     assert_bitwise(sim.read_fields(), w.fields, "unchanged state")
     sim.close()
+
+
+@pytest.mark.parametrize("lossy", [False, True])
+def test_isotropic_gradient_is_the_component_sum(lossy):
+    """spec.isotropic = 1 returns one block: the three components' derivatives
+    added in FP64 by the library (the design variable of a cell whose single
+    permittivity drives all three components), equal to the oracle's sum."""
+    w = wl.small_case((14, 12, 10), (PEC, PER, PEC), seed=31, nsteps=40, dipoles=[(3, 4, 5)])
+    sigma = wl.graded_shell(w.shape, 3, 0.3) if lossy else None
+    args = dict(nsteps=40, mon_comp=2, mon_lo=(11, 1, 1), mon_hi=(12, 11, 9), omega=0.4,
+                des_lo=(4, 3, 3), des_hi=(9, 8, 7), checkpoint_every=15)
+    res = {}
+    for iso in (False, True):
+        sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc)
+        sim.set_materials(w.eps, sigma=sigma)
+        sim.set_fields(w.fields)
+        for s in w.sources:
+            sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+        res[iso] = sim.adjoint(**args, isotropic=iso)
+        sim.close()
+    (J3, g3), (J1, g1) = res[False], res[True]
+    assert J1 == J3
+    assert g1.shape == g3.shape[1:]
+    s3 = g3.astype(np.float64).sum(axis=0)
+    assert np.abs(g1 - s3).max() <= 4e-7 * np.abs(s3).max()
+    eps3 = [np.array(w.eps) for _ in range(3)]
+    _, g_ref = adj.gradient(w.fields, eps3, w.bc, w.dt, w.dx, 40, args["mon_lo"], args["mon_hi"], 2,
+                            0.4, args["des_lo"], args["des_hi"], sources=w.sources,
+                            sigma=None if sigma is None else [sigma] * 3)
+    assert _rel(g1, np.sum(np.stack(g_ref), axis=0)) < 1e-4
 
 
 def test_design_objective_autograd():

@@ -53,6 +53,7 @@
 #include <vector>
 
 #include "fdtd_internal.h"
+#include "plan.h"
 
 namespace fdtd {
 
@@ -1064,18 +1065,10 @@ constexpr int kNW = 4;  // wavefronts per tile: tile = 15 x 15 x 15 updated cell
 
 }  // namespace
 
-// Host-side plan of one context's call (tickets, per-band tile ranges, the
-// tile->ticket table) and the launch resources of the launches it leads.
+// Host-side plan of one context's call (plan::Plan) and the launch resources
+// of the launches it leads.
 struct SystolicState {
-    int nsteps = -1, K = -1, wx = -1;  // the plan's step count, band and tile width along x
-    int nt = 0, D = 1, nbands = 0;
-    int per[3] = {0, 0, 0};  // periodic axes of the plan
-    int L[3] = {0, 0, 0};    // ring tiles on periodic axes
-    int group = 1;           // tiles of one ring group (must be co-resident)
-    std::vector<int4> tickets;  // (band, a, b, c) in dequeue order
-    std::vector<int> tix;       // per band, tile -> ticket
-    std::vector<int> band;      // per band: alo ahi blo bhi clo chi tix_off pad
-    std::vector<int> depth;     // per ticket: depth below the upwind corner (PEC axes)
+    plan::Plan pl;
     uint64_t version = 0;       // bumped whenever the plan is rebuilt
     // launch resources (used when this context leads a launch)
     int4* d_tickets = nullptr;
@@ -1100,6 +1093,8 @@ struct SystolicState {
 };
 
 namespace {
+
+static_assert(sizeof(plan::Ticket) == sizeof(int4), "tickets upload as int4");
 
 void free_launch(SystolicState* s)
 {
@@ -1126,101 +1121,33 @@ void free_launch(SystolicState* s)
     s->up_ver.clear();
 }
 
-int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-
 // updated cells along x of a tile of this context: conductive grids use the
 // narrower register tile that leaves room for the per-cell decay
 int tile_x(const fdtd_ctx* c) { return c->ca[0] ? WX_LOSSY : WX; }
 
+void tile_of(const fdtd_ctx* c, int W[3])
+{
+    W[0] = tile_x(c);
+    W[1] = 4 * kNW - 1;
+    W[2] = WZ;
+}
+
+void axes_of(const fdtd_ctx* c, int N[3], int per[3])
+{
+    N[0] = c->nx;
+    N[1] = c->ny;
+    N[2] = c->nz;
+    for (int d = 0; d < 3; ++d) per[d] = c->cfg.bc[d] == FDTD_BC_PERIODIC;
+}
+
 // The plan of one context: tiles per band, tickets in topological order.
 int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 {
-    constexpr int WY = 4 * kNW - 1;
-    const int W[3] = {tile_x(ctx), WY, WZ};
-    const int N[3] = {ctx->nx, ctx->ny, ctx->nz};
-    int per[3], L[3], group = 1;
-    for (int d = 0; d < 3; ++d) {
-        per[d] = ctx->cfg.bc[d] == FDTD_BC_PERIODIC;
-        L[d] = per[d] ? (N[d] + W[d] - 1) / W[d] : 0;
-        if (per[d]) group *= L[d];
-    }
-    // wrap a tile coordinate onto the ring of a periodic axis
-    auto wrap = [&](int d, int v) { return per[d] ? ((v % L[d]) + L[d]) % L[d] : v; };
-    const int nb = (nsteps + K - 1) / K;
-    std::vector<int> band(8 * (size_t)nb);
-    size_t ntot = 0;
-    for (int bb = 0; bb < nb; ++bb) {
-        const int t0 = bb * K, t1 = std::min(nsteps, t0 + K);
-        size_t cnt = 1;
-        for (int d = 0; d < 3; ++d) {
-            // tiles whose subdomain meets the grid at some step of the band
-            // (a periodic axis always holds its whole ring)
-            const int lo = per[d] ? 0 : -floordiv(W[d] - 1 + t1, W[d]);
-            const int hi = per[d] ? L[d] - 1 : floordiv(N[d] - 2 - t0, W[d]);
-            band[8 * bb + 2 * d] = lo;
-            band[8 * bb + 2 * d + 1] = hi;
-            cnt *= (size_t)(hi - lo + 1);
-        }
-        band[8 * bb + 6] = (int)ntot;
-        ntot += cnt;
-        if (ntot > (size_t)1 << 30) return fail(ctx, FDTD_EUNSUPPORTED, "systolic: too many tickets");
-    }
-    std::vector<int4> tickets(ntot);
-    std::vector<int> tix(ntot), depth(ntot);
-    size_t pos = 0;
-    for (int bb = 0; bb < nb; ++bb) {
-        const int* bi = &band[8 * bb];
-        const int n3[3] = {bi[1] - bi[0] + 1, bi[3] - bi[2] + 1, bi[5] - bi[4] + 1};
-        // depth below the most upwind corner, along the PEC axes only
-        int maxd = 0;
-        for (int d = 0; d < 3; ++d)
-            if (!per[d]) maxd += n3[d] - 1;
-        // loop order: PEC axes outside, periodic axes inside, so that the
-        // tiles of one ring group are enumerated (and so stored) together
-        int ax[3], k = 0;
-        for (int d = 0; d < 3; ++d)
-            if (!per[d]) ax[k++] = d;
-        for (int d = 0; d < 3; ++d)
-            if (per[d]) ax[k++] = d;
-        auto depth_of = [&](const int* i3) {
-            int dd = 0;
-            for (int d = 0; d < 3; ++d)
-                if (!per[d]) dd += n3[d] - 1 - i3[d];
-            return dd;
-        };
-        // counting sort by depth (upwind first), stable in the loop order
-        std::vector<int> count(maxd + 2, 0);
-        int i3[3];
-        for (i3[ax[0]] = 0; i3[ax[0]] < n3[ax[0]]; ++i3[ax[0]])
-            for (i3[ax[1]] = 0; i3[ax[1]] < n3[ax[1]]; ++i3[ax[1]])
-                for (i3[ax[2]] = 0; i3[ax[2]] < n3[ax[2]]; ++i3[ax[2]]) count[depth_of(i3) + 1]++;
-        for (int d = 1; d <= maxd + 1; ++d) count[d] += count[d - 1];
-        for (i3[ax[0]] = 0; i3[ax[0]] < n3[ax[0]]; ++i3[ax[0]])
-            for (i3[ax[1]] = 0; i3[ax[1]] < n3[ax[1]]; ++i3[ax[1]])
-                for (i3[ax[2]] = 0; i3[ax[2]] < n3[ax[2]]; ++i3[ax[2]]) {
-                    const int dd = depth_of(i3);
-                    const size_t tix_i = pos + (size_t)count[dd]++;
-                    tickets[tix_i] = make_int4(bb, bi[0] + i3[0], bi[2] + i3[1], bi[4] + i3[2]);
-                    depth[tix_i] = dd;
-                    tix[(size_t)bi[6] + ((size_t)i3[0] * n3[1] + i3[1]) * n3[2] + i3[2]] = (int)tix_i;
-                }
-        pos += (size_t)n3[0] * n3[1] * n3[2];
-    }
-    (void)wrap;
-    s->nsteps = nsteps;
-    s->K = K;
-    s->wx = W[0];
-    s->nt = (int)ntot;
-    s->nbands = nb;
-    for (int d = 0; d < 3; ++d) {
-        s->per[d] = per[d];
-        s->L[d] = L[d];
-    }
-    s->group = group;
-    s->tickets.swap(tickets);
-    s->tix.swap(tix);
-    s->band.swap(band);
-    s->depth.swap(depth);
+    int N[3], per[3], W[3];
+    axes_of(ctx, N, per);
+    tile_of(ctx, W);
+    std::string err;
+    if (!plan::build(N, per, W, nsteps, K, &s->pl, &err)) return fail(ctx, FDTD_EUNSUPPORTED, err);
     // unique across contexts, so a launch plan is never mistaken for the plan
     // of another context that happens to reuse an address
     static std::atomic<uint64_t> g_version{0};
@@ -1229,24 +1156,12 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
 }
 
 // Band length (steps per residency) for a launch over the contexts cs.  An
-// explicit option wins; otherwise a cost model picks it.  Per cell update, a
-// band of K steps costs the tile-steps that cover the band's skewed
-// space-time region, prod_d (n_d + s + 30) / n_d on PEC axes (15 L_d / n_d
-// on periodic rings), times (1 + beta / K) for the band's start and end (box
-// load, state write-back, the pipeline refill behind the band barrier of each
-// tile).  The region is n_d + K + 30 wide, but tiles leaving through an
-// upper wall stop once wholly outside: s = K / 2.  Tiles entering through a
-// lower wall skip their updates until their first cell enters (on grids with
-// no periodic axis), but they still hold a workgroup and keep pace with
-// their upwind neighbours, so they stay in the count: with s = 0 the model
-// took 64-step bands everywhere, and 64 grids of 16..64 cells per axis ran
-// at 21 instead of 36 G cell updates/s.  beta = 10 steps.  Over several
-// grids the cell-weighted mean is minimised (a batched launch asks per
+// explicit option wins; otherwise the cost model plan::band_cost picks it
+// (over several grids, the cell-weighted mean; a batched launch asks per
 // grid).
 int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
 {
     if (cs[0]->band_steps > 0) return (int)std::min<int64_t>(std::min(cs[0]->band_steps, kMaxBand), nsteps);
-    constexpr double kBeta = 10.0;
     static const int cand[] = {8, 12, 16, 24, 32, 48, 64};
     int best = (int)std::min<int64_t>(nsteps, 32);
     double best_cost = 1e300;
@@ -1254,19 +1169,11 @@ int default_band(fdtd_ctx* const* cs, int n, int64_t nsteps)
         const int K = (int)std::min<int64_t>(K0, nsteps);
         double cost = 0.0, cells = 0.0;
         for (int i = 0; i < n; ++i) {
-            const fdtd_ctx* c = cs[i];
-            const int nd[3] = {c->nx, c->ny, c->nz};
-            const int W[3] = {tile_x(c), 4 * kNW - 1, WZ};
-            double f = 1.0 + kBeta / K;
-            const double skew = 0.5 * K;
-            for (int d = 0; d < 3; ++d) {
-                const double slots = c->cfg.bc[d] == FDTD_BC_PERIODIC
-                                         ? (double)W[d] * ((nd[d] + W[d] - 1) / W[d])
-                                         : (double)nd[d] + skew + 30.0;
-                f *= slots / nd[d];
-            }
-            cost += f * (double)c->ncell;
-            cells += (double)c->ncell;
+            int N[3], per[3], W[3];
+            axes_of(cs[i], N, per);
+            tile_of(cs[i], W);
+            cost += plan::band_cost(N, per, W, K) * (double)cs[i]->ncell;
+            cells += (double)cs[i]->ncell;
         }
         cost /= cells;
         if (cost < best_cost * (1.0 - 1e-9)) {
@@ -1306,89 +1213,37 @@ int ensure_buffer(fdtd_ctx* ctx, T** p, size_t* cap, size_t n, const char* what)
 int upload_plan(fdtd_ctx* lead, SystolicState* L, fdtd_ctx* const* cs, int n)
 {
     bool same = (int)L->up_ctx.size() == n && L->d_tickets;
-    for (int i = 0; same && i < n; ++i) same = L->up_ctx[i] == cs[i] && L->up_ver[i] == cs[i]->sys->version;
+    for (int i = 0; i < n && same; ++i) same = L->up_ctx[i] == cs[i] && L->up_ver[i] == cs[i]->sys->version;
     if (same) return FDTD_OK;
     L->up_ctx.clear();
     L->up_ver.clear();
-    std::vector<size_t> base(n + 1, 0), tix_base(n + 1, 0), band_base(n + 1, 0);
-    for (int i = 0; i < n; ++i) {
-        base[i + 1] = base[i] + cs[i]->sys->tickets.size();
-        tix_base[i + 1] = tix_base[i] + cs[i]->sys->tix.size();
-        band_base[i + 1] = band_base[i] + cs[i]->sys->band.size();
-    }
-    const size_t nt = base[n];
-    if (nt > (size_t)1 << 30 || tix_base[n] > (size_t)1 << 30)
-        return fail(lead, FDTD_EUNSUPPORTED, "systolic: too many tickets");
-    std::vector<int> sim(nt), order(nt);
-    for (int i = 0; i < n; ++i)
-        for (size_t q = base[i]; q < base[i + 1]; ++q) sim[q] = i;
-    for (size_t q = 0; q < nt; ++q) order[q] = (int)q;
-    if (n > 1)
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-            const SystolicState* sx = cs[sim[x]]->sys;
-            const SystolicState* sy = cs[sim[y]]->sys;
-            const size_t lx = x - base[sim[x]], ly = y - base[sim[y]];
-            // band start step (simulations may have different band lengths)
-            const long long bx = (long long)sx->tickets[lx].x * sx->K, by = (long long)sy->tickets[ly].x * sy->K;
-            if (bx != by) return bx < by;
-            return sim[x] < sim[y];
-        });
-    std::vector<int> pos(nt);  // concatenated index -> merged position
-    for (size_t q = 0; q < nt; ++q) pos[order[q]] = (int)q;
-    std::vector<int4> tk(nt);
-    std::vector<int> tsim(nt), tix(tix_base[n]), band(band_base[n]);
-    for (int i = 0; i < n; ++i) {
-        const SystolicState* si = cs[i]->sys;
-        for (size_t q = 0; q < si->tickets.size(); ++q) {
-            tk[pos[base[i] + q]] = si->tickets[q];
-            tsim[pos[base[i] + q]] = i;
-        }
-        for (size_t q = 0; q < si->tix.size(); ++q) tix[tix_base[i] + q] = pos[base[i] + si->tix[q]];
-        for (size_t q = 0; q < si->band.size(); ++q)
-            band[band_base[i] + q] = si->band[q] + (q % 8 == 6 ? (int)tix_base[i] : 0);
-    }
-    // largest distance (in tickets) from a face producer to one of its
-    // consumers (the downwind neighbours), and the largest ring group
-    int D = 1, group = 1;
-    for (int i = 0; i < n; ++i) group = std::max(group, cs[i]->sys->group);
-    for (size_t t = 0; t < nt; ++t) {
-        const SystolicState* si = cs[tsim[t]]->sys;
-        const int4 q = tk[t];
-        const int* bi = &band[band_base[tsim[t]] + 8 * (size_t)q.x];
-        const int nbb = bi[3] - bi[2] + 1, nc = bi[5] - bi[4] + 1;
-        for (int d = 1; d < 8; ++d) {
-            int v[3] = {q.y - (d & 1), q.z - ((d >> 1) & 1), q.w - ((d >> 2) & 1)};
-            bool in = true;
-            for (int k = 0; k < 3; ++k) {
-                if (si->per[k]) v[k] = ((v[k] % si->L[k]) + si->L[k]) % si->L[k];
-                in = in && v[k] >= bi[2 * k] && v[k] <= bi[2 * k + 1];
-            }
-            if (!in) continue;
-            const int j = tix[(size_t)bi[6] + ((size_t)(v[0] - bi[0]) * nbb + (v[1] - bi[2])) * nc + (v[2] - bi[4])];
-            D = std::max(D, j - (int)t + 1);
-        }
-    }
+    std::vector<const plan::Plan*> plans(n);
+    for (int i = 0; i < n; ++i) plans[i] = &cs[i]->sys->pl;
+    plan::Merged m;
+    std::string err;
+    if (!plan::merge(plans.data(), n, &m, &err)) return fail(lead, FDTD_EUNSUPPORTED, err);
+    const size_t nt = m.tickets.size();
     int rc;
     if ((rc = ensure_buffer(lead, &L->d_tickets, &L->cap_tickets, nt, "tickets")) ||
         (rc = ensure_buffer(lead, &L->d_tsim, &L->cap_tsim, nt, "ticket simulations")) ||
-        (rc = ensure_buffer(lead, &L->d_tix, &L->cap_tix, tix.size(), "tile table")) ||
-        (rc = ensure_buffer(lead, &L->d_band, &L->cap_band, band.size(), "band table")) ||
+        (rc = ensure_buffer(lead, &L->d_tix, &L->cap_tix, m.tix.size(), "tile table")) ||
+        (rc = ensure_buffer(lead, &L->d_band, &L->cap_band, m.band.size(), "band table")) ||
         (rc = ensure_buffer(lead, &L->d_progress, &L->cap_prog, nt, "progress counters")))
         return rc;
     hipError_t e;
-    if ((e = hipMemcpy(L->d_tickets, tk.data(), nt * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(L->d_tsim, tsim.data(), nt * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(L->d_tix, tix.data(), tix.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(L->d_band, band.data(), band.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(L->d_tickets, m.tickets.data(), nt * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(L->d_tsim, m.tsim.data(), nt * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(L->d_tix, m.tix.data(), m.tix.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(L->d_band, m.band.data(), m.band.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(lead, e, "systolic plan upload");
     for (int i = 0; i < n; ++i) {
         L->up_ctx.push_back(cs[i]);
         L->up_ver.push_back(cs[i]->sys->version);
     }
     L->up_nt = (int)nt;
-    L->up_D = D;
-    L->up_group = group;
-    L->up_band_off.assign(band_base.begin(), band_base.end() - 1);
+    L->up_D = m.D;
+    L->up_group = m.group;
+    L->up_band_off = m.band_off;
     return FDTD_OK;
 }
 
@@ -1424,7 +1279,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
         const int K = lead->band_steps > 0 ? default_band(cs, 1, nsteps)
                                            : std::min(kcap, default_band(cs + i, 1, nsteps));
         Kmax = std::max(Kmax, K);
-        if (si->nsteps != (int)nsteps || si->K != K || si->wx != tile_x(cs[i])) {
+        if (si->pl.nsteps != (int)nsteps || si->pl.K != K || si->pl.wx != tile_x(cs[i])) {
             int rc = build_plan(cs[i], si, (int)nsteps, K);
             if (rc) return rc == FDTD_OK ? rc : fail(lead, rc, cs[i]->err);
         }
@@ -1433,7 +1288,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     int rc = upload_plan(lead, L, cs, n);
     if (rc) return rc;
     bool anyper = false;
-    for (int i = 0; i < n; ++i) anyper = anyper || cs[i]->sys->per[0] || cs[i]->sys->per[1] || cs[i]->sys->per[2];
+    for (int i = 0; i < n; ++i) anyper = anyper || cs[i]->sys->pl.per[0] || cs[i]->sys->pl.per[1] || cs[i]->sys->pl.per[2];
 
     // synchronisation variant: device-scope accesses (default) or cached
     // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
@@ -1552,11 +1407,11 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
         for (int d = 0; d < 3; ++d) {
             const int nd = d == 0 ? c->nx : (d == 1 ? c->ny : c->nz);
             const int W = d == 0 ? tile_x(c) : (d == 1 ? 4 * kNW - 1 : WZ);
-            P.per[d] = c->sys->per[d];
-            P.L[d] = c->sys->L[d];
-            P.wr[d] = c->sys->per[d] ? nd - W * (c->sys->L[d] - 1) : W;
+            P.per[d] = c->sys->pl.per[d];
+            P.L[d] = c->sys->pl.L[d];
+            P.wr[d] = c->sys->pl.per[d] ? nd - W * (c->sys->pl.L[d] - 1) : W;
         }
-        P.K = c->sys->K;
+        P.K = c->sys->pl.K;
     }
     hipStream_t st = lead->stream;
     // order the launch after each member's earlier work
@@ -1622,7 +1477,7 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
         cs[i]->step_count += nsteps;
         cs[i]->sys_grid = grid;
         cs[i]->sys_ring_slots = R;
-        cs[i]->sys_band = cs[i]->sys->K;
+        cs[i]->sys_band = cs[i]->sys->pl.K;
         cs[i]->sys_tickets = nt;
     }
     return FDTD_OK;

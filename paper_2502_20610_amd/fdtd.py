@@ -326,7 +326,7 @@ class Simulation:
         spec.checkpoint_every = int(checkpoint_every)
         spec.omega = float(omega)
         spec.nsteps = int(nsteps)
-        spec.isotropic = 1 if isotropic else 0
+        spec.isotropic = int(isotropic)    # the library refuses anything but 0 and 1
         shape = (() if isotropic else (3,)) + tuple(int(des_hi[a]) - int(des_lo[a]) for a in range(3))
         if out is not None:
             if not _is_torch(out) or not out.is_cuda or tuple(out.shape) != shape or \

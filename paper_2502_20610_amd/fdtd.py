@@ -79,6 +79,14 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libfdtd.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch carries a HIP runtime of its own beside the one the library links;
+    # bringing torch's up first lets both share the device (brought up after
+    # the library's, torch finds no GPU), so device tensors can be passed in
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     fp = ctypes.POINTER(ctypes.c_float)

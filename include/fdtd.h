@@ -276,6 +276,24 @@ enum {
  * Errors: FDTD_EINVAL for a NULL sums pointer or a bad `where`. */
 int fdtd_invariants(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h, int where);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * reduction as fdtd_invariants with every output on the device: sums
+ * (FDTD_INV_COUNT doubles, required), div_e and div_h (nx*ny*nz doubles each,
+ * or NULL), all device pointers on the context's device, written in order on
+ * the context's stream (nothing is synchronised or copied to the host).  The
+ * call allocates nothing: the partial sums live in a static device array of
+ * the library (1024 records of 8 doubles plus 8, 64 KiB in total, held on
+ * every GPU the library runs on until the process ends; its address is looked
+ * up once per device when a context is created).  Its size does not depend on
+ * the grid, so every grid fits; a device ordinal >= 64 is refused
+ * (FDTD_EUNSUPPORTED).  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (on different streams, or from different threads) race
+ * and may return wrong sums; calls in order on one stream are safe.  Results
+ * are bit-identical to fdtd_invariants on the same state.
+ * Errors: FDTD_EINVAL for a NULL sums pointer. */
+int fdtd_invariants_noalloc(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h);
+
 /* ---- gradient with respect to permittivity (reverse-time adjoint) -------
  *
  * The paper motivates fast FDTD by inverse design (Section 1), where a

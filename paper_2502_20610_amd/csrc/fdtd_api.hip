@@ -349,6 +349,10 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
 
     hipError_t e = hipSetDevice(cfg->device);
     if (e != hipSuccess) return fail(nullptr, FDTD_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    // the device address of the allocation-free entry point's scratch, once
+    // per device (this device is current)
+    if (invariants_scratch_init(cfg->device) != FDTD_OK)
+        return fail(nullptr, FDTD_EHIP, "fdtd_create: hipGetSymbolAddress of the invariants scratch failed");
 
     fdtd_ctx* ctx = new (std::nothrow) fdtd_ctx();
     if (!ctx) return fail(nullptr, FDTD_ENOMEM, "fdtd_create: host allocation failed");
@@ -849,8 +853,8 @@ int fdtd_invariants(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h, i
     }
     double* de = where == FDTD_DEVICE ? div_e : stage[0];
     double* dh = where == FDTD_DEVICE ? div_h : stage[1];
-    rc = invariants_launch(ctx, ctx->inv_scratch, de, dh);
-    const double* dsum = ctx->inv_scratch + invariants_sums_offset();
+    double* dsum = ctx->inv_scratch + invariants_sums_offset();
+    rc = invariants_launch(ctx, ctx->inv_scratch, dsum, de, dh);
     e = hipSuccess;
     if (!rc) {
         e = hipMemcpyAsync(sums, dsum, FDTD_INV_COUNT * sizeof(double), kind_from(where, false), ctx->stream);
@@ -864,6 +868,22 @@ int fdtd_invariants(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h, i
     if (e != hipSuccess) return hip_fail(ctx, e, "invariants");
     if (where == FDTD_HOST) return check_device_error(ctx);
     return FDTD_OK;
+}
+
+int fdtd_invariants_noalloc(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    if (!sums) return fail(ctx, FDTD_EINVAL, "invariants_noalloc: sums is NULL");
+    if (invariants_scratch_doubles() > kInvScratchDoubles)
+        return fail(ctx, FDTD_EUNSUPPORTED, "invariants_noalloc: the reduction needs more scratch than the "
+                                            "static array holds");
+    double* part = invariants_scratch_ptr(ctx->device);
+    if (!part)
+        return fail(ctx, FDTD_EUNSUPPORTED, "invariants_noalloc: no static scratch on this device "
+                                            "(device ordinal >= 64)");
+    (void)hipSetDevice(ctx->device);
+    return invariants_launch(ctx, part, sums, div_e, div_h);
 }
 
 int fdtd_adjoint(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where)

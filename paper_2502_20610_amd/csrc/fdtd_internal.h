@@ -126,10 +126,20 @@ int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int whe
 // whose partial records, and then the FDTD_INV_COUNT final sums, live in a
 // scratch area of invariants_scratch_doubles() doubles.
 constexpr int kInvBlocks = 1024;
+constexpr size_t kInvScratchDoubles = (size_t)kInvBlocks * 8 + 8;
 size_t invariants_scratch_doubles();
 // the final sums start at scratch + invariants_sums_offset()
 size_t invariants_sums_offset();
-int invariants_launch(fdtd_ctx* ctx, double* scratch, double* div_e, double* div_h);
+// partial records at `part`, the final sums at `out` (both device memory)
+int invariants_launch(fdtd_ctx* ctx, double* part, double* out, double* div_e, double* div_h);
+// The allocation-free variant's scratch (a static device array of
+// kInvScratchDoubles doubles in invariants.hip): look up its address on
+// `device` (the current device) once, at context creation; then
+// invariants_scratch_ptr(device) returns it (null if never looked up or
+// device >= kMaxScratchDevices).
+constexpr int kMaxScratchDevices = 64;
+int invariants_scratch_init(int device);
+double* invariants_scratch_ptr(int device);
 
 // Launch the source-injection kernel for the step that starts at step count s.
 int launch_sources(fdtd_ctx* ctx, int64_t s);

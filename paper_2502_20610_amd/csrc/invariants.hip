@@ -23,6 +23,8 @@
 // in a fixed order.
 #include <string.h>
 
+#include <mutex>
+
 #include "fdtd_internal.h"
 
 namespace fdtd {
@@ -31,6 +33,7 @@ namespace {
 
 constexpr int kRedThreads = 256;
 constexpr int kPart = 8;  // doubles per partial record (FDTD_INV_COUNT used)
+static_assert(kInvScratchDoubles == (size_t)kInvBlocks * kPart + kPart, "scratch: partials + sums");
 
 struct InvArgs {
     const float* f[6];
@@ -161,15 +164,15 @@ __global__ __launch_bounds__(kRedThreads) void invariants_finish(const double* p
 
 }  // namespace
 
-size_t invariants_scratch_doubles() { return (size_t)kInvBlocks * kPart + kPart; }
+size_t invariants_scratch_doubles() { return kInvScratchDoubles; }
 
 size_t invariants_sums_offset() { return (size_t)kInvBlocks * kPart; }
 
-// Launch the reduction on ctx's stream: partial records and the final sums
-// in `scratch` (invariants_scratch_doubles() doubles, device memory); the
-// seven sums land at scratch + kInvBlocks * kPart.  div_e / div_h: device
-// arrays of ncell doubles, or null.
-int invariants_launch(fdtd_ctx* ctx, double* scratch, double* div_e, double* div_h)
+// Launch the reduction on ctx's stream: the partial records in `part`
+// (kInvBlocks * kPart doubles, device memory), the FDTD_INV_COUNT final sums
+// at `out` (device memory).  div_e / div_h: device arrays of ncell doubles,
+// or null.
+int invariants_launch(fdtd_ctx* ctx, double* part, double* out, double* div_e, double* div_h)
 {
     InvArgs A;
     memset(&A, 0, sizeof(A));
@@ -190,18 +193,58 @@ int invariants_launch(fdtd_ctx* ctx, double* scratch, double* div_e, double* div
     A.nz = ctx->nz;
     for (int d = 0; d < 3; ++d) A.pec[d] = ctx->cfg.bc[d] == FDTD_BC_PEC;
     A.cH = (double)ctx->cH;
-    A.part = scratch;
+    A.part = part;
     A.div_e = div_e;
     A.div_h = div_h;
     using Kern = void (*)(InvArgs);
     const Kern k = h16 ? (lossy ? invariants_kernel<true, true> : invariants_kernel<true, false>)
                        : (lossy ? invariants_kernel<false, true> : invariants_kernel<false, false>);
     hipLaunchKernelGGL(k, dim3(kInvBlocks), dim3(kRedThreads), 0, ctx->stream, A);
-    hipLaunchKernelGGL(invariants_finish, dim3(1), dim3(kRedThreads), 0, ctx->stream, (const double*)scratch,
-                       kInvBlocks, (double)ctx->cH, scratch + (size_t)kInvBlocks * kPart);
+    hipLaunchKernelGGL(invariants_finish, dim3(1), dim3(kRedThreads), 0, ctx->stream, (const double*)part,
+                       kInvBlocks, (double)ctx->cH, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "launch(invariants)");
     return FDTD_OK;
+}
+
+}  // namespace fdtd
+
+// Scratch of the allocation-free entry point (fdtd_invariants_noalloc): the
+// reduction's partial records followed by its final sums, 64 KiB.  Every GPU
+// the library runs on holds its own copy until the process ends; host code
+// never uses this name as an address (on the host it is a stand-in), only
+// the per-device address looked up below.
+static __device__ __align__(256) double scratch[fdtd::kInvScratchDoubles];
+
+namespace fdtd {
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices];  // device address of `scratch`, per device
+
+}  // namespace
+
+int invariants_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return FDTD_OK;  // the entry point refuses
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return FDTD_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return FDTD_EHIP;
+    }
+    g_scratch_ptr[device] = static_cast<double*>(p);
+    return FDTD_OK;
+}
+
+double* invariants_scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace fdtd

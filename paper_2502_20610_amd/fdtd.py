@@ -42,6 +42,7 @@ EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_lossy_
            "fdtd_add_source", "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_synchronize",
            "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
            "fdtd_kernel_stats", "fdtd_get_info", "fdtd_set_field_scale", "fdtd_invariants",
+           "fdtd_invariants_noalloc",
            "fdtd_prepare")
 
 
@@ -111,6 +112,7 @@ def load_library():
         "fdtd_get_info": ([vp, ctypes.c_int, ctypes.POINTER(i64)], ctypes.c_int),
         "fdtd_set_field_scale": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "fdtd_invariants": ([vp, vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "fdtd_invariants_noalloc": ([vp, vp, vp, vp], ctypes.c_int),
         "fdtd_prepare": ([vp, i64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -313,6 +315,15 @@ class Simulation:
         if per_cell:
             return out, de, dh
         return out
+
+    def invariants_noalloc(self, sums, div_e=None, div_h=None):
+        """fdtd_invariants_noalloc: the invariants into torch float64 CUDA
+        tensors (sums of INVARIANT_NAMES length; div_e, div_h of the grid's
+        cell count, or None), stream-ordered, with no allocation in the
+        library.  Returns the tensors as given."""
+        ptr = [ctypes.c_void_p(t.data_ptr()) if t is not None else None for t in (sums, div_e, div_h)]
+        self._check(self._lib.fdtd_invariants_noalloc(self._h, ptr[0], ptr[1], ptr[2]))
+        return sums, div_e, div_h
 
     def adjoint(self, nsteps: int, mon_comp: int, mon_lo, mon_hi, omega: float, des_lo, des_hi,
                 checkpoint_every: int = 0, out=None, isotropic: bool = False):

@@ -38,7 +38,7 @@ PLAIN_BYTES_PER_UPDATE = PLAIN_E_BYTES + PLAIN_H_BYTES
 PLAIN_FUSED_BYTES_PER_UPDATE = 60
 
 
-def systolic_alg_bytes_per_update(tile, band, conductive=False, fp16=False):
+def systolic_alg_bytes_per_update(tile, band, conductive=False, fp16=False, materials=False):
     """Algorithmic HBM bytes per cell update of the systolic scheme: what the
     method itself must move (Section 4's accounting).  Every step a tile of
     V = Wx*Wy*Wz updated cells takes in its three leading faces (A = WyWz +
@@ -50,17 +50,19 @@ def systolic_alg_bytes_per_update(tile, band, conductive=False, fp16=False):
         in = 6 es + coefficient bytes, out = 6 es,
 
     es being the stored field element (4 B, or 2 B with FP16 storage) and the
-    coefficients cE (3 es) plus, with conductivity, ca (12 B).  FP32 at the
-    15x15x15 tile: 60 * 0.2 + 60 / K = 12 + 60 / K."""
+    coefficients cE (3 es) plus, with conductivity, ca (12 B); with material
+    indices the coefficients of a cell are its 4-byte index.  FP32 at the
+    15x15x15 tile: 60 * 0.2 + 60 / K = 12 + 60 / K, with material indices
+    52 * 0.2 + 52 / K = 10.4 + 52 / K."""
     wx, wy, wz = tile
     es = 2 if fp16 else 4
-    coef = 3 * es + (12 if conductive else 0)
+    coef = 4 if materials else 3 * es + (12 if conductive else 0)
     cin, cout = 6 * es + coef, 6 * es
     a, v = wy * wz + wx * wz + wx * wy, wx * wy * wz
     return (cin + cout) * a / v + (cout + cin) / band
 
 
-def systolic_bytes_per_update(tile, band, conductive=False, fp16=False):
+def systolic_bytes_per_update(tile, band, conductive=False, fp16=False, materials=False):
     """HBM bytes per cell update of this design's exchange (reported beside
     the algorithmic count; it moves more than the method needs, since the
     z face's coefficients are written to a ring as well as read, and with
@@ -75,10 +77,15 @@ def systolic_bytes_per_update(tile, band, conductive=False, fp16=False):
 
     Once per band the whole state goes out and comes back in: E and H out
     and in, the coefficients in (60 B per cell in FP32, 72 B when conductive,
-    30 B with FP16 storage)."""
+    30 B with FP16 storage).  With material indices the x and y faces and
+    the band start read the 4-byte index instead of the coefficients (the z
+    face still carries the 12 B of values)."""
     wx, wy, wz = tile
     axy, v = wx * wy, wx * wy * wz
     c = 24 if conductive else 12            # coefficient bytes per cell (FP32)
+    if materials:
+        per_step = (wy * wz + wx * wz) * (24 + 4 + 24) + axy * (24 + c) * 2
+        return per_step / v + (2 * 24 + 4) / band
     if fp16:
         per_step = (wy * wz + wx * wz + axy) * (24 + c) * 2
         band_bytes = 2 * 12 + 6
@@ -125,13 +132,20 @@ def make_workload(name: str):
 
 
 def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None, storage="fp32"):
+    """scheme: "systolic", "plain", "plain_fused", or "systolic_arrays" (the
+    systolic scheme streaming the per-cell coefficient arrays instead of the
+    material indices)."""
     import torch
     from paper_2502_20610_amd import fdtd
     stream = torch.cuda.current_stream()
+    options = dict(options or {})
+    if scheme == "systolic_arrays":
+        scheme = "systolic"
+        options[fdtd.OPT_MATERIAL_IDS] = 0
     sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme=scheme, stream=stream.cuda_stream,
                           storage=storage)
     try:
-        for k, v in (options or {}).items():
+        for k, v in options.items():
             sim.set_option(k, v)
         dev = torch.device("cuda:0")
         if sigma is None:
@@ -161,7 +175,9 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None
                                                    fdtd.KERNEL_SOURCES, fdtd.KERNEL_SYSTOLIC,
                                                    fdtd.KERNEL_PLAIN_FUSED)}
         if scheme == "systolic":
-            stats["info"] = {"grid": sim.info(fdtd.INFO_SYSTOLIC_GRID),
+            stats["info"] = {"materials": sim.info(fdtd.INFO_MATERIALS) if options.get(
+                                 fdtd.OPT_MATERIAL_IDS, 1) else 0,
+                             "grid": sim.info(fdtd.INFO_SYSTOLIC_GRID),
                              "band_steps": sim.info(fdtd.INFO_SYSTOLIC_BAND),
                              "tickets": sim.info(fdtd.INFO_SYSTOLIC_TICKETS),
                              "ring_slots": sim.info(fdtd.INFO_RING_SLOTS),
@@ -421,7 +437,7 @@ def main():
     ap.add_argument("--steps", type=int, default=128)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--schemes", default="systolic,plain,plain_fused")
+    ap.add_argument("--schemes", default="systolic,systolic_arrays,plain,plain_fused")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--band", type=int, default=0, help="systolic band length (0 = default)")
     ap.add_argument("--workgroups", type=int, default=0, help="systolic grid size (0 = auto)")
@@ -497,7 +513,7 @@ def main():
     for scheme in args.schemes.split(","):
         try:
             opts = {}
-            if scheme == "systolic":
+            if scheme in ("systolic", "systolic_arrays"):
                 if args.band:
                     opts[fdtd.OPT_BAND_STEPS] = args.band
                 if args.workgroups:
@@ -520,10 +536,11 @@ def main():
         avg_s = ms / 1e3 / max(n, 1)
         steps_per_launch = args.steps / max(n, 1)
         band = stats["info"]["band_steps"]
+        mats = stats["info"]["materials"] > 0
         b_alg = systolic_alg_bytes_per_update(stats["info"]["tile"], band, sigma is not None,
-                                              args.storage == "fp16")
+                                              args.storage == "fp16", mats)
         b_design = systolic_bytes_per_update(stats["info"]["tile"], band, sigma is not None,
-                                             args.storage == "fp16")
+                                             args.storage == "fp16", mats)
         if band >= steps_per_launch and band < 64 and not args.band:
             log("systolic: the band (%d steps) is capped by the call length (--steps %d)"
                 % (band, args.steps))
@@ -532,7 +549,7 @@ def main():
         flops = FLOPS_PER_CELL * updates / avg_s / 1e12
         launch = {"workload": w.name + ("_conductive" if sigma is not None else "")
                   + ("_fp16" if args.storage == "fp16" else ""),
-                  "steps": int(round(steps_per_launch)), "band": band}
+                  "steps": int(round(steps_per_launch)), "band": band, "materials": int(mats)}
         traffic = counter_traffic("systolic_kernel", "paper_2502_20610_amd/csrc/systolic.hip",
                                   dict(launch, cells=cells))
         # arithmetic intensity 36 / b_alg flop/B is below the machine balance
@@ -580,13 +597,15 @@ def main():
     for scheme, (ts, st) in results.items():
         c = cells * args.steps / ts
         entry = {"cups": c, "ms_per_step": ts / args.steps * 1e3}
-        if scheme == "systolic":
+        if scheme in ("systolic", "systolic_arrays"):
             entry.update(st["info"])
+            mats = st["info"]["materials"] > 0
             b = systolic_alg_bytes_per_update(st["info"]["tile"], st["info"]["band_steps"],
-                                              sigma is not None, args.storage == "fp16")
+                                              sigma is not None, args.storage == "fp16", mats)
             entry["alg_bytes_per_update"] = b
             entry["design_bytes_per_update"] = systolic_bytes_per_update(
-                st["info"]["tile"], st["info"]["band_steps"], sigma is not None, args.storage == "fp16")
+                st["info"]["tile"], st["info"]["band_steps"], sigma is not None, args.storage == "fp16",
+                mats)
             entry["alg_roofline_frac"] = c * b / (HBM_PEAK_GBS * 1e9)
             entry["effective_bw_frac_84B"] = c * PLAIN_BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9)
         if scheme == "plain":
@@ -610,6 +629,9 @@ def main():
         out["systolic_over_plain"] = out["systolic"]["cups"] / out["plain"]["cups"]
     if "plain_fused" in results and "systolic" in results:
         out["systolic_over_plain_fused"] = out["systolic"]["cups"] / out["plain_fused"]["cups"]
+    if "plain_fused" in results and "systolic_arrays" in results:
+        out["systolic_arrays_over_plain_fused"] = (out["systolic_arrays"]["cups"]
+                                                   / out["plain_fused"]["cups"])
     if sigma is not None:
         out["config"]["conductive"] = {"shell_cells": 16, "sigma_max": args.sigma}
     if args.storage == "fp16":

@@ -129,7 +129,12 @@ int fdtd_destroy(fdtd_ctx* ctx);
  * device and reported at the next synchronising call).  The library
  * computes cE_c = (float)(dt / ((double)eps_c * dx)) and zeroes it on the
  * index-0 planes of PEC axes tangential to component c.  The arrays are
- * copied; the caller keeps ownership. */
+ * copied; the caller keeps ownership.  With FP32 storage the library also
+ * looks for the distinct triples (cEx, cEy, cEz) of the grid (on the device,
+ * a few passes over the coefficients, synchronising the stream): with at
+ * most 256 of them (entry 0 being (+0, +0, +0)) it keeps a 4-byte material
+ * index per cell, which the systolic scheme streams in place of the three
+ * coefficients (the bits it multiplies by are the same). */
 int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
                        const float* eps_z, int where);
 
@@ -371,7 +376,11 @@ enum {
                                  that does not fit is FDTD_EUNSUPPORTED)    */
     FDTD_OPT_WORKGROUPS = 2,  /* systolic: persistent grid size, 0 = auto       */
     FDTD_OPT_SPIN_LIMIT = 3,  /* systolic: polls before a wait times out        */
-    FDTD_OPT_PROFILE = 4      /* 1 = time every kernel launch with HIP events    */
+    FDTD_OPT_PROFILE = 4,     /* 1 = time every kernel launch with HIP events    */
+    FDTD_OPT_MATERIAL_IDS = 5 /* systolic: 1 (default) = stream per-cell material
+                                 indices instead of the coefficient arrays where
+                                 the context has them (FDTD_INFO_MATERIALS > 0);
+                                 0 = always the arrays.  Same results.        */
 };
 
 /* Set a tuning option (see FDTD_OPT_*).  FDTD_EINVAL for unknown options or
@@ -400,7 +409,10 @@ enum {
     FDTD_INFO_TILE_X = 4,          /* updated cells per systolic tile along x, y, z (x:  */
                                    /* 15, or 11 for a context with conductivity)         */
     FDTD_INFO_TILE_Y = 5,
-    FDTD_INFO_TILE_Z = 6
+    FDTD_INFO_TILE_Z = 6,
+    FDTD_INFO_MATERIALS = 7        /* entries of the context's material table, entry 0 */
+                                   /* (+0, +0, +0) included; 0 = none (conductive or   */
+                                   /* FP16 storage, or more than 256 distinct triples)  */
 };
 
 /* Read a piece of launch information (FDTD_INFO_*) into *value; 0 before the

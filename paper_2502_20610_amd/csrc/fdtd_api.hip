@@ -368,6 +368,7 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
     ctx->workgroups = 0;
     ctx->spin_limit = int64_t(1) << 22;
     ctx->profile = false;
+    ctx->use_mat = true;
     ctx->cH = (float)(cfg->dt / cfg->dx);
     ctx->err = "no error";
 
@@ -452,6 +453,10 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
         fail(nullptr, FDTD_EHIP, std::string("fdtd_create init: ") + hipGetErrorString(e));
         return bail(FDTD_EHIP);
     }
+    if (build_material_ids(ctx) != FDTD_OK) {
+        fail(nullptr, FDTD_EHIP, "fdtd_create init: " + ctx->err);
+        return bail(FDTD_EHIP);
+    }
     *out = ctx;
     return FDTD_OK;
 }
@@ -467,6 +472,7 @@ int fdtd_destroy(fdtd_ctx* ctx)
     }
     ctx->pending.clear();
     systolic_release(ctx);
+    release_material_ids(ctx);
     for (int c = 0; c < 6; ++c) {
         if (ctx->field[c]) (void)hipFree(ctx->field[c]);
         if (ctx->field16[c]) (void)hipFree(ctx->field16[c]);
@@ -538,7 +544,7 @@ int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y, co
         if (ctx->ca[c]) (void)hipFree(ctx->ca[c]);
         ctx->ca[c] = nullptr;
     }
-    return FDTD_OK;
+    return build_material_ids(ctx);
 }
 
 int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
@@ -602,6 +608,7 @@ int fdtd_set_lossy_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps
         (void)hipFree(stage);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "set_lossy_materials");
+    release_material_ids(ctx);  // the conductive update reads its per-cell arrays
     return FDTD_OK;
 }
 
@@ -915,6 +922,10 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
         if (value < 1) return fail(ctx, FDTD_EINVAL, "set_option: spin limit must be >= 1");
         ctx->spin_limit = value;
         return FDTD_OK;
+    case FDTD_OPT_MATERIAL_IDS:
+        if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: material ids is 0 or 1");
+        ctx->use_mat = value == 1;
+        return FDTD_OK;
     case FDTD_OPT_PROFILE:
         if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: profile is 0 or 1");
         if (value == 1) {
@@ -960,6 +971,7 @@ int fdtd_get_info(const fdtd_ctx* ctx, int key, int64_t* value)
     case FDTD_INFO_TILE_X: *value = wx; return FDTD_OK;
     case FDTD_INFO_TILE_Y: *value = wy; return FDTD_OK;
     case FDTD_INFO_TILE_Z: *value = wz; return FDTD_OK;
+    case FDTD_INFO_MATERIALS: *value = ctx->nmat; return FDTD_OK;
     default: return FDTD_EINVAL;
     }
 }

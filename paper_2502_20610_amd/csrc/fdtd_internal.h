@@ -85,6 +85,14 @@ struct fdtd_ctx {
 
     double* inv_scratch;  // partial sums of fdtd_invariants (allocated on first use)
 
+    // material indices (lossless FP32 grids with at most kMaxMaterials
+    // distinct coefficient triples): per-cell index into a table of
+    // (cEx, cEy, cEz); nmat = 0 when the per-cell arrays are the only form
+    uint32_t* mat_id;
+    float* mat_tab;   // kMaxMaterials x 3 floats, entry 0 = (+0, +0, +0)
+    int nmat;
+    bool use_mat;     // FDTD_OPT_MATERIAL_IDS
+
     fdtd::SystolicState* sys;
     int sys_grid;        // persistent workgroups of the last systolic launch
     int sys_ring_slots;  // face-ring slots of the last systolic launch
@@ -140,6 +148,14 @@ int invariants_launch(fdtd_ctx* ctx, double* part, double* out, double* div_e, d
 constexpr int kMaxScratchDevices = 64;
 int invariants_scratch_init(int device);
 double* invariants_scratch_ptr(int device);
+
+// Material indices (materials.hip): find the distinct coefficient triples
+// of a lossless FP32 context after its coefficients were built; leaves
+// nmat = 0 when there are more than kMaxMaterials (or the context is
+// conductive or stores FP16).  release_material_ids frees them.
+constexpr int kMaxMaterials = 256;
+int build_material_ids(fdtd_ctx* ctx);
+void release_material_ids(fdtd_ctx* ctx);
 
 // Launch the source-injection kernel for the step that starts at step count s.
 int launch_sources(fdtd_ctx* ctx, int64_t s);

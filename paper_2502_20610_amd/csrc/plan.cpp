@@ -13,8 +13,13 @@ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 }  // namespace
 
 bool build(const int N[3], const int per_in[3], const int W[3], int nsteps, int K, Plan* out,
-           std::string* err)
+           std::string* err, const Order& order)
 {
+    for (int d = 0; d < 3; ++d)
+        if (order.w[d] < 1 || order.w[d] > 64) {
+            *err = "systolic: order weights must lie in [1, 64]";
+            return false;
+        }
     int per[3], L[3], group = 1;
     for (int d = 0; d < 3; ++d) {
         per[d] = per_in[d] ? 1 : 0;
@@ -50,10 +55,15 @@ bool build(const int N[3], const int per_in[3], const int W[3], int nsteps, int 
     for (int bb = 0; bb < nb; ++bb) {
         const int* bi = &band[(size_t)kBandRec * bb];
         const int n3[3] = {bi[1] - bi[0] + 1, bi[3] - bi[2] + 1, bi[5] - bi[4] + 1};
-        // depth below the most upwind corner, along the PEC axes only
-        int maxd = 0;
+        // sort key: weighted depth below the most upwind corner along the
+        // PEC axes, under an optional slab index along one PEC axis
+        int kmax = 0;
         for (int d = 0; d < 3; ++d)
-            if (!per[d]) maxd += n3[d] - 1;
+            if (!per[d]) kmax += order.w[d] * (n3[d] - 1);
+        const int sa = order.slab_axis;
+        const bool slabs = sa >= 0 && sa < 3 && !per[sa] && order.slab > 0;
+        const int nslab = slabs ? (n3[sa] + order.slab - 1) / order.slab : 1;
+        const int maxd = nslab * (kmax + 1) - 1;
         // loop order: PEC axes outside, periodic axes inside, so that the
         // tiles of one ring group are enumerated (and so stored) together
         int ax[3], k = 0;
@@ -64,7 +74,8 @@ bool build(const int N[3], const int per_in[3], const int W[3], int nsteps, int 
         auto depth_of = [&](const int* i3) {
             int dd = 0;
             for (int d = 0; d < 3; ++d)
-                if (!per[d]) dd += n3[d] - 1 - i3[d];
+                if (!per[d]) dd += order.w[d] * (n3[d] - 1 - i3[d]);
+            if (slabs) dd += (nslab - 1 - i3[sa] / order.slab) * (kmax + 1);
             return dd;
         };
         // counting sort by depth (upwind first), stable in the loop order

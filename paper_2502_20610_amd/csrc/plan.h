@@ -40,11 +40,26 @@ struct Plan {
     std::vector<int> depth;       // per ticket: depth below the upwind corner (PEC axes)
 };
 
+// Dequeue order of the tiles of a band.  Tiles are sorted (stably, ring
+// groups staying whole) by the key
+//     slab-major:  (slabs - 1 - i_s / slab) * (kmax + 1) + sum_d w[d] (n_d - 1 - i_d)
+// where i_d is the tile's index in the band's range along PEC axis d, n_d
+// the range's length, and the slab term applies when slab_axis names a PEC
+// axis (slab > 0).  Any positive weights keep every upwind neighbour (along
+// PEC axes) earlier, and so does cutting one axis into slabs taken from its
+// upwind end: w = (1, 1, 1) without slabs is the plain depth below the most
+// upwind corner.
+struct Order {
+    int w[3] = {1, 1, 1};
+    int slab_axis = -1;
+    int slab = 0;
+};
+
 // Build the plan of one grid: N cells per axis, per[d] = 1 on periodic axes,
 // W updated cells per tile and axis, a call of nsteps steps in bands of K.
 // Returns false (with *err) when the plan would exceed 2^30 tickets.
 bool build(const int N[3], const int per[3], const int W[3], int nsteps, int K, Plan* out,
-           std::string* err);
+           std::string* err, const Order& order = Order());
 
 // The plans of several grids merged into one launch order: tickets by band
 // start step, then by grid, each grid keeping its own order.  D = the largest

@@ -44,6 +44,7 @@
 // On PEC axes cells outside the grid are ghosts that read as +0, which
 // reproduces the closed box of the periodic-index definition; on periodic
 // axes the tiles form rings and positions wrap.
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -87,6 +88,8 @@ struct SimArgs {
     int wr[3];   // updated cells of the ring's last (ragged) tile
     int K;       // steps per band of this simulation
     float sc[6], isc[6];  // FP16 storage: field scale 2^e_c and its inverse
+    const unsigned* mid;  // material index per cell (material variant only)
+    const float* mtab;    // material table: kMaxMaterials x (cEx, cEy, cEz)
 };
 
 struct SysArgs {
@@ -321,9 +324,12 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     return *s_abort == 0;
 }
 
-template <int NW, bool DEV, bool PER, bool LOSSY, bool F16>
+template <int NW, bool DEV, bool PER, bool LOSSY, bool F16, bool MAT>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void systolic_kernel(SysArgs A)
 {
+    // MAT: the coefficients enter as per-cell material indices into a table
+    // (lossless FP32 grids); the z face still carries the values themselves
+    static_assert(!(MAT && (LOSSY || F16)), "material indices: lossless FP32 only");
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
     constexpr int PY = 4 * NW;
     constexpr int WY = PY - 1;
@@ -341,8 +347,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     // y-neighbour exchange, two components per half-step
     __shared__ float xch[2][WXk][PY][PZ];
     // incoming faces of the next box: y face [comp][x][z], z face [comp][y][x]
-    __shared__ float xst[NQA][PY][PZ];   // x face [comp][y slot][z slot]
-    __shared__ float yst[NQA][YR][PZ];
+    // (with material indices the x and y faces stage E, H and the index)
+    constexpr int NQS = MAT ? 7 : NQA;
+    __shared__ float xst[NQS][PY][PZ];   // x face [comp][y slot][z slot]
+    __shared__ float yst[NQS][YR][PZ];
+    __shared__ float s_tab[MAT ? kMaxMaterials * 3 : 1];  // material table (cEx, cEy, cEz)
     __shared__ __attribute__((aligned(16))) float zst[NQA][PY][LS];
     // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
     // (with FP16 storage the y face carries the coefficients as well)
@@ -430,6 +439,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         for (int q = 0; q < 6; ++q) rf[q] = make_rsrc((const char*)P.f[q] + ebase * ES, rbytes);
 #pragma unroll
         for (int q = 0; q < 3; ++q) rc[q] = make_rsrc((const char*)P.cE[q] + ebase * ES, rbytes);
+        __amdgpu_buffer_rsrc_t rid;
+        if (MAT) rid = make_rsrc((const char*)P.mid + ebase * 4ull, rbytes);
         __amdgpu_buffer_rsrc_t rca[3];
         if (LOSSY) {
 #pragma unroll
@@ -446,6 +457,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             s_srcw[tid][1] = sq.len;
             s_srcp[tid] = sq.wave;
         }
+        if (MAT)
+            for (int i = tid; i < kMaxMaterials * 3; i += 64 * NW) s_tab[i] = P.mtab[i];
         __syncthreads();
         const int me = t;  // progress counters are per ticket
         const int ox = a * WXk, oy = b * WY, oz = c * WZ;
@@ -595,9 +608,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     } else {
                         E[q][j] = bld<SP>(rf[q], off);
                         H[q][j] = bld<SP>(rf[3 + q], off);
-                        C[q][j] = bld<0>(rc[q], off);
+                        if (!MAT) C[q][j] = bld<0>(rc[q], off);
                     }
                     if (LOSSY) CA[q][j] = bld<0>(rca[q], off);
+                }
+                if (MAT) {
+                    // (an index out of the grid reads 0: the (+0, +0, +0) entry)
+                    const unsigned id = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rid, (int)off, 0, 0) &
+                                        (unsigned)(kMaxMaterials - 1);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) C[q][j] = s_tab[3 * id + q];
                 }
             }
         }
@@ -698,6 +718,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     if (q < 6) {
                         dma_dword<DEV>(rrx, lx, okxr ? oxr + (unsigned)q * cb : kOOB);
                         if (ydo) dma_dword<DEV>(rry, ly, okyr ? oyr + (unsigned)q * cb : kOOB);
+                    } else if (MAT) {
+                        if (q == 6) {  // the material index (one word per cell)
+                            dma_dword<false>(rid, lx, oxf);
+                            if (ydo) dma_dword<false>(rid, ly, oyf);
+                        }
                     } else if (q < 9 && F16) {
                         dma_dword<DEV>(rrxc, lx, okxr ? oxc + (unsigned)(q - 6) * cb : kOOB);
                         if (ydo) dma_dword<DEV>(rryc, ly, okyr ? oyc + (unsigned)(q - 6) * cb : kOOB);
@@ -997,13 +1022,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // forward shell's H^(tau+1/2) and coefficients into the registers
             if (dy == fy) {
 #pragma unroll
-                for (int j = 0; j < WXk; ++j)
+                for (int j = 0; j < WXk; ++j) {
+                    const unsigned id = MAT ? (__builtin_bit_cast(unsigned, yst[6][j][zs]) & (unsigned)(kMaxMaterials - 1)) : 0u;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         H[q][j] = yst[3 + q][j][zs];
-                        C[q][j] = yst[6 + q][j][zs];
+                        C[q][j] = MAT ? s_tab[3 * id + q] : yst[6 + q][j][zs];
                         if (LOSSY) CA[q][j] = yst[9 + q][j][zs];
                     }
+                }
             } else if (dz == fz) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
@@ -1014,17 +1041,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         if (LOSSY) CA[q][j] = zst[9 + q][dy1][j];
                     }
             }
+            const unsigned xid = MAT ? (__builtin_bit_cast(unsigned, xst[6][ys][zs]) & (unsigned)(kMaxMaterials - 1)) : 0u;
             if (!PER || wxr == WXk) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     H[q][WXk] = xst[3 + q][ys][zs];
-                    C[q][WXk] = xst[6 + q][ys][zs];
+                    C[q][WXk] = MAT ? s_tab[3 * xid + q] : xst[6 + q][ys][zs];
                     if (LOSSY) CA[q][WXk] = xst[9 + q][ys][zs];
                 }
             } else {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    const float vh = xst[3 + q][ys][zs], vc = xst[6 + q][ys][zs];
+                    const float vh = xst[3 + q][ys][zs], vc = MAT ? s_tab[3 * xid + q] : xst[6 + q][ys][zs];
                     const float va = LOSSY ? xst[9 + q][ys][zs] : 0.f;
 #pragma unroll
                     for (int j = 0; j < WXk; ++j) {
@@ -1147,7 +1175,21 @@ int build_plan(fdtd_ctx* ctx, SystolicState* s, int nsteps, int K)
     axes_of(ctx, N, per);
     tile_of(ctx, W);
     std::string err;
-    if (!plan::build(N, per, W, nsteps, K, &s->pl, &err)) return fail(ctx, FDTD_EUNSUPPORTED, err);
+    plan::Order order;
+    // FDTD_SYSTOLIC_ORDER="wx,wy,wz[,axis,slab]" overrides the dequeue order
+    // (weights of the depth key; optional slabs along one axis)
+    if (const char* o = getenv("FDTD_SYSTOLIC_ORDER")) {
+        int v[5] = {1, 1, 1, -1, 0};
+        const int n = sscanf(o, "%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4]);
+        if (n >= 3) {
+            for (int d = 0; d < 3; ++d) order.w[d] = v[d];
+            if (n == 5) {
+                order.slab_axis = v[3];
+                order.slab = v[4];
+            }
+        }
+    }
+    if (!plan::build(N, per, W, nsteps, K, &s->pl, &err, order)) return fail(ctx, FDTD_EUNSUPPORTED, err);
     // unique across contexts, so a launch plan is never mistaken for the plan
     // of another context that happens to reuse an address
     static std::atomic<uint64_t> g_version{0};
@@ -1294,18 +1336,21 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
     const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
     const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
-    // variants: [sync][periodic][FP32, conductive, FP16 storage]
+    // material indices when every member has them (and allows them)
+    bool mat = !lossy && !h16;
+    for (int i = 0; i < n && mat; ++i) mat = cs[i]->use_mat && cs[i]->nmat > 0 && cs[i]->mat_id;
+    // variants: [sync][periodic][FP32, conductive, FP16 storage, FP32 with material indices]
     using Kern = void (*)(SysArgs);
-    static const Kern kernels[2][2][3] = {
-        {{systolic_kernel<kNW, false, false, false, false>, systolic_kernel<kNW, false, false, true, false>,
-          systolic_kernel<kNW, false, false, false, true>},
-         {systolic_kernel<kNW, false, true, false, false>, systolic_kernel<kNW, false, true, true, false>,
-          systolic_kernel<kNW, false, true, false, true>}},
-        {{systolic_kernel<kNW, true, false, false, false>, systolic_kernel<kNW, true, false, true, false>,
-          systolic_kernel<kNW, true, false, false, true>},
-         {systolic_kernel<kNW, true, true, false, false>, systolic_kernel<kNW, true, true, true, false>,
-          systolic_kernel<kNW, true, true, false, true>}}};
-    const Kern kern = kernels[dev][anyper][h16 ? 2 : (lossy ? 1 : 0)];
+    static const Kern kernels[2][2][4] = {
+        {{systolic_kernel<kNW, false, false, false, false, false>, systolic_kernel<kNW, false, false, true, false, false>,
+          systolic_kernel<kNW, false, false, false, true, false>, systolic_kernel<kNW, false, false, false, false, true>},
+         {systolic_kernel<kNW, false, true, false, false, false>, systolic_kernel<kNW, false, true, true, false, false>,
+          systolic_kernel<kNW, false, true, false, true, false>, systolic_kernel<kNW, false, true, false, false, true>}},
+        {{systolic_kernel<kNW, true, false, false, false, false>, systolic_kernel<kNW, true, false, true, false, false>,
+          systolic_kernel<kNW, true, false, false, true, false>, systolic_kernel<kNW, true, false, false, false, true>},
+         {systolic_kernel<kNW, true, true, false, false, false>, systolic_kernel<kNW, true, true, true, false, false>,
+          systolic_kernel<kNW, true, true, false, true, false>, systolic_kernel<kNW, true, true, false, false, true>}}};
+    const Kern kern = kernels[dev][anyper][h16 ? 2 : (lossy ? 1 : (mat ? 3 : 0))];
     hipError_t e;
     if (L->sm_count == 0) {
         hipDeviceProp_t prop;
@@ -1412,6 +1457,8 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
             P.wr[d] = c->sys->pl.per[d] ? nd - W * (c->sys->pl.L[d] - 1) : W;
         }
         P.K = c->sys->pl.K;
+        P.mid = mat ? c->mat_id : nullptr;
+        P.mtab = mat ? c->mat_tab : nullptr;
     }
     hipStream_t st = lead->stream;
     // order the launch after each member's earlier work

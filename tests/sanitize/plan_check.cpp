@@ -41,11 +41,12 @@ static int g_fail = 0;
 
 static int wrap(const Plan& p, int d, int v) { return p.per[d] ? ((v % p.L[d]) + p.L[d]) % p.L[d] : v; }
 
-static bool check_plan(const int N[3], const int per[3], const int W[3], int nsteps, int K, Plan* out)
+static bool check_plan(const int N[3], const int per[3], const int W[3], int nsteps, int K, Plan* out,
+                       const fdtd::plan::Order& order = fdtd::plan::Order())
 {
     Plan& p = *out;
     std::string err;
-    CHECK(fdtd::plan::build(N, per, W, nsteps, K, &p, &err), "build failed: %s", err.c_str());
+    CHECK(fdtd::plan::build(N, per, W, nsteps, K, &p, &err, order), "build failed: %s", err.c_str());
     CHECK(p.nbands == (nsteps + K - 1) / K, "band count");
     CHECK((int)p.tickets.size() == p.nt && (int)p.tix.size() == p.nt && (int)p.depth.size() == p.nt, "sizes");
     CHECK((int)p.band.size() == kBandRec * p.nbands, "band records");
@@ -184,6 +185,19 @@ int main()
         if (!(cost >= 1.0 && isfinite(cost))) {
             fprintf(stderr, "band cost %g\n", cost);
             return 1;
+        }
+        // other dequeue orders: weighted depth keys and slabs along each axis
+        const int orders[][5] = {{1, 1, 3, -1, 0}, {4, 4, 1, -1, 0}, {1, 1, 1, 1, 2}, {2, 1, 1, 0, 1}, {1, 3, 2, 2, 3}};
+        for (const auto& o : orders) {
+            fdtd::plan::Order ord;
+            for (int d = 0; d < 3; ++d) ord.w[d] = o[d];
+            ord.slab_axis = o[3];
+            ord.slab = o[4];
+            Plan q;
+            if (!check_plan(c.N, c.per, c.W, c.nsteps, c.K, &q, ord)) {
+                fprintf(stderr, "order %d,%d,%d slab %d:%d\n", o[0], o[1], o[2], o[3], o[4]);
+                return 1;
+            }
         }
         if (c.N[0] <= 64) plans.push_back(std::move(p));
     }

@@ -38,6 +38,12 @@ def test_systolic_algorithmic_bytes_follow_the_face_and_band_formula():
     in FP32), out = E and H (24 B): 12 + 60/K at the 15^3 tile."""
     assert bench.systolic_alg_bytes_per_update((15, 15, 15), 20) == pytest.approx(12.0 + 3.0)
     assert bench.systolic_alg_bytes_per_update((15, 15, 15), 64) == pytest.approx(12.0 + 60 / 64)
+    # material indices: a cell's coefficients enter as its 4-byte index (in = 28 B)
+    assert bench.systolic_alg_bytes_per_update((15, 15, 15), 20, materials=True) == pytest.approx(
+        52 * 0.2 + 52 / 20)
+    # this design with indices: x and y faces read the index, the z face keeps the values
+    assert bench.systolic_bytes_per_update((15, 15, 15), 20, materials=True) == pytest.approx(
+        (2 * 225 * 52 + 225 * 72) / 3375 + 52 / 20)
     # the paper's 31x15x15 block: A = 225 + 465 + 465
     assert bench.systolic_alg_bytes_per_update((31, 15, 15), 64) == pytest.approx(
         60 * 1155 / 6975 + 60 / 64)

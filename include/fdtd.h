@@ -377,10 +377,16 @@ enum {
     FDTD_OPT_WORKGROUPS = 2,  /* systolic: persistent grid size, 0 = auto       */
     FDTD_OPT_SPIN_LIMIT = 3,  /* systolic: polls before a wait times out        */
     FDTD_OPT_PROFILE = 4,     /* 1 = time every kernel launch with HIP events    */
-    FDTD_OPT_MATERIAL_IDS = 5 /* systolic: 1 (default) = stream per-cell material
+    FDTD_OPT_MATERIAL_IDS = 5,/* systolic: 1 (default) = stream per-cell material
                                  indices instead of the coefficient arrays where
                                  the context has them (FDTD_INFO_MATERIALS > 0);
                                  0 = always the arrays.  Same results.        */
+    FDTD_OPT_GRAPHS = 6       /* plain schemes: 1 (default) = calls of 16 steps
+                                 or more replay a HIP graph of 16 steps
+                                 (captured on first use, re-captured when the
+                                 arrays, sources or scales change); 0 = one
+                                 launch per kernel.  Same results; per-kernel
+                                 timing (FDTD_OPT_PROFILE) launches directly. */
 };
 
 /* Set a tuning option (see FDTD_OPT_*).  FDTD_EINVAL for unknown options or

@@ -133,12 +133,18 @@ __global__ void zero_pec_kernel(T* __restrict__ f, int comp, int nx, int ny, int
     if (comp != 2 && bcz == FDTD_BC_PEC && t < (long long)nx * ny) f[t * nz] = T(0);
 }
 
+// With stepp (a step loop replayed as a graph) the step is read from *stepp,
+// which the kernel then advances; otherwise it is s.
 __global__ void sources_kernel(float* Ex, float* Ey, float* Ez, const DevSource* __restrict__ src,
-                               int nsrc, long long s, int ny, int nz)
+                               int nsrc, long long s, int ny, int nz, long long* stepp)
 {
     // One thread; sources are applied in table order (several sources on one
     // cell add up in the same order as in any other scheme).
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (stepp) {
+        s = *stepp;
+        *stepp = s + 1;
+    }
     for (int q = 0; q < nsrc; ++q) {
         long long m = s - src[q].first;
         if (m < 0 || m >= src[q].len) continue;
@@ -152,9 +158,13 @@ __global__ void sources_kernel(float* Ex, float* Ey, float* Ez, const DevSource*
 // sum stored rounded again.
 __global__ void sources_f16_kernel(uint16_t* Ex, uint16_t* Ey, uint16_t* Ez, const DevSource* __restrict__ src,
                                    int nsrc, long long s, int ny, int nz, float sx, float sy, float sz,
-                                   float ix, float iy, float iz)
+                                   float ix, float iy, float iz, long long* stepp)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (stepp) {
+        s = *stepp;
+        *stepp = s + 1;
+    }
     for (int q = 0; q < nsrc; ++q) {
         long long m = s - src[q].first;
         if (m < 0 || m >= src[q].len) continue;
@@ -297,21 +307,21 @@ bool sources_active(const fdtd_ctx* ctx, int64_t s)
     return false;
 }
 
-int launch_sources(fdtd_ctx* ctx, int64_t s)
+int launch_sources(fdtd_ctx* ctx, int64_t s, hipStream_t st, long long* stepp)
 {
     PendingTiming t;
-    timing_begin(ctx, FDTD_KERNEL_SOURCES, &t);
+    if (!stepp) timing_begin(ctx, FDTD_KERNEL_SOURCES, &t);
     if (ctx->storage == FDTD_FP16_STORAGE)
-        hipLaunchKernelGGL(sources_f16_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->field16[0],
+        hipLaunchKernelGGL(sources_f16_kernel, dim3(1), dim3(64), 0, st, ctx->field16[0],
                            ctx->field16[1], ctx->field16[2], ctx->dev_sources, ctx->dev_sources_n,
                            (long long)s, ctx->ny, ctx->nz, ldexpf(1.0f, ctx->fexp[0]), ldexpf(1.0f, ctx->fexp[1]),
                            ldexpf(1.0f, ctx->fexp[2]), ldexpf(1.0f, -ctx->fexp[0]), ldexpf(1.0f, -ctx->fexp[1]),
-                           ldexpf(1.0f, -ctx->fexp[2]));
+                           ldexpf(1.0f, -ctx->fexp[2]), stepp);
     else
-        hipLaunchKernelGGL(sources_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->field[0],
+        hipLaunchKernelGGL(sources_kernel, dim3(1), dim3(64), 0, st, ctx->field[0],
                            ctx->field[1], ctx->field[2], ctx->dev_sources, ctx->dev_sources_n,
-                           (long long)s, ctx->ny, ctx->nz);
-    timing_end(ctx, &t);
+                           (long long)s, ctx->ny, ctx->nz, stepp);
+    if (!stepp) timing_end(ctx, &t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "launch(sources)");
     return FDTD_OK;
@@ -369,6 +379,7 @@ int fdtd_create(const fdtd_config* cfg, fdtd_ctx** out)
     ctx->spin_limit = int64_t(1) << 22;
     ctx->profile = false;
     ctx->use_mat = true;
+    ctx->use_graphs = true;
     ctx->cH = (float)(cfg->dt / cfg->dx);
     ctx->err = "no error";
 
@@ -473,6 +484,7 @@ int fdtd_destroy(fdtd_ctx* ctx)
     ctx->pending.clear();
     systolic_release(ctx);
     release_material_ids(ctx);
+    release_step_graph(ctx);
     for (int c = 0; c < 6; ++c) {
         if (ctx->field[c]) (void)hipFree(ctx->field[c]);
         if (ctx->field16[c]) (void)hipFree(ctx->field16[c]);
@@ -921,6 +933,10 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
     case FDTD_OPT_SPIN_LIMIT:
         if (value < 1) return fail(ctx, FDTD_EINVAL, "set_option: spin limit must be >= 1");
         ctx->spin_limit = value;
+        return FDTD_OK;
+    case FDTD_OPT_GRAPHS:
+        if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: graphs is 0 or 1");
+        ctx->use_graphs = value == 1;
         return FDTD_OK;
     case FDTD_OPT_MATERIAL_IDS:
         if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: material ids is 0 or 1");

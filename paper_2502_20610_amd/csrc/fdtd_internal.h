@@ -37,6 +37,7 @@ struct PendingTiming {
 };
 
 struct SystolicState;  // defined in systolic.hip
+struct StepGraph;      // defined in plain.hip
 
 }  // namespace fdtd
 
@@ -93,6 +94,11 @@ struct fdtd_ctx {
     int nmat;
     bool use_mat;     // FDTD_OPT_MATERIAL_IDS
 
+    // plain schemes: step loops replayed as a HIP graph (FDTD_OPT_GRAPHS)
+    bool use_graphs;
+    fdtd::StepGraph* graph;
+    long long* d_step;  // the step counter the graph advances (two words)
+
     fdtd::SystolicState* sys;
     int sys_grid;        // persistent workgroups of the last systolic launch
     int sys_ring_slots;  // face-ring slots of the last systolic launch
@@ -117,6 +123,9 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps);
 int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps);
 // Allocate the fused step's second field set (plain.hip).
 int plain_fused_prepare(fdtd_ctx* ctx);
+// Free the captured step graph and its counter (plain.hip).
+void release_step_graph_exec(StepGraph* g);
+void release_step_graph(fdtd_ctx* ctx);
 
 // Systolic scheme (systolic.hip).
 int systolic_supported(const fdtd_ctx* ctx, std::string* why);
@@ -157,8 +166,10 @@ constexpr int kMaxMaterials = 256;
 int build_material_ids(fdtd_ctx* ctx);
 void release_material_ids(fdtd_ctx* ctx);
 
-// Launch the source-injection kernel for the step that starts at step count s.
-int launch_sources(fdtd_ctx* ctx, int64_t s);
+// Launch the source-injection kernel for the step that starts at step count s
+// on stream st (ctx->stream for a direct launch); with stepp (a graph being
+// captured) the kernel reads the step from *stepp and advances it instead.
+int launch_sources(fdtd_ctx* ctx, int64_t s, hipStream_t st, long long* stepp = nullptr);
 
 // True if any source is active in the step starting at step count s.
 bool sources_active(const fdtd_ctx* ctx, int64_t s);

@@ -16,6 +16,7 @@
 #include "fdtd_internal.h"
 
 #include <algorithm>
+#include <new>
 
 namespace {
 
@@ -186,8 +187,16 @@ __global__ __launch_bounds__(64 * (kFY + 1)) void plain_fused_kernel(
     const float* __restrict__ cEx, const float* __restrict__ cEy, const float* __restrict__ cEz,
     const float* __restrict__ cax, const float* __restrict__ cay, const float* __restrict__ caz,
     float cH, int nx, int ny, int nz, int gz, int gy, int ntiles, int xchunk,
-    const fdtd::DevSource* __restrict__ src, int nsrc, long long step)
+    const fdtd::DevSource* __restrict__ src, int nsrc, long long step, const long long* step_in,
+    long long* step_out)
 {
+    // a replayed graph passes the step through device words: read from
+    // step_in, the next one written to step_out (a different word, so no
+    // block of this launch reads what it writes)
+    if (step_in) {
+        step = *step_in;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) *step_out = step + 1;
+    }
     // E' of the last three planes (x, y, z components): a plane is read in
     // the iteration after it is written and overwritten two iterations
     // later, so one barrier per plane separates every write from the reads
@@ -372,7 +381,59 @@ void plain_grid(const fdtd_ctx* ctx, dim3* grid, int* xchunk)
 
 namespace fdtd {
 
-int plain_step(fdtd_ctx* ctx, int64_t nsteps)
+// One step loop of a plain scheme replayed as a HIP graph: kGraphSteps steps
+// of kernel nodes, captured once on a private stream and replayed with one
+// launch per kGraphSteps steps.  Kernels that need the step number (the
+// sources) read it from a device counter that the graph itself advances.
+// The graph is rebuilt whenever an argument its kernels were captured with
+// changes (arrays, sources, scales, scheme).
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<const void*> key;
+};
+
+namespace {
+
+constexpr int kGraphSteps = 16;  // steps per replay (even: the fused scheme's two field sets alternate)
+
+__global__ void set_step_kernel(long long* p, long long v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        p[0] = v;
+        p[1] = v;
+    }
+}
+
+// Everything the captured kernels take: a replay is valid while it is unchanged.
+std::vector<const void*> graph_key(const fdtd_ctx* ctx, int scheme)
+{
+    std::vector<const void*> k;
+    k.push_back((const void*)(intptr_t)scheme);
+    k.push_back((const void*)(intptr_t)ctx->storage);
+    for (int c = 0; c < 6; ++c) {
+        k.push_back(ctx->field[c]);
+        k.push_back(ctx->alt[c]);
+        k.push_back(ctx->field16[c]);
+        k.push_back((const void*)(intptr_t)ctx->fexp[c]);
+    }
+    for (int c = 0; c < 3; ++c) {
+        k.push_back(ctx->coef[c]);
+        k.push_back(ctx->coef16[c]);
+        k.push_back(ctx->ca[c]);
+    }
+    k.push_back(ctx->dev_sources);
+    k.push_back((const void*)(intptr_t)ctx->dev_sources_n);
+    k.push_back(ctx->d_step);
+    return k;
+}
+
+// Queue n steps of the two-launch plain scheme on st.  Direct launches (stepp
+// null) start at ctx->step_count and skip the sources kernel on steps no
+// source reaches; under capture (stepp set) every step has a sources node
+// that reads and advances *stepp.
+int queue_plain(fdtd_ctx* ctx, hipStream_t st, int64_t n, long long* stepp)
 {
     dim3 grid;
     int xchunk;
@@ -386,46 +447,181 @@ int plain_step(fdtd_ctx* ctx, int64_t nsteps)
     const bool h16 = ctx->storage == FDTD_FP16_STORAGE;
     uint16_t* const* f16 = ctx->field16;
     uint16_t* const* c16 = ctx->coef16;
-    for (int64_t n = 0; n < nsteps; ++n) {
-        const int64_t s = ctx->step_count;
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t s = ctx->step_count + q;
         PendingTiming t;
-        timing_begin(ctx, FDTD_KERNEL_PLAIN_E, &t);
+        if (!stepp) timing_begin(ctx, FDTD_KERNEL_PLAIN_E, &t);
         if (h16)
-            hipLaunchKernelGGL((plain_E_kernel<false, F16Store>), grid, block, 0, ctx->stream, f16[0], f16[1],
+            hipLaunchKernelGGL((plain_E_kernel<false, F16Store>), grid, block, 0, st, f16[0], f16[1],
                                f16[2], f16[3], f16[4], f16[5], c16[0], c16[1], c16[2], nullptr, nullptr,
                                nullptr, ctx->nx, ctx->ny, ctx->nz, xchunk, sc);
         else if (ctx->ca[0])
-            hipLaunchKernelGGL((plain_E_kernel<true, F32Store>), grid, block, 0, ctx->stream, ctx->field[0],
+            hipLaunchKernelGGL((plain_E_kernel<true, F32Store>), grid, block, 0, st, ctx->field[0],
                                ctx->field[1], ctx->field[2], ctx->field[3], ctx->field[4], ctx->field[5],
                                ctx->coef[0], ctx->coef[1], ctx->coef[2], ctx->ca[0], ctx->ca[1],
                                ctx->ca[2], ctx->nx, ctx->ny, ctx->nz, xchunk, sc);
         else
-            hipLaunchKernelGGL((plain_E_kernel<false, F32Store>), grid, block, 0, ctx->stream, ctx->field[0],
+            hipLaunchKernelGGL((plain_E_kernel<false, F32Store>), grid, block, 0, st, ctx->field[0],
                                ctx->field[1], ctx->field[2], ctx->field[3], ctx->field[4], ctx->field[5],
                                ctx->coef[0], ctx->coef[1], ctx->coef[2], nullptr, nullptr, nullptr,
                                ctx->nx, ctx->ny, ctx->nz, xchunk, sc);
-        timing_end(ctx, &t);
+        if (!stepp) timing_end(ctx, &t);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "launch(plain E)");
-        if (sources_active(ctx, s)) {
-            int rc = launch_sources(ctx, s);
+        if (stepp ? ctx->dev_sources_n > 0 : sources_active(ctx, s)) {
+            int rc = launch_sources(ctx, s, st, stepp);
             if (rc) return rc;
         }
-        timing_begin(ctx, FDTD_KERNEL_PLAIN_H, &t);
+        if (!stepp) timing_begin(ctx, FDTD_KERNEL_PLAIN_H, &t);
         if (h16)
-            hipLaunchKernelGGL(plain_H_kernel<F16Store>, grid, block, 0, ctx->stream, f16[0], f16[1], f16[2],
+            hipLaunchKernelGGL(plain_H_kernel<F16Store>, grid, block, 0, st, f16[0], f16[1], f16[2],
                                f16[3], f16[4], f16[5], ctx->cH, ctx->nx, ctx->ny, ctx->nz, xchunk, sc);
         else
-            hipLaunchKernelGGL(plain_H_kernel<F32Store>, grid, block, 0, ctx->stream, ctx->field[0],
+            hipLaunchKernelGGL(plain_H_kernel<F32Store>, grid, block, 0, st, ctx->field[0],
                                ctx->field[1], ctx->field[2], ctx->field[3], ctx->field[4], ctx->field[5],
                                ctx->cH, ctx->nx, ctx->ny, ctx->nz, xchunk, sc);
-        timing_end(ctx, &t);
+        if (!stepp) timing_end(ctx, &t);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "launch(plain H)");
-        ctx->step_count += 1;
     }
     return FDTD_OK;
 }
+
+// Queue n steps of the fused plain scheme on st (n even under capture, so
+// the graph ends on the field set it started from).  Direct launches trade
+// ctx->field and ctx->alt after every step; a capture leaves them as they
+// were (it passes the step through the device words stepp[0] and stepp[1]).
+int queue_fused(fdtd_ctx* ctx, hipStream_t st, int64_t n, long long* stepp)
+{
+    const int gz = (ctx->nz + kFZ - 1) / kFZ;
+    const int gy = (ctx->ny + kFY - 1) / kFY;
+    // enough blocks to fill the CUs several times over, with long x runs
+    const long long base = (long long)gz * gy;
+    long long nchunks = std::max<long long>(1, std::min<long long>((4096 + base - 1) / base, ctx->nx));
+    const int xchunk = (int)((ctx->nx + nchunks - 1) / nchunks);
+    const long long ntiles = base * ((ctx->nx + xchunk - 1) / xchunk);
+    if (ntiles > (1LL << 30)) return fail(ctx, FDTD_EUNSUPPORTED, "fused plain step: grid too large");
+    const dim3 grid((unsigned)((ntiles + kXCD - 1) / kXCD * kXCD));  // a multiple of kXCD
+    const dim3 block(64, kFY + 1);
+    const bool lossy = ctx->ca[0] != nullptr;
+    const bool srcs = ctx->dev_sources_n > 0;
+    float* in[6];
+    float* out[6];
+    for (int c = 0; c < 6; ++c) {
+        in[c] = ctx->field[c];
+        out[c] = ctx->alt[c];
+    }
+    for (int64_t q = 0; q < n; ++q) {
+        const long long* sin = (stepp && srcs) ? stepp + (q & 1) : nullptr;
+        long long* sout = (stepp && srcs) ? stepp + ((q + 1) & 1) : nullptr;
+        PendingTiming t;
+        if (!stepp) timing_begin(ctx, FDTD_KERNEL_PLAIN_FUSED, &t);
+        hipLaunchKernelGGL((lossy ? plain_fused_kernel<true> : plain_fused_kernel<false>), grid, block, 0,
+                           st, in[0], in[1], in[2], in[3], in[4], in[5], out[0], out[1], out[2],
+                           out[3], out[4], out[5], ctx->coef[0], ctx->coef[1], ctx->coef[2], ctx->ca[0],
+                           ctx->ca[1], ctx->ca[2], ctx->cH, ctx->nx, ctx->ny, ctx->nz, gz, gy,
+                           (int)ntiles, xchunk, (const DevSource*)ctx->dev_sources, ctx->dev_sources_n,
+                           (long long)(ctx->step_count + q), sin, sout);
+        if (!stepp) timing_end(ctx, &t);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(ctx, e, "launch(fused plain step)");
+        for (int c = 0; c < 6; ++c) std::swap(in[c], out[c]);
+    }
+    if (!stepp && (n & 1))
+        for (int c = 0; c < 6; ++c) std::swap(ctx->field[c], ctx->alt[c]);
+    return FDTD_OK;
+}
+
+// (Re)capture the graph of kGraphSteps steps of `scheme` when its key changed.
+int ensure_graph(fdtd_ctx* ctx, int scheme)
+{
+    hipError_t e;
+    if (!ctx->d_step) {
+        if ((e = hipMalloc(&ctx->d_step, 2 * sizeof(long long))) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->d_step = nullptr;
+            return fail(ctx, FDTD_ENOMEM, "step graph: counter allocation failed");
+        }
+    }
+    if (!ctx->graph) {
+        ctx->graph = new (std::nothrow) StepGraph();
+        if (!ctx->graph) return fail(ctx, FDTD_ENOMEM, "step graph: host allocation failed");
+    }
+    StepGraph* G = ctx->graph;
+    std::vector<const void*> key = graph_key(ctx, scheme);
+    if (G->exec && G->key == key) return FDTD_OK;
+    release_step_graph_exec(G);
+    if (!G->cap && (e = hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(ctx, e, "step graph: capture stream");
+    if ((e = hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(ctx, e, "step graph: begin capture");
+    const int rc = scheme == FDTD_SCHEME_PLAIN_FUSED ? queue_fused(ctx, G->cap, kGraphSteps, ctx->d_step)
+                                                     : queue_plain(ctx, G->cap, kGraphSteps, ctx->d_step);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(G->cap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "step graph: end capture");
+    G->graph = g;
+    if ((e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+        G->exec = nullptr;
+        return hip_fail(ctx, e, "step graph: instantiate");
+    }
+    G->key = key;
+    return FDTD_OK;
+}
+
+// Advance n steps: whole graphs of kGraphSteps steps where the option allows
+// (and per-kernel timing is off), direct launches for the rest.
+int run_steps(fdtd_ctx* ctx, int64_t nsteps, int scheme)
+{
+    const bool fused = scheme == FDTD_SCHEME_PLAIN_FUSED;
+    int64_t reps = (ctx->use_graphs && !ctx->profile) ? nsteps / kGraphSteps : 0;
+    if (reps > 0) {
+        int rc = ensure_graph(ctx, scheme);
+        if (rc) return rc;
+        hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_step,
+                           (long long)ctx->step_count);
+        hipError_t e = hipGetLastError();
+        for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(ctx->graph->exec, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "step graph: launch");
+        ctx->step_count += reps * kGraphSteps;  // (an even count: the field sets are where they were)
+    }
+    const int64_t rest = nsteps - reps * kGraphSteps;
+    if (rest > 0) {
+        int rc = fused ? queue_fused(ctx, ctx->stream, rest, nullptr) : queue_plain(ctx, ctx->stream, rest, nullptr);
+        if (rc) return rc;
+        ctx->step_count += rest;
+    }
+    return FDTD_OK;
+}
+
+}  // namespace
+
+void release_step_graph_exec(StepGraph* G)
+{
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    G->exec = nullptr;
+    G->graph = nullptr;
+    G->key.clear();
+}
+
+void release_step_graph(fdtd_ctx* ctx)
+{
+    if (ctx->graph) {
+        release_step_graph_exec(ctx->graph);
+        if (ctx->graph->cap) (void)hipStreamDestroy(ctx->graph->cap);
+        delete ctx->graph;
+        ctx->graph = nullptr;
+    }
+    if (ctx->d_step) (void)hipFree(ctx->d_step);
+    ctx->d_step = nullptr;
+}
+
+int plain_step(fdtd_ctx* ctx, int64_t nsteps) { return run_steps(ctx, nsteps, FDTD_SCHEME_PLAIN); }
 
 int plain_fused_prepare(fdtd_ctx* ctx)
 {
@@ -448,35 +644,7 @@ int plain_fused_step(fdtd_ctx* ctx, int64_t nsteps)
 {
     int rc = plain_fused_prepare(ctx);
     if (rc) return rc;
-    const int gz = (ctx->nz + kFZ - 1) / kFZ;
-    const int gy = (ctx->ny + kFY - 1) / kFY;
-    // enough blocks to fill the CUs several times over, with long x runs
-    const long long base = (long long)gz * gy;
-    long long nchunks = std::max<long long>(1, std::min<long long>((4096 + base - 1) / base, ctx->nx));
-    const int xchunk = (int)((ctx->nx + nchunks - 1) / nchunks);
-    const long long ntiles = base * ((ctx->nx + xchunk - 1) / xchunk);
-    if (ntiles > (1LL << 30)) return fail(ctx, FDTD_EUNSUPPORTED, "fused plain step: grid too large");
-    const dim3 grid((unsigned)((ntiles + kXCD - 1) / kXCD * kXCD));  // a multiple of kXCD
-    const dim3 block(64, kFY + 1);
-    const bool lossy = ctx->ca[0] != nullptr;
-    for (int64_t n = 0; n < nsteps; ++n) {
-        float* const* in = ctx->field;
-        float* const* out = ctx->alt;
-        PendingTiming t;
-        timing_begin(ctx, FDTD_KERNEL_PLAIN_FUSED, &t);
-        hipLaunchKernelGGL((lossy ? plain_fused_kernel<true> : plain_fused_kernel<false>), grid, block, 0,
-                           ctx->stream, in[0], in[1], in[2], in[3], in[4], in[5], out[0], out[1], out[2],
-                           out[3], out[4], out[5], ctx->coef[0], ctx->coef[1], ctx->coef[2], ctx->ca[0],
-                           ctx->ca[1], ctx->ca[2], ctx->cH, ctx->nx, ctx->ny, ctx->nz, gz, gy,
-                           (int)ntiles, xchunk, (const DevSource*)ctx->dev_sources, ctx->dev_sources_n,
-                           (long long)ctx->step_count);
-        timing_end(ctx, &t);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(ctx, e, "launch(fused plain step)");
-        for (int c = 0; c < 6; ++c) std::swap(ctx->field[c], ctx->alt[c]);
-        ctx->step_count += 1;
-    }
-    return FDTD_OK;
+    return run_steps(ctx, nsteps, FDTD_SCHEME_PLAIN_FUSED);
 }
 
 }  // namespace fdtd

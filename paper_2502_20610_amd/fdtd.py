@@ -27,7 +27,8 @@ BC_PEC, BC_PERIODIC = 0, 1
 SCHEME_PLAIN, SCHEME_SYSTOLIC, SCHEME_PLAIN_FUSED = 0, 1, 2
 FP32, FP16_STORAGE = 0, 1
 HOST, DEVICE = 0, 1
-OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_MATERIAL_IDS = range(6)
+(OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_MATERIAL_IDS,
+ OPT_GRAPHS) = range(7)
 KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC, KERNEL_PLAIN_FUSED = range(5)
 (INFO_SYSTOLIC_GRID, INFO_SYSTOLIC_BAND, INFO_SYSTOLIC_TICKETS, INFO_RING_SLOTS, INFO_TILE_X,
  INFO_TILE_Y, INFO_TILE_Z, INFO_MATERIALS) = range(8)

@@ -131,7 +131,8 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %r" % name)
 
 
-def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None, storage="fp32"):
+def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None, storage="fp32",
+               autotune=False):
     """scheme: "systolic", "plain", "plain_fused", or "systolic_arrays" (the
     systolic scheme streaming the per-cell coefficient arrays instead of the
     material indices)."""
@@ -160,6 +161,9 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None
         log("%s: warmup %d steps" % (scheme, warmup))
         if warmup:
             sim.step(warmup)
+        if autotune and scheme == "systolic":
+            tile, band = sim.autotune(steps)
+            log("%s: autotune chose tile width %d, band %d" % (scheme, tile, band))
         # build what a call of `steps` steps needs (the systolic plan and face
         # rings, the fused step's second field set) outside the timed region
         sim.prepare(steps)
@@ -440,6 +444,10 @@ def main():
     ap.add_argument("--schemes", default="systolic,systolic_arrays,plain,plain_fused")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--band", type=int, default=0, help="systolic band length (0 = default)")
+    ap.add_argument("--tile-x", type=int, default=0, help="systolic tile width along x (0 = default, 11, 15)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="systolic: time the tile widths and band lengths first (fdtd_autotune) and "
+                         "run the fastest")
     ap.add_argument("--workgroups", type=int, default=0, help="systolic grid size (0 = auto)")
     ap.add_argument("--sweep", default="",
                     help="comma-separated n: instead of the headline line, one JSON line per "
@@ -518,7 +526,10 @@ def main():
                     opts[fdtd.OPT_BAND_STEPS] = args.band
                 if args.workgroups:
                     opts[fdtd.OPT_WORKGROUPS] = args.workgroups
-            t, stats = run_scheme(w, scheme, args.steps, args.warmup, opts, sigma, args.storage)
+                if args.tile_x:
+                    opts[fdtd.OPT_TILE_X] = args.tile_x
+            t, stats = run_scheme(w, scheme, args.steps, args.warmup, opts, sigma, args.storage,
+                                  autotune=args.autotune and scheme == "systolic")
         except fdtd.FdtdError as e:
             if e.code == fdtd.FDTD_EUNSUPPORTED:
                 log("%s unavailable: %s" % (scheme, e))

@@ -381,17 +381,38 @@ enum {
                                  indices instead of the coefficient arrays where
                                  the context has them (FDTD_INFO_MATERIALS > 0);
                                  0 = always the arrays.  Same results.        */
-    FDTD_OPT_GRAPHS = 6       /* plain schemes: 1 (default) = calls of 16 steps
+    FDTD_OPT_GRAPHS = 6,      /* plain schemes: 1 (default) = calls of 16 steps
                                  or more replay a HIP graph of 16 steps
                                  (captured on first use, re-captured when the
                                  arrays, sources or scales change); 0 = one
                                  launch per kernel.  Same results; per-kernel
                                  timing (FDTD_OPT_PROFILE) launches directly. */
+    FDTD_OPT_TILE_X = 7       /* systolic: updated cells per tile along x on a
+                                 lossless FP32 grid, 15 or 11 (0 = default, 15;
+                                 conductive grids always take 11, FP16 storage
+                                 15).  A batch needs one width for all.        */
 };
 
 /* Set a tuning option (see FDTD_OPT_*).  FDTD_EINVAL for unknown options or
  * out-of-range values. */
 int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value);
+
+/* Systolic scheme: choose the tile width along x and the band length (the
+ * subdomain size and steps per exchange that Section 4 fixes by hand for one
+ * GPU) by timing the candidates on this context's grid, for calls of nsteps
+ * steps (runs of min(nsteps, 64) steps): widths 15 and 11 on lossless FP32
+ * grids (11 when conductive, 15 with FP16 storage), bands of 8, 12, 16, 24,
+ * 32, 48, 64 steps and the run length itself, each run twice from the
+ * current state.  The fields and step count are restored after every run
+ * (a device copy of the six field arrays is held meanwhile), and the
+ * fastest pair becomes the context's FDTD_OPT_TILE_X and
+ * FDTD_OPT_BAND_STEPS.  The choice is kept for the process, keyed by grid
+ * shape, boundaries, storage, conductivity, material indices and run length:
+ * a later call with the same key takes it without timing anything.
+ * tile_x, band_steps: the chosen values, or NULL.  Synchronises.
+ * Errors: FDTD_EUNSUPPORTED for another scheme or when no candidate runs,
+ * FDTD_ENOMEM without room for the copy; the errors of fdtd_step. */
+int fdtd_autotune(fdtd_ctx* ctx, int64_t nsteps, int64_t* tile_x, int64_t* band_steps);
 
 enum {
     FDTD_KERNEL_PLAIN_E = 0,   /* plain E half-step                        */

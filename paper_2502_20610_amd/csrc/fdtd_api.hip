@@ -264,6 +264,8 @@ int grid_for(long long n)
 
 namespace fdtd {
 
+int device_error(fdtd_ctx* ctx) { return check_device_error(ctx); }
+
 int fail(fdtd_ctx* ctx, int code, const std::string& msg)
 {
     if (ctx)
@@ -889,6 +891,13 @@ int fdtd_invariants(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h, i
     return FDTD_OK;
 }
 
+int fdtd_autotune(fdtd_ctx* ctx, int64_t nsteps, int64_t* tile_x, int64_t* band_steps)
+{
+    int rc = check_live(ctx);
+    if (rc) return rc == FDTD_ESTATE ? fail(ctx, rc, "context is poisoned") : rc;
+    return autotune_run(ctx, nsteps, tile_x, band_steps);
+}
+
 int fdtd_invariants_noalloc(fdtd_ctx* ctx, double* sums, double* div_e, double* div_h)
 {
     int rc = check_live(ctx);
@@ -933,6 +942,13 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
     case FDTD_OPT_SPIN_LIMIT:
         if (value < 1) return fail(ctx, FDTD_EINVAL, "set_option: spin limit must be >= 1");
         ctx->spin_limit = value;
+        return FDTD_OK;
+    case FDTD_OPT_TILE_X:
+        if (value != 0 && value != 11 && value != 15)
+            return fail(ctx, FDTD_EINVAL, "set_option: tile width is 0 (default), 11 or 15");
+        if (value == 11 && ctx->storage != FDTD_FP32)
+            return fail(ctx, FDTD_EUNSUPPORTED, "set_option: the 11-wide tile needs FP32 storage");
+        ctx->tile_narrow = value == 11;
         return FDTD_OK;
     case FDTD_OPT_GRAPHS:
         if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: graphs is 0 or 1");

@@ -93,6 +93,7 @@ struct fdtd_ctx {
     float* mat_tab;   // kMaxMaterials x 3 floats, entry 0 = (+0, +0, +0)
     int nmat;
     bool use_mat;     // FDTD_OPT_MATERIAL_IDS
+    bool tile_narrow; // FDTD_OPT_TILE_X = 11 on a lossless FP32 grid
 
     // plain schemes: step loops replayed as a HIP graph (FDTD_OPT_GRAPHS)
     bool use_graphs;
@@ -135,6 +136,12 @@ int systolic_step_batch(fdtd_ctx* const* ctxs, int n, int64_t nsteps);
 int systolic_prepare(fdtd_ctx* ctx, int64_t nsteps);
 void systolic_release(fdtd_ctx* ctx);
 void systolic_tile(const fdtd_ctx* ctx, int* wx, int* wy, int* wz);
+
+// Measured tile width and band length of the systolic scheme (autotune.hip).
+int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* tile_x, int64_t* band_steps);
+// Read the device error word: FDTD_ETIMEOUT (and poison), FDTD_EINVAL for a
+// pending bad-permittivity report (then cleared), else FDTD_OK.  Synchronous.
+int device_error(fdtd_ctx* ctx);
 
 // Reverse-time adjoint of a monitor objective (adjoint.hip).
 int adjoint_run(fdtd_ctx* ctx, fdtd_adjoint_spec* spec, float* grad_eps, int where);

@@ -324,9 +324,11 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     return *s_abort == 0;
 }
 
-template <int NW, bool DEV, bool PER, bool LOSSY, bool F16, bool MAT>
+template <int NW, bool DEV, bool PER, bool LOSSY, bool F16, bool MAT, bool NARROW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void systolic_kernel(SysArgs A)
 {
+    // NARROW: the 11-wide x tile of the conductive variant on a lossless grid
+    static_assert(!(NARROW && (LOSSY || F16)), "narrow tile: lossless FP32 only");
     // MAT: the coefficients enter as per-cell material indices into a table
     // (lossless FP32 grids); the z face still carries the values themselves
     static_assert(!(MAT && (LOSSY || F16)), "material indices: lossless FP32 only");
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     static_assert(PY == 16, "face staging assumes 16 slots on every axis");
     // x slots in registers: 16 (15 updated); with conductivity 12 (11
     // updated), which frees the registers of the per-cell decay ca
-    constexpr int PXk = LOSSY ? WX_LOSSY + 1 : PX;
+    constexpr int PXk = (LOSSY || NARROW) ? WX_LOSSY + 1 : PX;
     constexpr int WXk = PXk - 1;
     // staged components: E, H, cb (cE), and ca with conductivity
     constexpr int NQA = LOSSY ? 12 : 9;
@@ -1151,7 +1153,11 @@ void free_launch(SystolicState* s)
 
 // updated cells along x of a tile of this context: conductive grids use the
 // narrower register tile that leaves room for the per-cell decay
-int tile_x(const fdtd_ctx* c) { return c->ca[0] ? WX_LOSSY : WX; }
+// (a lossless FP32 context may ask for the narrow tile too: FDTD_OPT_TILE_X)
+int tile_x(const fdtd_ctx* c)
+{
+    return (c->ca[0] || (c->tile_narrow && c->storage == FDTD_FP32)) ? WX_LOSSY : WX;
+}
 
 void tile_of(const fdtd_ctx* c, int W[3])
 {
@@ -1308,6 +1314,8 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
             return fail(lead, FDTD_EUNSUPPORTED, "systolic batch: conductive and lossless grids cannot share a launch");
         if ((cs[i]->storage == FDTD_FP16_STORAGE) != h16)
             return fail(lead, FDTD_EUNSUPPORTED, "systolic batch: FP32 and FP16 storage cannot share a launch");
+        if (tile_x(cs[i]) != tile_x(lead))
+            return fail(lead, FDTD_EUNSUPPORTED, "systolic batch: every member needs the same tile width");
     }
     // band length per simulation: the lead's option for all, else each
     // simulation's own choice of the cost model
@@ -1339,18 +1347,28 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     // material indices when every member has them (and allows them)
     bool mat = !lossy && !h16;
     for (int i = 0; i < n && mat; ++i) mat = cs[i]->use_mat && cs[i]->nmat > 0 && cs[i]->mat_id;
-    // variants: [sync][periodic][FP32, conductive, FP16 storage, FP32 with material indices]
+    // the narrow tile on a lossless FP32 grid (every member shares the width)
+    const bool narrow = !lossy && !h16 && tile_x(lead) == WX_LOSSY;
+    // variants: [sync][periodic][FP32, conductive, FP16 storage, FP32 with
+    // material indices, and the last two with the narrow tile (device-scope
+    // synchronisation only)]
     using Kern = void (*)(SysArgs);
-    static const Kern kernels[2][2][4] = {
-        {{systolic_kernel<kNW, false, false, false, false, false>, systolic_kernel<kNW, false, false, true, false, false>,
-          systolic_kernel<kNW, false, false, false, true, false>, systolic_kernel<kNW, false, false, false, false, true>},
-         {systolic_kernel<kNW, false, true, false, false, false>, systolic_kernel<kNW, false, true, true, false, false>,
-          systolic_kernel<kNW, false, true, false, true, false>, systolic_kernel<kNW, false, true, false, false, true>}},
-        {{systolic_kernel<kNW, true, false, false, false, false>, systolic_kernel<kNW, true, false, true, false, false>,
-          systolic_kernel<kNW, true, false, false, true, false>, systolic_kernel<kNW, true, false, false, false, true>},
-         {systolic_kernel<kNW, true, true, false, false, false>, systolic_kernel<kNW, true, true, true, false, false>,
-          systolic_kernel<kNW, true, true, false, true, false>, systolic_kernel<kNW, true, true, false, false, true>}}};
-    const Kern kern = kernels[dev][anyper][h16 ? 2 : (lossy ? 1 : (mat ? 3 : 0))];
+    static const Kern kernels[2][2][6] = {
+        {{systolic_kernel<kNW, false, false, false, false, false, false>, systolic_kernel<kNW, false, false, true, false, false, false>,
+          systolic_kernel<kNW, false, false, false, true, false, false>, systolic_kernel<kNW, false, false, false, false, true, false>,
+          nullptr, nullptr},
+         {systolic_kernel<kNW, false, true, false, false, false, false>, systolic_kernel<kNW, false, true, true, false, false, false>,
+          systolic_kernel<kNW, false, true, false, true, false, false>, systolic_kernel<kNW, false, true, false, false, true, false>,
+          nullptr, nullptr}},
+        {{systolic_kernel<kNW, true, false, false, false, false, false>, systolic_kernel<kNW, true, false, true, false, false, false>,
+          systolic_kernel<kNW, true, false, false, true, false, false>, systolic_kernel<kNW, true, false, false, false, true, false>,
+          systolic_kernel<kNW, true, false, false, false, false, true>, systolic_kernel<kNW, true, false, false, false, true, true>},
+         {systolic_kernel<kNW, true, true, false, false, false, false>, systolic_kernel<kNW, true, true, true, false, false, false>,
+          systolic_kernel<kNW, true, true, false, true, false, false>, systolic_kernel<kNW, true, true, false, false, true, false>,
+          systolic_kernel<kNW, true, true, false, false, false, true>, systolic_kernel<kNW, true, true, false, false, true, true>}}};
+    const int var = h16 ? 2 : (lossy ? 1 : (mat ? 3 : 0)) + (narrow ? (mat ? 2 : 4) : 0);
+    const Kern kern = kernels[dev][anyper][var];
+    if (!kern) return fail(lead, FDTD_EUNSUPPORTED, "systolic: the narrow tile needs device-scope synchronisation");
     hipError_t e;
     if (L->sm_count == 0) {
         hipDeviceProp_t prop;

@@ -28,7 +28,7 @@ SCHEME_PLAIN, SCHEME_SYSTOLIC, SCHEME_PLAIN_FUSED = 0, 1, 2
 FP32, FP16_STORAGE = 0, 1
 HOST, DEVICE = 0, 1
 (OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_MATERIAL_IDS,
- OPT_GRAPHS) = range(7)
+ OPT_GRAPHS, OPT_TILE_X) = range(8)
 KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC, KERNEL_PLAIN_FUSED = range(5)
 (INFO_SYSTOLIC_GRID, INFO_SYSTOLIC_BAND, INFO_SYSTOLIC_TICKETS, INFO_RING_SLOTS, INFO_TILE_X,
  INFO_TILE_Y, INFO_TILE_Z, INFO_MATERIALS) = range(8)
@@ -43,7 +43,7 @@ EXPORTS = ("fdtd_create", "fdtd_destroy", "fdtd_set_materials", "fdtd_set_lossy_
            "fdtd_add_source", "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_synchronize",
            "fdtd_current_step", "fdtd_last_error", "fdtd_adjoint", "fdtd_set_option",
            "fdtd_kernel_stats", "fdtd_get_info", "fdtd_set_field_scale", "fdtd_invariants",
-           "fdtd_invariants_noalloc",
+           "fdtd_invariants_noalloc", "fdtd_autotune",
            "fdtd_prepare")
 
 
@@ -114,6 +114,7 @@ def load_library():
         "fdtd_set_field_scale": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "fdtd_invariants": ([vp, vp, vp, vp, ctypes.c_int], ctypes.c_int),
         "fdtd_invariants_noalloc": ([vp, vp, vp, vp], ctypes.c_int),
+        "fdtd_autotune": ([vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
         "fdtd_prepare": ([vp, i64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -316,6 +317,13 @@ class Simulation:
         if per_cell:
             return out, de, dh
         return out
+
+    def autotune(self, nsteps: int):
+        """fdtd_autotune: time the systolic tile widths and band lengths for
+        calls of ``nsteps`` steps and keep the fastest; returns (tile_x, band)."""
+        w, k = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.fdtd_autotune(self._h, int(nsteps), ctypes.byref(w), ctypes.byref(k)))
+        return int(w.value), int(k.value)
 
     def invariants_noalloc(self, sums, div_e=None, div_h=None):
         """fdtd_invariants_noalloc: the invariants into torch float64 CUDA

@@ -1,0 +1,106 @@
+"""The 11-wide systolic tile on lossless grids and the measured choice of tile
+width and band length (fdtd_autotune).
+
+* FDTD_OPT_TILE_X = 11 runs the lossless update on the narrow tile: bitwise
+  with the FP32 oracle on PEC, periodic and mixed boundaries (ragged periodic
+  rings of 11-wide tiles), with material indices and with the arrays.
+* fdtd_autotune leaves the fields and the step count as they were, returns a
+  candidate pair, keeps it for a second context of the same key, and the run
+  that follows stays bitwise.
+* Refusals: the narrow tile with FP16 storage, a batch mixing widths.
+"""
+import numpy as np
+import pytest
+
+from paper_2502_20610_amd import fdtd
+from paper_2502_20610_amd import workloads as wl
+from tests.test_gpu_parity import assert_bitwise, oracle_f32
+
+pytestmark = pytest.mark.gpu
+
+PEC, PER = 0, 1
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+if not _gpu_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _sim(w, opts=()):
+    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic")
+    for k, v in opts:
+        sim.set_option(k, v)
+    sim.set_materials(w.eps)
+    sim.set_fields(w.fields)
+    for s in w.sources:
+        sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+    return sim
+
+
+@pytest.mark.parametrize("bc,shape", [((PEC, PEC, PEC), (45, 37, 41)), ((PER, PER, PEC), (40, 34, 31)),
+                                      ((PER, PEC, PER), (23, 30, 33)), ((PER, PER, PER), (35, 32, 17))])
+@pytest.mark.parametrize("ids", [1, 0])
+def test_narrow_tile_bitwise(bc, shape, ids):
+    w = wl.small_case(shape, bc, seed=71 + shape[0], nsteps=23, dipoles=[tuple(n // 2 for n in shape)])
+    sim = _sim(w, [(fdtd.OPT_TILE_X, 11), (fdtd.OPT_MATERIAL_IDS, ids), (fdtd.OPT_BAND_STEPS, 8)])
+    try:
+        sim.step(23)
+        assert sim.info(fdtd.INFO_TILE_X) == 11
+        assert_bitwise(sim.read_fields(), oracle_f32(w), "narrow tile %s ids=%d" % (bc, ids))
+    finally:
+        sim.close()
+
+
+def test_autotune_restores_state_and_keeps_its_choice():
+    w = wl.small_case((52, 47, 44), (PEC, PEC, PEC), seed=5, nsteps=30, dipoles=[(26, 23, 22)])
+    sim = _sim(w)
+    try:
+        sim.step(7)
+        before = sim.read_fields()
+        tile, band = sim.autotune(23)
+        assert tile in (11, 15) and band in (8, 12, 16, 23)
+        assert sim.current_step == 7
+        assert_bitwise(sim.read_fields(), before, "state after autotune")
+        sim.step(23)
+        assert sim.info(fdtd.INFO_TILE_X) == tile and sim.info(fdtd.INFO_SYSTOLIC_BAND) == band
+        assert_bitwise(sim.read_fields(), oracle_f32(w, 30), "run after autotune")
+    finally:
+        sim.close()
+    other = _sim(w)
+    try:
+        assert other.autotune(23) == (tile, band)     # kept for the same key
+    finally:
+        other.close()
+
+
+def test_autotune_refusals_and_narrow_tile_refusals():
+    w = wl.small_case((24, 24, 24), (PEC, PEC, PEC), seed=2, nsteps=4)
+    plain = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="plain")
+    try:
+        with pytest.raises(fdtd.FdtdError) as e:
+            plain.autotune(10)
+        assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+    finally:
+        plain.close()
+    h = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic", storage="fp16")
+    try:
+        with pytest.raises(fdtd.FdtdError) as e:
+            h.set_option(fdtd.OPT_TILE_X, 11)
+        assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+    finally:
+        h.close()
+    a, b = _sim(w, [(fdtd.OPT_TILE_X, 11)]), _sim(w)
+    try:
+        with pytest.raises(fdtd.FdtdError) as e:
+            fdtd.step_batch([a, b], 4)
+        assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+    finally:
+        a.close()
+        b.close()

@@ -11,9 +11,9 @@
 // The distinct triples are found on the device in rounds.  Each round
 // classifies every cell against the triples known so far (a hash table in
 // LDS, keyed on the three bit patterns); cells that match get their index,
-// and up to kCand cells that do not report their triple.  The host adds the
-// new triples and runs another round until every cell matches, or gives up
-// once there are more than kMaxMaterials.  Entry 0 is always (+0, +0, +0):
+// and unmatched triples are reported, up to kCand distinct ones per round.
+// The host adds the new triples and runs another round until every cell
+// matches, or gives up once there are more than kMaxMaterials.  Entry 0 is always (+0, +0, +0):
 // the value that positions outside the grid read.
 #include <string.h>
 
@@ -39,8 +39,12 @@ __host__ __device__ inline unsigned slot_of(unsigned a, unsigned b, unsigned c)
 }
 
 // keys: kSlots x 3 words (the triple's bits), idx: kSlots entries (-1 empty).
-// cand[0] counts unmatched cells; cand[1 + 3 i ..] holds the first kCand
-// unmatched triples.
+// Cells that match get their index.  Unmatched triples are reported into a
+// table of kCand slots keyed by a hash of the triple: each wavefront reports
+// up to four distinct triples per launch (one atomic compare-and-swap each,
+// no waiting), so a round finds up to kCand new triples; cand[0] is set when
+// any cell did not match.  cand layout: [0] flag, [1 .. kCand] slot keys,
+// then kCand triples.
 __global__ __launch_bounds__(kThreads) void classify_kernel(const float* __restrict__ c0,
                                                             const float* __restrict__ c1,
                                                             const float* __restrict__ c2, long long n,
@@ -58,31 +62,49 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const float* __restr
         s_idx[i] = idx[i];
     }
     __syncthreads();
-    for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < n;
-         p += (long long)gridDim.x * kThreads) {
-        const unsigned a = __float_as_uint(c0[p]), b = __float_as_uint(c1[p]), c = __float_as_uint(c2[p]);
-        unsigned s = slot_of(a, b, c);
+    int reports = 0;  // wave-uniform: distinct triples this wavefront reported
+    const long long nr = (n + kThreads - 1) / kThreads * kThreads;  // every lane runs every pass
+    for (long long p0 = (long long)blockIdx.x * kThreads; p0 < nr; p0 += (long long)gridDim.x * kThreads) {
+        const long long p = p0 + threadIdx.x;
+        const bool in = p < n;
+        unsigned a = 0, b = 0, c = 0;
         int found = -1;
-        // the table is at most a quarter full, so an empty slot ends every probe
-        for (int probe = 0; probe < kSlots; ++probe) {
-            const int id = s_idx[s];
-            if (id < 0) break;
-            if (s_key[s][0] == a && s_key[s][1] == b && s_key[s][2] == c) {
-                found = id;
-                break;
+        if (in) {
+            a = __float_as_uint(c0[p]);
+            b = __float_as_uint(c1[p]);
+            c = __float_as_uint(c2[p]);
+            unsigned s = slot_of(a, b, c);
+            // the table is at most a quarter full, so an empty slot ends every probe
+            for (int probe = 0; probe < kSlots; ++probe) {
+                const int id = s_idx[s];
+                if (id < 0) break;
+                if (s_key[s][0] == a && s_key[s][1] == b && s_key[s][2] == c) {
+                    found = id;
+                    break;
+                }
+                s = (s + 1) & (kSlots - 1);
             }
-            s = (s + 1) & (kSlots - 1);
+            ids[p] = found >= 0 ? (unsigned)found : 0u;
         }
-        if (found >= 0) {
-            ids[p] = (unsigned)found;
-        } else {
-            ids[p] = 0u;
-            const unsigned q = atomicAdd(cand, 1u);
-            if (q < (unsigned)kCand) {
-                cand[1 + 3 * q] = a;
-                cand[2 + 3 * q] = b;
-                cand[3 + 3 * q] = c;
+        unsigned long long miss = __ballot(in && found < 0);
+        if (miss && (threadIdx.x & 63) == __ffsll((long long)miss) - 1) cand[0] = 1u;
+        while (miss && reports < 4) {
+            const int lead = __ffsll((long long)miss) - 1;
+            const unsigned ta = __shfl(a, lead, 64), tb = __shfl(b, lead, 64), tc = __shfl(c, lead, 64);
+            if ((int)(threadIdx.x & 63) == lead) {
+                const unsigned h = (slot_of(ta, tb, tc) * 0x9E3779B9u) | 1u;  // never 0 (free)
+                const unsigned q = h % (unsigned)kCand;
+                const unsigned prev = atomicCAS(&cand[1 + q], 0u, h);
+                if (prev == 0u) {
+                    unsigned* t = cand + 1 + kCand + 3 * q;
+                    t[0] = ta;
+                    t[1] = tb;
+                    t[2] = tc;
+                }
             }
+            // lanes holding the same triple are covered by that report
+            miss &= __ballot(!(a == ta && b == tb && c == tc));
+            ++reports;
         }
     }
 }
@@ -122,7 +144,8 @@ int build_material_ids(fdtd_ctx* ctx)
     unsigned* d_keys = nullptr;
     int* d_idx = nullptr;
     unsigned* d_cand = nullptr;
-    const size_t scratch = kSlots * 3 * sizeof(unsigned) + kSlots * sizeof(int) + (1 + 3 * kCand) * sizeof(unsigned);
+    const size_t ncand = 1 + kCand + 3 * kCand;  // flag, slot keys, triples
+    const size_t scratch = kSlots * 3 * sizeof(unsigned) + kSlots * sizeof(int) + ncand * sizeof(unsigned);
     char* d_scratch = nullptr;
     if ((e = hipMalloc(&d_scratch, scratch)) != hipSuccess) {
         (void)hipGetLastError();
@@ -133,7 +156,8 @@ int build_material_ids(fdtd_ctx* ctx)
     d_cand = (unsigned*)(d_idx + kSlots);
 
     std::vector<unsigned> tab(3, 0u);  // entry 0: (+0, +0, +0)
-    std::vector<unsigned> keys(kSlots * 3), cand(1 + 3 * kCand);
+    std::vector<unsigned> keys(kSlots * 3), cand(ncand);
+    const std::vector<unsigned> cand0(ncand, 0u);
     std::vector<int> idx(kSlots);
     bool ok = false;
     e = hipSuccess;
@@ -147,12 +171,12 @@ int build_material_ids(fdtd_ctx* ctx)
             idx[s] = m;
             for (int q = 0; q < 3; ++q) keys[3 * s + q] = tab[3 * m + q];
         }
-        unsigned zero = 0;
         if ((e = hipMemcpyAsync(d_keys, keys.data(), keys.size() * sizeof(unsigned), hipMemcpyHostToDevice,
                                 ctx->stream)) != hipSuccess ||
             (e = hipMemcpyAsync(d_idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream)) !=
                 hipSuccess ||
-            (e = hipMemcpyAsync(d_cand, &zero, sizeof(unsigned), hipMemcpyHostToDevice, ctx->stream)) != hipSuccess)
+            (e = hipMemcpyAsync(d_cand, cand0.data(), ncand * sizeof(unsigned), hipMemcpyHostToDevice,
+                                ctx->stream)) != hipSuccess)
             break;
         hipLaunchKernelGGL(classify_kernel, dim3(grid_blocks(ctx->ncell)), dim3(kThreads), 0, ctx->stream,
                            ctx->coef[0], ctx->coef[1], ctx->coef[2], (long long)ctx->ncell, d_keys, d_idx,
@@ -166,13 +190,13 @@ int build_material_ids(fdtd_ctx* ctx)
             ok = true;
             break;
         }
-        const int nc = (int)std::min<unsigned>(cand[0], kCand);
-        for (int i = 0; i < nc && (int)tab.size() / 3 <= kMaxMaterials; ++i) {
+        for (int i = 0; i < kCand && (int)tab.size() / 3 <= kMaxMaterials; ++i) {
+            if (cand[1 + i] == 0) continue;  // slot not claimed
+            const unsigned* t = &cand[1 + kCand + 3 * i];
             bool have = false;
             for (size_t m = 0; m < tab.size() / 3 && !have; ++m)
-                have = tab[3 * m] == cand[1 + 3 * i] && tab[3 * m + 1] == cand[2 + 3 * i] &&
-                       tab[3 * m + 2] == cand[3 + 3 * i];
-            if (!have) tab.insert(tab.end(), &cand[1 + 3 * i], &cand[4 + 3 * i]);
+                have = tab[3 * m] == t[0] && tab[3 * m + 1] == t[1] && tab[3 * m + 2] == t[2];
+            if (!have) tab.insert(tab.end(), t, t + 3);
         }
         if ((int)tab.size() / 3 > kMaxMaterials) break;  // too many: the per-cell arrays serve
     }

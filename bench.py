@@ -304,7 +304,10 @@ def batch_bench(nsims: int, steps: int, dims=(64, 192)):
     from paper_2502_20610_amd import workloads as wl
     ws = wl.c4_batch(nsims, steps, dims=dims)
     cells = sum(w.cells for w in ws)
-    stream = torch.cuda.current_stream()
+    # one stream for every context of every mode, so that per-grid launches
+    # really run back to back (a null handle would give each context a
+    # stream of its own, and their launches would overlap)
+    stream = torch.cuda.Stream()
     dev = torch.device("cuda:0")
 
     def make(scheme):

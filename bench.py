@@ -84,8 +84,10 @@ def systolic_bytes_per_update(tile, band, conductive=False, fp16=False, material
     axy, v = wx * wy, wx * wy * wz
     c = 24 if conductive else 12            # coefficient bytes per cell (FP32)
     if materials:
+        # (the faces travel in FP32 whatever the storage; the band's state is
+        # E and H in the stored format and the index)
         per_step = (wy * wz + wx * wz) * (24 + 4 + 24) + axy * (24 + c) * 2
-        return per_step / v + (2 * 24 + 4) / band
+        return per_step / v + (2 * (12 if fp16 else 24) + 4) / band
     if fp16:
         per_step = (wy * wz + wx * wz + axy) * (24 + c) * 2
         band_bytes = 2 * 12 + 6
@@ -132,7 +134,7 @@ def make_workload(name: str):
 
 
 def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None, storage="fp32",
-               autotune=False):
+               autotune=False, profile=True):
     """scheme: "systolic", "plain", "plain_fused", or "systolic_arrays" (the
     systolic scheme streaming the per-cell coefficient arrays instead of the
     material indices)."""
@@ -168,16 +170,19 @@ def run_scheme(w, scheme: str, steps: int, warmup: int, options=None, sigma=None
         # rings, the fused step's second field set) outside the timed region
         sim.prepare(steps)
         sim.synchronize()
-        sim.set_option(fdtd.OPT_PROFILE, 1)
+        # per-kernel HIP-event timing (the plain schemes then launch every
+        # kernel directly instead of replaying their step graphs)
+        if profile:
+            sim.set_option(fdtd.OPT_PROFILE, 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.step(steps)
         sim.synchronize()
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        stats = {k: sim.kernel_stats(k) for k in (fdtd.KERNEL_PLAIN_E, fdtd.KERNEL_PLAIN_H,
-                                                   fdtd.KERNEL_SOURCES, fdtd.KERNEL_SYSTOLIC,
-                                                   fdtd.KERNEL_PLAIN_FUSED)}
+        stats = {k: (sim.kernel_stats(k) if profile else (0, 0.0))
+                 for k in (fdtd.KERNEL_PLAIN_E, fdtd.KERNEL_PLAIN_H, fdtd.KERNEL_SOURCES,
+                           fdtd.KERNEL_SYSTOLIC, fdtd.KERNEL_PLAIN_FUSED)}
         if scheme == "systolic":
             stats["info"] = {"materials": sim.info(fdtd.INFO_MATERIALS) if options.get(
                                  fdtd.OPT_MATERIAL_IDS, 1) else 0,
@@ -280,7 +285,8 @@ def sweep(args):
             if scheme == "systolic" and args.band:
                 opts[fdtd.OPT_BAND_STEPS] = args.band
             try:
-                t, _ = run_scheme(w, scheme, steps, 32, opts)
+                # wall clock only: no per-kernel events (the plain schemes replay graphs)
+                t, _ = run_scheme(w, scheme, steps, 32, opts, profile=False)
             except fdtd.FdtdError as e:
                 row[scheme] = None
                 log("n=%d %s unavailable: %s" % (n, scheme, e))

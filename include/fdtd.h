@@ -129,12 +129,13 @@ int fdtd_destroy(fdtd_ctx* ctx);
  * device and reported at the next synchronising call).  The library
  * computes cE_c = (float)(dt / ((double)eps_c * dx)) and zeroes it on the
  * index-0 planes of PEC axes tangential to component c.  The arrays are
- * copied; the caller keeps ownership.  With FP32 storage the library also
- * looks for the distinct triples (cEx, cEy, cEz) of the grid (on the device,
- * a few passes over the coefficients, synchronising the stream): with at
- * most 256 of them (entry 0 being (+0, +0, +0)) it keeps a 4-byte material
- * index per cell, which the systolic scheme streams in place of the three
- * coefficients (the bits it multiplies by are the same). */
+ * copied; the caller keeps ownership.  The library also looks for the
+ * distinct triples (cEx, cEy, cEz) of the grid (on the device, a few passes
+ * over the coefficients, synchronising the stream; with FP16 storage the
+ * triples of their binary16 values): with at most 256 of them (entry 0
+ * being (+0, +0, +0)) it keeps a 4-byte material index per cell, which the
+ * systolic scheme streams in place of the three coefficients (the bits it
+ * multiplies by are the same). */
 int fdtd_set_materials(fdtd_ctx* ctx, const float* eps_x, const float* eps_y,
                        const float* eps_z, int where);
 
@@ -438,8 +439,8 @@ enum {
     FDTD_INFO_TILE_Y = 5,
     FDTD_INFO_TILE_Z = 6,
     FDTD_INFO_MATERIALS = 7        /* entries of the context's material table, entry 0 */
-                                   /* (+0, +0, +0) included; 0 = none (conductive or   */
-                                   /* FP16 storage, or more than 256 distinct triples)  */
+                                   /* (+0, +0, +0) included; 0 = none (conductive, or  */
+                                   /* more than 256 distinct triples)                   */
 };
 
 /* Read a piece of launch information (FDTD_INFO_*) into *value; 0 before the

@@ -86,7 +86,7 @@ struct fdtd_ctx {
 
     double* inv_scratch;  // partial sums of fdtd_invariants (allocated on first use)
 
-    // material indices (lossless FP32 grids with at most kMaxMaterials
+    // material indices (lossless grids with at most kMaxMaterials
     // distinct coefficient triples): per-cell index into a table of
     // (cEx, cEy, cEz); nmat = 0 when the per-cell arrays are the only form
     uint32_t* mat_id;
@@ -166,9 +166,10 @@ int invariants_scratch_init(int device);
 double* invariants_scratch_ptr(int device);
 
 // Material indices (materials.hip): find the distinct coefficient triples
-// of a lossless FP32 context after its coefficients were built; leaves
-// nmat = 0 when there are more than kMaxMaterials (or the context is
-// conductive or stores FP16).  release_material_ids frees them.
+// of a lossless context after its coefficients were built (FP32 values; the
+// exact FP32 values of binary16 ones with FP16 storage); leaves nmat = 0
+// when there are more than kMaxMaterials (or the context is conductive).
+// release_material_ids frees them.
 constexpr int kMaxMaterials = 256;
 int build_material_ids(fdtd_ctx* ctx);
 void release_material_ids(fdtd_ctx* ctx);

@@ -4,9 +4,11 @@
 // (the structural fields of Section 4).  Grids built from a few materials
 // (boxes of a few permittivities, PEC walls) hold only a few distinct
 // triples (cEx, cEy, cEz) per cell.  The systolic scheme then streams a
-// 4-byte index per cell instead of the 12 bytes of the triple and looks the
-// triple up in a table of at most kMaxMaterials entries: the coefficient
-// values, and so every result, are the same bits as with the arrays.
+// 4-byte index per cell instead of the triple (12 bytes, or the 6 of
+// binary16 with FP16 storage, which also had to travel on face rings) and
+// looks the triple up in a table of at most kMaxMaterials entries: the
+// coefficient values, and so every result, are the same bits as with the
+// arrays.
 //
 // The distinct triples are found on the device in rounds.  Each round
 // classifies every cell against the triples known so far (a hash table in
@@ -45,9 +47,12 @@ __host__ __device__ inline unsigned slot_of(unsigned a, unsigned b, unsigned c)
 // no waiting), so a round finds up to kCand new triples; cand[0] is set when
 // any cell did not match.  cand layout: [0] flag, [1 .. kCand] slot keys,
 // then kCand triples.
-__global__ __launch_bounds__(kThreads) void classify_kernel(const float* __restrict__ c0,
-                                                            const float* __restrict__ c1,
-                                                            const float* __restrict__ c2, long long n,
+// With H16 the coefficients are binary16 (FP16 storage) and the triple is
+// that of their exact FP32 values.
+template <bool H16>
+__global__ __launch_bounds__(kThreads) void classify_kernel(const void* __restrict__ c0v,
+                                                            const void* __restrict__ c1v,
+                                                            const void* __restrict__ c2v, long long n,
                                                             const unsigned* __restrict__ keys,
                                                             const int* __restrict__ idx,
                                                             unsigned* __restrict__ ids,
@@ -55,6 +60,10 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const float* __restr
 {
     __shared__ unsigned s_key[kSlots][3];
     __shared__ int s_idx[kSlots];
+    auto bits = [&](const void* base, long long p) -> unsigned {
+        if (H16) return __float_as_uint((float)__builtin_bit_cast(_Float16, ((const uint16_t*)base)[p]));
+        return __float_as_uint(((const float*)base)[p]);
+    };
     for (int i = threadIdx.x; i < kSlots; i += kThreads) {
         s_key[i][0] = keys[3 * i];
         s_key[i][1] = keys[3 * i + 1];
@@ -70,9 +79,9 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const float* __restr
         unsigned a = 0, b = 0, c = 0;
         int found = -1;
         if (in) {
-            a = __float_as_uint(c0[p]);
-            b = __float_as_uint(c1[p]);
-            c = __float_as_uint(c2[p]);
+            a = bits(c0v, p);
+            b = bits(c1v, p);
+            c = bits(c2v, p);
             unsigned s = slot_of(a, b, c);
             // the table is at most a quarter full, so an empty slot ends every probe
             for (int probe = 0; probe < kSlots; ++probe) {
@@ -129,7 +138,7 @@ void release_material_ids(fdtd_ctx* ctx)
 int build_material_ids(fdtd_ctx* ctx)
 {
     ctx->nmat = 0;
-    if (ctx->storage != FDTD_FP32 || ctx->ca[0]) return FDTD_OK;  // lossless FP32 grids only
+    if (ctx->ca[0]) return FDTD_OK;  // lossless grids only
     hipError_t e;
     if (!ctx->mat_id && (e = hipMalloc(&ctx->mat_id, (size_t)ctx->ncell * sizeof(unsigned))) != hipSuccess) {
         (void)hipGetLastError();
@@ -178,9 +187,12 @@ int build_material_ids(fdtd_ctx* ctx)
             (e = hipMemcpyAsync(d_cand, cand0.data(), ncand * sizeof(unsigned), hipMemcpyHostToDevice,
                                 ctx->stream)) != hipSuccess)
             break;
-        hipLaunchKernelGGL(classify_kernel, dim3(grid_blocks(ctx->ncell)), dim3(kThreads), 0, ctx->stream,
-                           ctx->coef[0], ctx->coef[1], ctx->coef[2], (long long)ctx->ncell, d_keys, d_idx,
-                           ctx->mat_id, d_cand);
+        const bool h16 = ctx->storage == FDTD_FP16_STORAGE;
+        const void* cs[3];
+        for (int q = 0; q < 3; ++q) cs[q] = h16 ? (const void*)ctx->coef16[q] : (const void*)ctx->coef[q];
+        hipLaunchKernelGGL(h16 ? classify_kernel<true> : classify_kernel<false>, dim3(grid_blocks(ctx->ncell)),
+                           dim3(kThreads), 0, ctx->stream, cs[0], cs[1], cs[2], (long long)ctx->ncell, d_keys,
+                           d_idx, ctx->mat_id, d_cand);
         if ((e = hipGetLastError()) != hipSuccess) break;
         if ((e = hipMemcpyAsync(cand.data(), d_cand, cand.size() * sizeof(unsigned), hipMemcpyDeviceToHost,
                                 ctx->stream)) != hipSuccess ||

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     static_assert(!(NARROW && (LOSSY || F16)), "narrow tile: lossless FP32 only");
     // MAT: the coefficients enter as per-cell material indices into a table
     // (lossless FP32 grids); the z face still carries the values themselves
-    static_assert(!(MAT && (LOSSY || F16)), "material indices: lossless FP32 only");
+    static_assert(!(MAT && LOSSY), "material indices: lossless grids only");
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
     constexpr int PY = 4 * NW;
     constexpr int WY = PY - 1;
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     __shared__ __attribute__((aligned(16))) float zst[NQA][PY][LS];
     // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
     // (with FP16 storage the y face carries the coefficients as well)
-    constexpr int NQY = F16 ? 9 : 6;
+    constexpr int NQY = (F16 && !MAT) ? 9 : 6;
     __shared__ float ytr[NQY][LS][PZ];
     __shared__ __attribute__((aligned(16))) float ztr[NQA][PY][LS];
     __shared__ int s_ticket;
@@ -442,7 +442,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
         for (int q = 0; q < 3; ++q) rc[q] = make_rsrc((const char*)P.cE[q] + ebase * ES, rbytes);
         __amdgpu_buffer_rsrc_t rid;
-        if (MAT) rid = make_rsrc((const char*)P.mid + ebase * 4ull, rbytes);
+        if (MAT)
+            rid = make_rsrc((const char*)P.mid + ebase * 4ull,
+                            (unsigned)min(((unsigned long long)P.nx * plane - ebase) * 4ull, 0xFFFFFF00ull));
         __amdgpu_buffer_rsrc_t rca[3];
         if (LOSSY) {
 #pragma unroll
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     if (F16) {
                         E[q][j] = bld16<SP>(rf[q], off) * P.sc[q];
                         H[q][j] = bld16<SP>(rf[3 + q], off) * P.sc[3 + q];
-                        C[q][j] = bld16<0>(rc[q], off);
+                        if (!MAT) C[q][j] = bld16<0>(rc[q], off);
                     } else {
                         E[q][j] = bld<SP>(rf[q], off);
                         H[q][j] = bld<SP>(rf[3 + q], off);
@@ -615,8 +617,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     if (LOSSY) CA[q][j] = bld<0>(rca[q], off);
                 }
                 if (MAT) {
-                    // (an index out of the grid reads 0: the (+0, +0, +0) entry)
-                    const unsigned id = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rid, (int)off, 0, 0) &
+                    // (an index out of the grid reads 0: the (+0, +0, +0) entry; the
+                    // index array holds 4 bytes per cell whatever the field storage)
+                    const unsigned ioff = (F16 && off != kOOB) ? off * 2u : off;
+                    const unsigned id = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rid, (int)ioff, 0, 0) &
                                         (unsigned)(kMaxMaterials - 1);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) C[q][j] = s_tab[3 * id + q];
@@ -954,7 +958,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 // H (and, on the z face, the coefficients) of the first layer
 #pragma unroll
                 for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)(3 + q) * cb : kOOB, H[q][0]);
-                if (F16) {
+                if (F16 && !MAT) {
                     const unsigned oxc_ = (sls * step_c3 + (unsigned)dy * LS + (unsigned)dz) * 4u;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) bst<SP>(rrxc, has_xc ? oxc_ + (unsigned)q * cb : kOOB, C[q][0]);
@@ -965,7 +969,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
                             ytr[3 + q][j][zs] = H[q][j];
-                            if (F16) ytr[6 + q][j][zs] = C[q][j];
+                            if (F16 && !MAT) ytr[6 + q][j][zs] = C[q][j];
                         }
                 }
                 if (dz == 1) {
@@ -1345,28 +1349,33 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
     const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
     // material indices when every member has them (and allows them)
-    bool mat = !lossy && !h16;
+    bool mat = !lossy;
     for (int i = 0; i < n && mat; ++i) mat = cs[i]->use_mat && cs[i]->nmat > 0 && cs[i]->mat_id;
     // the narrow tile on a lossless FP32 grid (every member shares the width)
     const bool narrow = !lossy && !h16 && tile_x(lead) == WX_LOSSY;
     // variants: [sync][periodic][FP32, conductive, FP16 storage, FP32 with
-    // material indices, and the last two with the narrow tile (device-scope
-    // synchronisation only)]
+    // material indices, the last two with the narrow tile, FP16 storage with
+    // material indices (the last three: device-scope synchronisation only)]
     using Kern = void (*)(SysArgs);
-    static const Kern kernels[2][2][6] = {
+    static const Kern kernels[2][2][7] = {
         {{systolic_kernel<kNW, false, false, false, false, false, false>, systolic_kernel<kNW, false, false, true, false, false, false>,
           systolic_kernel<kNW, false, false, false, true, false, false>, systolic_kernel<kNW, false, false, false, false, true, false>,
-          nullptr, nullptr},
+          nullptr, nullptr, nullptr},
          {systolic_kernel<kNW, false, true, false, false, false, false>, systolic_kernel<kNW, false, true, true, false, false, false>,
           systolic_kernel<kNW, false, true, false, true, false, false>, systolic_kernel<kNW, false, true, false, false, true, false>,
-          nullptr, nullptr}},
+          nullptr, nullptr, nullptr}},
         {{systolic_kernel<kNW, true, false, false, false, false, false>, systolic_kernel<kNW, true, false, true, false, false, false>,
           systolic_kernel<kNW, true, false, false, true, false, false>, systolic_kernel<kNW, true, false, false, false, true, false>,
-          systolic_kernel<kNW, true, false, false, false, false, true>, systolic_kernel<kNW, true, false, false, false, true, true>},
+          systolic_kernel<kNW, true, false, false, false, false, true>, systolic_kernel<kNW, true, false, false, false, true, true>,
+          systolic_kernel<kNW, true, false, false, true, true, false>},
          {systolic_kernel<kNW, true, true, false, false, false, false>, systolic_kernel<kNW, true, true, true, false, false, false>,
           systolic_kernel<kNW, true, true, false, true, false, false>, systolic_kernel<kNW, true, true, false, false, true, false>,
-          systolic_kernel<kNW, true, true, false, false, false, true>, systolic_kernel<kNW, true, true, false, false, true, true>}}};
-    const int var = h16 ? 2 : (lossy ? 1 : (mat ? 3 : 0)) + (narrow ? (mat ? 2 : 4) : 0);
+          systolic_kernel<kNW, true, true, false, false, false, true>, systolic_kernel<kNW, true, true, false, false, true, true>,
+          systolic_kernel<kNW, true, true, false, true, true, false>}}};
+    // (FP16 storage with material indices: device-scope synchronisation only;
+    // the fence variant streams the binary16 coefficients)
+    if (h16 && !dev) mat = false;
+    const int var = h16 ? (mat ? 6 : 2) : (lossy ? 1 : (mat ? 3 : 0)) + (narrow ? (mat ? 2 : 4) : 0);
     const Kern kern = kernels[dev][anyper][var];
     if (!kern) return fail(lead, FDTD_EUNSUPPORTED, "systolic: the narrow tile needs device-scope synchronisation");
     hipError_t e;
@@ -1400,7 +1409,9 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     const size_t face = (size_t)(4 * kNW) * 16 * sizeof(float);  // one component of one face
     const size_t rf6 = (size_t)R * Kmax * 6 * face;
     const size_t rc3 = (size_t)R * Kmax * 3 * face;
-    const size_t rb[6] = {rf6, rf6, rf6, lossy ? rf6 : rc3, h16 ? rc3 : 0, h16 ? rc3 : 0};
+    // (with FP16 storage the x and y faces' coefficients travel on rings of
+    // their own, unless material indices replace them)
+    const size_t rb[6] = {rf6, rf6, rf6, lossy ? rf6 : rc3, (h16 && !mat) ? rc3 : 0, (h16 && !mat) ? rc3 : 0};
     if (rf6 >= ((size_t)1 << 32) && lead->band_steps == 0 && Kmax > 1) {
         // an automatic band: take the longest one whose rings fit
         const size_t per_step = (size_t)R * 6 * face;

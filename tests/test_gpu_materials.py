@@ -104,7 +104,7 @@ def test_materials_change_and_device_input():
         sim.close()
 
 
-def test_conductive_and_fp16_contexts_have_no_table():
+def test_conductive_contexts_have_no_table():
     w = wl.small_case((20, 20, 20), (PEC, PEC, PEC), seed=2, nsteps=4)
     sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic")
     try:
@@ -114,12 +114,32 @@ def test_conductive_and_fp16_contexts_have_no_table():
         assert sim.info(fdtd.INFO_MATERIALS) > 0
     finally:
         sim.close()
-    sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic", storage="fp16")
-    try:
-        sim.set_materials(w.eps)
-        assert sim.info(fdtd.INFO_MATERIALS) == 0
-    finally:
-        sim.close()
+
+
+@pytest.mark.parametrize("bc", [(PEC, PEC, PEC), (PER, PER, PEC)])
+def test_fp16_storage_indices_and_rings_both_bitwise(bc):
+    """FP16 storage: the table holds the exact FP32 values of the binary16
+    coefficients; with indices the x and y faces read them instead of the
+    coefficient rings.  Both forms equal the FP16-storage oracle."""
+    from oracle import f16
+    w = wl.small_case((41, 36, 38), bc, seed=17 + bc[0], nsteps=24, dipoles=[(20, 18, 19)])
+    ref = f16.run_systolic(w.fields, f16.coeff_E16(w.eps3(), w.bc, w.dt, w.dx), np.float32(w.dt / w.dx),
+                           [24], [8], sources=w.sources)
+    for ids in (1, 0):
+        sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic", storage="fp16")
+        try:
+            sim.set_option(fdtd.OPT_MATERIAL_IDS, ids)
+            sim.set_option(fdtd.OPT_BAND_STEPS, 8)
+            sim.set_materials(w.eps)
+            assert sim.info(fdtd.INFO_MATERIALS) > 0
+            sim.set_fields(w.fields)
+            for s in w.sources:
+                sim.add_source(s["comp"], s["i"], s["j"], s["k"], s["waveform"])
+            sim.step(24)
+            got = sim.read_fields()
+        finally:
+            sim.close()
+        assert_bitwise(got, ref, "FP16 storage %s ids=%d" % (bc, ids))
 
 
 def test_batch_mixing_indices_and_arrays():

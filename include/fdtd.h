@@ -388,10 +388,15 @@ enum {
                                  arrays, sources or scales change); 0 = one
                                  launch per kernel.  Same results; per-kernel
                                  timing (FDTD_OPT_PROFILE) launches directly. */
-    FDTD_OPT_TILE_X = 7       /* systolic: updated cells per tile along x on a
+    FDTD_OPT_TILE_X = 7,      /* systolic: updated cells per tile along x on a
                                  lossless FP32 grid, 15 or 11 (0 = default, 15;
                                  conductive grids always take 11, FP16 storage
                                  15).  A batch needs one width for all.        */
+    FDTD_OPT_AUTOTUNE_PLAIN = 8 /* 1 = fdtd_autotune also times the plain
+                                 two-launch scheme (FP32 storage only, where
+                                 every scheme gives the same bits) and switches
+                                 the context to it when it is faster; 0
+                                 (default) = systolic configurations only     */
 };
 
 /* Set a tuning option (see FDTD_OPT_*).  FDTD_EINVAL for unknown options or
@@ -409,7 +414,10 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value);
  * fastest pair becomes the context's FDTD_OPT_TILE_X and
  * FDTD_OPT_BAND_STEPS.  The choice is kept for the process, keyed by grid
  * shape, boundaries, storage, conductivity, material indices and run length:
- * a later call with the same key takes it without timing anything.
+ * a later call with the same key takes it without timing anything.  With
+ * FDTD_OPT_AUTOTUNE_PLAIN the plain two-launch scheme is timed as well (FP32
+ * storage); when it is faster the context switches to it
+ * (FDTD_INFO_SCHEME) and tile_x and band_steps read 0.
  * tile_x, band_steps: the chosen values, or NULL.  Synchronises.
  * Errors: FDTD_EUNSUPPORTED for another scheme or when no candidate runs,
  * FDTD_ENOMEM without room for the copy; the errors of fdtd_step. */
@@ -438,9 +446,10 @@ enum {
                                    /* 15, or 11 for a context with conductivity)         */
     FDTD_INFO_TILE_Y = 5,
     FDTD_INFO_TILE_Z = 6,
-    FDTD_INFO_MATERIALS = 7        /* entries of the context's material table, entry 0 */
+    FDTD_INFO_MATERIALS = 7,       /* entries of the context's material table, entry 0 */
                                    /* (+0, +0, +0) included; 0 = none (conductive, or  */
                                    /* more than 256 distinct triples)                   */
+    FDTD_INFO_SCHEME = 8           /* the context's scheme (FDTD_SCHEME_*)              */
 };
 
 /* Read a piece of launch information (FDTD_INFO_*) into *value; 0 before the

@@ -8,6 +8,10 @@
 // length the caller will use, from the context's current state, which is
 // restored after every run.  The fastest pair becomes the context's options
 // and is kept for the process, keyed by everything the choice depends on.
+// With FP32 storage, where every scheme computes the same bits, the plain
+// two-launch scheme (replayed as a graph) can be timed too: small grids,
+// whose state sits in the last-level cache and whose few tiles cannot fill a
+// systolic pipeline, run faster on it, and the context then switches to it.
 #include <string.h>
 
 #include <map>
@@ -21,12 +25,17 @@ namespace fdtd {
 namespace {
 
 std::mutex g_tune_mu;
-std::map<std::vector<int64_t>, std::pair<int, int>> g_tuned;  // key -> (tile width, band)
+// key -> (tile width, band); (0, 0) when the plain scheme won
+std::map<std::vector<int64_t>, std::pair<int, int>> g_tuned;
+
+// the plain two-launch scheme takes part: asked for, and FP32 storage (the
+// FP16 schemes round at different places, so switching would change results)
+bool plain_candidate(const fdtd_ctx* ctx) { return ctx->tune_plain && ctx->storage == FDTD_FP32; }
 
 std::vector<int64_t> tune_key(const fdtd_ctx* ctx, int64_t probe)
 {
     return {ctx->nx, ctx->ny, ctx->nz, ctx->cfg.bc[0], ctx->cfg.bc[1], ctx->cfg.bc[2], ctx->storage,
-            ctx->ca[0] != nullptr, ctx->use_mat && ctx->nmat > 0, probe};
+            ctx->ca[0] != nullptr, ctx->use_mat && ctx->nmat > 0, probe, plain_candidate(ctx)};
 }
 
 }  // namespace
@@ -41,8 +50,12 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
-            ctx->tile_narrow = it->second.first == 11;
-            ctx->band_steps = it->second.second;
+            if (it->second.first == 0) {
+                ctx->scheme = FDTD_SCHEME_PLAIN;
+            } else {
+                ctx->tile_narrow = it->second.first == 11;
+                ctx->band_steps = it->second.second;
+            }
             if (out_tile) *out_tile = it->second.first;
             if (out_band) *out_band = it->second.second;
             return FDTD_OK;
@@ -129,6 +142,25 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
                 if (d) rc = d;
             }
         }
+    // the plain two-launch scheme, timed the same way (twice: the first run
+    // also captures its step graph)
+    bool plain_wins = false;
+    if (plain_candidate(ctx) && have && !rc && e == hipSuccess) {
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && !rc && e == hipSuccess; ++rep) {
+            if ((e = restore()) != hipSuccess) break;
+            if ((e = hipEventRecord(ev[0], ctx->stream)) != hipSuccess) break;
+            int r = plain_step(ctx, probe);
+            if (r) {
+                rc = r;
+                break;
+            }
+            if ((e = hipEventRecord(ev[1], ctx->stream)) != hipSuccess || (e = hipEventSynchronize(ev[1])) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess)
+                break;
+            if (rep == 1 && ms < best_ms) plain_wins = true;
+        }
+    }
     // back to the state and options the context had
     hipError_t e2 = restore();
     if (e == hipSuccess) e = e2;
@@ -141,8 +173,13 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
     if (!have) return fail(ctx, FDTD_EUNSUPPORTED, "autotune: no candidate runs on this grid");
-    ctx->tile_narrow = best_w == 11;
-    ctx->band_steps = best_k;
+    if (plain_wins) {
+        ctx->scheme = FDTD_SCHEME_PLAIN;
+        best_w = best_k = 0;
+    } else {
+        ctx->tile_narrow = best_w == 11;
+        ctx->band_steps = best_k;
+    }
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tuned[key] = {best_w, best_k};

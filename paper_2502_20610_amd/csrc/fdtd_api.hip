@@ -950,6 +950,10 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
             return fail(ctx, FDTD_EUNSUPPORTED, "set_option: the 11-wide tile needs FP32 storage");
         ctx->tile_narrow = value == 11;
         return FDTD_OK;
+    case FDTD_OPT_AUTOTUNE_PLAIN:
+        if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: autotune-plain is 0 or 1");
+        ctx->tune_plain = value == 1;
+        return FDTD_OK;
     case FDTD_OPT_GRAPHS:
         if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: graphs is 0 or 1");
         ctx->use_graphs = value == 1;
@@ -1004,6 +1008,7 @@ int fdtd_get_info(const fdtd_ctx* ctx, int key, int64_t* value)
     case FDTD_INFO_TILE_Y: *value = wy; return FDTD_OK;
     case FDTD_INFO_TILE_Z: *value = wz; return FDTD_OK;
     case FDTD_INFO_MATERIALS: *value = ctx->nmat; return FDTD_OK;
+    case FDTD_INFO_SCHEME: *value = ctx->scheme; return FDTD_OK;
     default: return FDTD_EINVAL;
     }
 }

@@ -94,6 +94,7 @@ struct fdtd_ctx {
     int nmat;
     bool use_mat;     // FDTD_OPT_MATERIAL_IDS
     bool tile_narrow; // FDTD_OPT_TILE_X = 11 on a lossless FP32 grid
+    bool tune_plain;  // FDTD_OPT_AUTOTUNE_PLAIN
 
     // plain schemes: step loops replayed as a HIP graph (FDTD_OPT_GRAPHS)
     bool use_graphs;

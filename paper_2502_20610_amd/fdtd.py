@@ -28,10 +28,10 @@ SCHEME_PLAIN, SCHEME_SYSTOLIC, SCHEME_PLAIN_FUSED = 0, 1, 2
 FP32, FP16_STORAGE = 0, 1
 HOST, DEVICE = 0, 1
 (OPT_SCHEME, OPT_BAND_STEPS, OPT_WORKGROUPS, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_MATERIAL_IDS,
- OPT_GRAPHS, OPT_TILE_X) = range(8)
+ OPT_GRAPHS, OPT_TILE_X, OPT_AUTOTUNE_PLAIN) = range(9)
 KERNEL_PLAIN_E, KERNEL_PLAIN_H, KERNEL_SOURCES, KERNEL_SYSTOLIC, KERNEL_PLAIN_FUSED = range(5)
 (INFO_SYSTOLIC_GRID, INFO_SYSTOLIC_BAND, INFO_SYSTOLIC_TICKETS, INFO_RING_SLOTS, INFO_TILE_X,
- INFO_TILE_Y, INFO_TILE_Z, INFO_MATERIALS) = range(8)
+ INFO_TILE_Y, INFO_TILE_Z, INFO_MATERIALS, INFO_SCHEME) = range(9)
 # fdtd_invariants sums, in order
 INVARIANT_NAMES = ("energy", "e_energy", "h_energy", "div_e_l1", "div_e_l2sq", "div_h_l1",
                    "div_h_l2sq")

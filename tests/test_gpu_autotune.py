@@ -80,6 +80,32 @@ def test_autotune_restores_state_and_keeps_its_choice():
         other.close()
 
 
+def test_autotune_with_the_plain_scheme_as_a_candidate():
+    """FDTD_OPT_AUTOTUNE_PLAIN: the plain two-launch scheme is timed too; on a
+    small grid it usually wins.  Whichever wins, the context reports it, the
+    outputs agree with it, and the run that follows is bitwise.  FP16 storage
+    never switches (its schemes round at different places)."""
+    w = wl.small_case((32, 32, 32), (PEC, PEC, PEC), seed=8, nsteps=40, dipoles=[(16, 16, 16)])
+    sim = _sim(w, [(fdtd.OPT_AUTOTUNE_PLAIN, 1)])
+    try:
+        tile, band = sim.autotune(40)
+        scheme = sim.info(fdtd.INFO_SCHEME)
+        assert scheme in (fdtd.SCHEME_PLAIN, fdtd.SCHEME_SYSTOLIC)
+        assert (tile, band) == (0, 0) if scheme == fdtd.SCHEME_PLAIN else tile in (11, 15)
+        sim.step(40)
+        assert_bitwise(sim.read_fields(), oracle_f32(w, 40), "run after autotune (scheme %d)" % scheme)
+    finally:
+        sim.close()
+    h = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic", storage="fp16")
+    try:
+        h.set_option(fdtd.OPT_AUTOTUNE_PLAIN, 1)
+        h.set_materials(w.eps)
+        tile, band = h.autotune(16)
+        assert h.info(fdtd.INFO_SCHEME) == fdtd.SCHEME_SYSTOLIC and tile == 15
+    finally:
+        h.close()
+
+
 def test_autotune_refusals_and_narrow_tile_refusals():
     w = wl.small_case((24, 24, 24), (PEC, PEC, PEC), seed=2, nsteps=4)
     plain = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="plain")

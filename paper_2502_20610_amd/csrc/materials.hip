@@ -222,6 +222,8 @@ int build_material_ids(fdtd_ctx* ctx)
     }
     (void)hipFree(d_scratch);
     if (e != hipSuccess) return hip_fail(ctx, e, "material table");
+    // too many materials: the per-cell arrays serve, the index array goes
+    if (ctx->nmat == 0) release_material_ids(ctx);
     return FDTD_OK;
 }
 

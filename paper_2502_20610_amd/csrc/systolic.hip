@@ -197,6 +197,30 @@ __device__ __forceinline__ void dma_dword(__amdgpu_buffer_rsrc_t desc, unsigned 
                      :: "s"(lds), "v"(voff), "s"(desc) : "memory");
 }
 
+// Uniform words read through the scalar data cache (every lane has the same
+// address, and the value lands in scalar registers).  Each load completes
+// inside its asm statement.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned sload(const void* p)
+{
+    unsigned v;
+    asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+    return v;
+}
+__device__ __forceinline__ v4i sload4(const void* p)
+{
+    v4i v;
+    asm volatile("s_load_dwordx4 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+    return v;
+}
+__device__ __forceinline__ const float* sload_ptr(const void* p)
+{
+    v2i v;
+    asm volatile("s_load_dwordx2 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+    return (const float*)(((unsigned long long)(unsigned)v[1] << 32) | (unsigned)v[0]);
+}
+
 // An LDS address made opaque at this point of the program, so that the
 // per-component destinations derived from it are formed where they are used
 // instead of being kept live (in scalar registers) across the step loop.
@@ -280,6 +304,19 @@ __device__ __forceinline__ void complete_loads()
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+}
+
+// Complete every vector memory operation of this wavefront except the last N
+// it issued, then a workgroup barrier.  The vector memory counter retires in
+// issue order (loads, stores and loads into LDS alike), so with N = the number
+// of stores issued since a group of loads into LDS, those loads have landed
+// and every earlier store has completed, while the N recent stores may still
+// be in flight.  N must not exceed the operations actually issued since.
+template <int N>
+__device__ __forceinline__ void complete_all_but()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" :: "n"(N) : "memory");
 }
 
 // Wait until every listed tile's counter is >= target (acquire).  Lanes
@@ -398,6 +435,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     constexpr unsigned step_f = 6u * ring_comp;  // floats per (slot, local step): E and H
     constexpr unsigned step_c = (unsigned)(NQA - 6) * ring_comp;  // the z face's coefficients
     constexpr unsigned cb = ring_comp * 4u;      // bytes per component
+    // Lazy publishing (grids with no periodic axis): a level goes out once
+    // its stores have completed in the shadow of later work.  The global
+    // stores each half-step issues after its prefetch: the x face (3, with
+    // FP16 storage also its 3 coefficients), then the y and z faces.
+    constexpr bool LAZY = !PER;
+    constexpr int kStoresE = 3 + 3 + 3;
+    constexpr int kStoresH = 3 + ((F16 && !MAT) ? 3 : 0) + (NQY - 3) + (NQA - 3);
 
     float E[3][PXk], H[3][PXk], C[3][PXk];
     float CA[LOSSY ? 3 : 1][PXk];  // conductive decay per cell (unused when lossless)
@@ -865,9 +909,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     FDTD_APPLY_SOURCE(s_src[q][0], s_src[q][1], s_src[q][2], s_src[q][3], s_srcw[q][0],
                                       s_srcw[q][1], s_wv[q][ls]);
                 }
-                for (int q = kLdsSrc; q < P.nsrc; ++q)
-                    FDTD_APPLY_SOURCE(P.src[q].comp, P.src[q].i, P.src[q].j, P.src[q].k, P.src[q].first,
-                                      P.src[q].len, P.src[q].wave[m]);
+                for (int q = kLdsSrc; q < P.nsrc; ++q) {
+                    // (scalar loads: nothing of this rare loop is left on the
+                    // vector memory counter, which the prefetch waits use)
+                    const DevSource* sp = P.src + q;
+                    const v4i h = sload4(sp);         // comp, i, j, k
+                    const v4i fl = sload4(&sp->len);  // len, first
+                    const long long len = (long long)(((unsigned long long)(unsigned)fl[1] << 32) | (unsigned)fl[0]);
+                    const long long first = (long long)(((unsigned long long)(unsigned)fl[3] << 32) | (unsigned)fl[2]);
+                    const float* wave = sload_ptr(&sp->wave);
+                    // (the sample's index is clamped into the waveform: the
+                    // load sits under a uniform branch but must never stray)
+                    FDTD_APPLY_SOURCE(h[0], h[1], h[2], h[3], first, len,
+                                      __builtin_bit_cast(float, sload(wave + min(max(m, 0ll), len - 1))));
+                }
             }
 #undef FDTD_APPLY_SOURCE
 
@@ -888,18 +943,40 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         for (int j = 0; j < WXk; ++j) ztr[q][dy1][j] = E[q][j];
                 }
                 store_faces(std::integral_constant<int, 0>(), std::integral_constant<int, 3>(), std::integral_constant<int, 3>());
+                // (lazy: the early prefetch lands; this half-step's stores may fly on)
+                if (LAZY && earlyE) complete_all_but<kStoresE>();
+            } else if (LAZY && earlyE) {
+                complete_all_but<0>();
             }
-            // publish (which also completes an early prefetch); a late prefetch
-            // waits for the upwind neighbours only after this tile's own flag
-            // is out, since on a periodic ring they wait on it in turn
-            publish<DEV>(A, me, 2u * (unsigned)tau - 1u);
-            if (!earlyE) {
-                if (!ensure_up(2u * (unsigned)tau - 1u)) {
-                    aborted = true;
-                    break;
+            if (!LAZY) {
+                // publish (which also completes an early prefetch); a late
+                // prefetch waits for the upwind neighbours only after this
+                // tile's own flag is out, since on a periodic ring they wait
+                // on it in turn
+                publish<DEV>(A, me, 2u * (unsigned)tau - 1u);
+                if (!earlyE) {
+                    if (!ensure_up(2u * (unsigned)tau - 1u)) {
+                        aborted = true;
+                        break;
+                    }
+                    prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
+                    complete_loads();
                 }
-                prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
-                complete_loads();
+            } else {
+                // Without periodic axes no tile waits on a tile downwind of it,
+                // so the level of the previous step (2 tau - 2) is published
+                // here, once its stores have completed behind this half-step's
+                // work, and the E level of this step is not published on its
+                // own (the next full level covers it).
+                if (!earlyE) {
+                    if (!ensure_up(2u * (unsigned)tau - 1u)) {
+                        aborted = true;
+                        break;
+                    }
+                    prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
+                    complete_loads();
+                }
+                if (tau > t0 + 1) set_flag<DEV>(A, me, 2u * (unsigned)tau - 2u);
             }
 
             // forward shell's E^tau into the registers
@@ -984,6 +1061,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
                 store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, NQY - 3>(),
                             std::integral_constant<int, NQA - 3>());
+                // (lazy: the early prefetch lands; the level 2 tau goes out in
+                // the next step's E half)
+                if (LAZY && earlyH) complete_all_but<kStoresH>();
+            } else if (LAZY && earlyH) {
+                complete_all_but<0>();
             }
             if (tau == t1 && inB) {
                 // band end: the whole subdomain goes back to the field arrays
@@ -1002,7 +1084,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     }
                 }
             }
-            publish<DEV>(A, me, 2u * (unsigned)tau);
+            if (!LAZY || tau == t1)
+                publish<DEV>(A, me, 2u * (unsigned)tau);
+            else
+                asm volatile("" ::: "memory");  // (keeps memory accesses on their side, as publish does)
             if (tau == t1) break;
             // Past a PEC wall: once the box of the next step lies wholly past
             // the upper wall of a PEC axis (the tile only moves further out),
@@ -1010,7 +1095,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // consumers read those positions as ghosts (+0, out-of-range
             // loads).  The band-end level releases everything that waits on
             // it: its consumers, the next occupant of its ring slot and its
-            // own next band.  (publish has completed every load in flight.)
+            // own next band.  (publish completes every load in flight.)
             if ((!perx && ox + tau + 1 >= P.nx) || (!pery && oy + tau + 1 >= P.ny) ||
                 (!perz && oz + tau + 1 >= P.nz)) {
                 publish<DEV>(A, me, 2u * (unsigned)t1);

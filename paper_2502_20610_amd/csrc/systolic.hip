@@ -276,6 +276,22 @@ __device__ __forceinline__ int ticket_of(const SysArgs& A, const int* bi, int a,
                  (c - bi[4])];
 }
 
+// Ticket indices of the tiles (a, b, c) + s * (d & 1, (d >> 1) & 1, (d >> 2) & 1),
+// s = +1 (upwind corner) or -1 (downwind), in the band whose record is bi: lane
+// d = lane & 7 of each wavefront looks up one direction, so that the eight
+// lookups cost one round trip instead of eight dependent ones.  Every lane
+// returns its own direction's ticket, or -1 when the band lacks that tile;
+// readlane(v, d) gives direction d.
+template <bool PER>
+__device__ __forceinline__ int corner_tickets(const SysArgs& A, const SimArgs& P, const int* bi, int a, int b,
+                                              int c, int s)
+{
+    const int d = (int)(threadIdx.x & 7);
+    const int ua = wrap_tile<PER>(P, 0, a + s * (d & 1)), ub = wrap_tile<PER>(P, 1, b + s * ((d >> 1) & 1)),
+              uc = wrap_tile<PER>(P, 2, c + s * ((d >> 2) & 1));
+    return band_has(bi, ua, ub, uc) ? ticket_of(A, bi, ua, ub, uc) : -1;
+}
+
 // Set the tile's progress counter (release): every wavefront has completed
 // the global stores the new level covers, and passed a barrier since.
 template <bool DEV>
@@ -319,6 +335,20 @@ __device__ __forceinline__ void complete_all_but()
     asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" :: "n"(N) : "memory");
 }
 
+// Barrier of the progress waits.  With device-scope accesses (DEV) only the
+// LDS words and the execution order need it: the polled counters are used in
+// registers, and the data they release is read after the barrier with
+// device-scope loads, so outstanding global operations (a box load, a
+// half-step's face stores) can stay in flight.  Otherwise a full barrier.
+template <bool DEV>
+__device__ __forceinline__ void wait_barrier()
+{
+    if (DEV)
+        lds_barrier();
+    else
+        __syncthreads();
+}
+
 // Wait until every listed tile's counter is >= target (acquire).  Lanes
 // 0..n-1 of the first wavefront poll one counter each.  Returns false (on
 // every thread) if a wait expired or another workgroup raised the error.
@@ -329,9 +359,9 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     const int tid = threadIdx.x;
     if (s_min) {
         // every wavefront has finished reading *s_min before it is reset
-        __syncthreads();
+        wait_barrier<DEV>();
         if (tid == 0 && n) *s_min = 0xFFFFFFFFu;
-        __syncthreads();
+        wait_barrier<DEV>();
     }
     if (tid < n) {
         int my = idx[0];
@@ -357,7 +387,7 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
         if (s_min) atomicMin(s_min, v);
         if (!DEV) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __syncthreads();
+    wait_barrier<DEV>();
     return *s_abort == 0;
 }
 
@@ -446,6 +476,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     float E[3][PXk], H[3][PXk], C[3][PXk];
     float CA[LOSSY ? 3 : 1][PXk];  // conductive decay per cell (unused when lossless)
 
+    int staged_sim = -1, staged_band = -1;  // what the LDS copies below hold
     for (;;) {
         __syncthreads();
         if (tid == 0) {
@@ -464,7 +495,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int bnd = tk.x, a = tk.y, b = tk.z, c = tk.w;
         const int t0_ = bnd;  // band index; its steps follow once the record is read
         // this ticket's simulation: arrays, sizes, sources, boundaries
-        const SimArgs P = load_sim(A.sims + (A.tsim ? __builtin_amdgcn_readfirstlane(A.tsim[t]) : 0));
+        const int simi = A.tsim ? __builtin_amdgcn_readfirstlane(A.tsim[t]) : 0;
+        const SimArgs P = load_sim(A.sims + simi);
+        // The LDS copies of the sources, of their samples for the band and of
+        // the material table depend on the simulation and the band only: they
+        // are kept from this workgroup's previous ticket when both are the same.
+        const bool restage = simi != staged_sim || bnd != staged_band;
+        staged_sim = simi;
+        staged_band = bnd;
         const int t0 = t0_ * P.K;
         const int t1 = min(A.nsteps, t0 + P.K);
         const int* bi = P.band + 8 * bnd;
@@ -495,19 +533,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             for (int q = 0; q < 3; ++q) rca[q] = make_rsrc((const char*)P.ca[q] + ebase * 4ull, rbytes);
         }
         const float cH = P.cH;
-        if (tid < min(P.nsrc, kLdsSrc)) {
-            const DevSource sq = P.src[tid];
-            s_src[tid][0] = sq.comp;
-            s_src[tid][1] = sq.i;
-            s_src[tid][2] = sq.j;
-            s_src[tid][3] = sq.k;
-            s_srcw[tid][0] = sq.first;
-            s_srcw[tid][1] = sq.len;
-            s_srcp[tid] = sq.wave;
+        if (restage) {
+            if (tid < min(P.nsrc, kLdsSrc)) {
+                const DevSource sq = P.src[tid];
+                s_src[tid][0] = sq.comp;
+                s_src[tid][1] = sq.i;
+                s_src[tid][2] = sq.j;
+                s_src[tid][3] = sq.k;
+                s_srcw[tid][0] = sq.first;
+                s_srcw[tid][1] = sq.len;
+                s_srcp[tid] = sq.wave;
+            }
+            if (MAT)
+                for (int i = tid; i < kMaxMaterials * 3; i += 64 * NW) s_tab[i] = P.mtab[i];
+            __syncthreads();
         }
-        if (MAT)
-            for (int i = tid; i < kMaxMaterials * 3; i += 64 * NW) s_tab[i] = P.mtab[i];
-        __syncthreads();
         const int me = t;  // progress counters are per ticket
         const int ox = a * WXk, oy = b * WY, oz = c * WZ;
 
@@ -516,18 +556,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         int ups[8], sl_up[8];
         int nup = 0;
         sl_up[0] = -1;
+        {
+            const int upv = corner_tickets<PER>(A, P, bi, a, b, c, 1);
 #pragma unroll
-        for (int d = 1; d < 8; ++d) {
-            const int ua = wrap_tile<PER>(P, 0, a + (d & 1)), ub = wrap_tile<PER>(P, 1, b + ((d >> 1) & 1)),
-                      uc = wrap_tile<PER>(P, 2, c + ((d >> 2) & 1));
-            sl_up[d] = -1;
-            if (band_has(bi, ua, ub, uc)) {
-                const int pi = ticket_of(A, bi, ua, ub, uc);
+            for (int d = 1; d < 8; ++d) {
+                const int pi = __builtin_amdgcn_readlane(upv, d);
+                sl_up[d] = -1;
+                if (pi >= 0) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (k == nup) ups[k] = pi;
-                ++nup;
-                sl_up[d] = pi % A.R;
+                    for (int k = 0; k < 8; ++k)
+                        if (k == nup) ups[k] = pi;
+                    ++nup;
+                    sl_up[d] = pi % A.R;
+                }
             }
         }
 #pragma unroll
@@ -539,12 +580,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const int* bp = P.band + 8 * (bnd - 1);
             int wl[8];
             int nw = 0;
+            const int bv = corner_tickets<PER>(A, P, bp, a, b, c, 1);
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
-                const int ua = wrap_tile<PER>(P, 0, a + (d & 1)), ub = wrap_tile<PER>(P, 1, b + ((d >> 1) & 1)),
-                          uc = wrap_tile<PER>(P, 2, c + ((d >> 2) & 1));
-                if (band_has(bp, ua, ub, uc)) {
-                    const int pi = ticket_of(A, bp, ua, ub, uc);
+                const int pi = __builtin_amdgcn_readlane(bv, d);
+                if (pi >= 0) {
 #pragma unroll
                     for (int k = 0; k < 8; ++k)
                         if (k == nw) wl[k] = pi;
@@ -567,12 +607,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             int wl[8];
             wl[0] = t - A.R;
             int nw = 1;
+            const int cv = corner_tickets<PER>(A, PP, pb, pk.y, pk.z, pk.w, -1);
 #pragma unroll
             for (int d = 1; d < 8; ++d) {
-                const int da = wrap_tile<PER>(PP, 0, pk.y - (d & 1)), db = wrap_tile<PER>(PP, 1, pk.z - ((d >> 1) & 1)),
-                          dc = wrap_tile<PER>(PP, 2, pk.w - ((d >> 2) & 1));
-                if (band_has(pb, da, db, dc)) {
-                    const int ci = ticket_of(A, pb, da, db, dc);
+                const int ci = __builtin_amdgcn_readlane(cv, d);
+                if (ci >= 0) {
 #pragma unroll
                     for (int k = 1; k < 8; ++k)
                         if (k == nw) wl[k] = ci;
@@ -604,7 +643,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         //      sample step0 + tau - 1 - first; the range test is repeated at use)
         {
             const int nl = min(P.nsrc, kLdsSrc);
-            for (int i = tid; i < nl * kMaxBand; i += 64 * NW) {
+            for (int i = restage ? tid : nl * kMaxBand; i < nl * kMaxBand; i += 64 * NW) {
                 const int q = i / kMaxBand, l = i % kMaxBand;
                 const long long m = P.step0 + t0 + l - s_srcw[q][0];
                 s_wv[q][l] = (l < t1 - t0 && m >= 0 && m < s_srcw[q][1]) ? s_srcp[q][m] : 0.f;

@@ -53,7 +53,7 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
             if (it->second.first == 0) {
                 ctx->scheme = FDTD_SCHEME_PLAIN;
             } else {
-                ctx->tile_narrow = it->second.first == 11;
+                ctx->tile_wx = (int)it->second.first;
                 ctx->band_steps = it->second.second;
             }
             if (out_tile) *out_tile = it->second.first;
@@ -68,6 +68,8 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
         widths = {11};
     else if (h16)
         widths = {15};
+    else if (ctx->use_mat && ctx->nmat > 0 && ctx->mat_id)
+        widths = {15, 11, 19};  // (the 19-wide tile needs material indices)
     else
         widths = {15, 11};
     std::vector<int> bands;
@@ -90,7 +92,7 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
         e = hipMemcpyAsync((char*)saved + c * bytes, arr(c), bytes, hipMemcpyDeviceToDevice, ctx->stream);
     const int64_t step0 = ctx->step_count;
     const int band0 = ctx->band_steps;
-    const bool narrow0 = ctx->tile_narrow;
+    const int wx0 = ctx->tile_wx;
     auto restore = [&]() {
         hipError_t r = hipSuccess;
         for (int c = 0; c < 6 && r == hipSuccess; ++c)
@@ -107,7 +109,7 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
     int rc = FDTD_OK;
     for (size_t wi = 0; wi < widths.size() && e == hipSuccess && !rc; ++wi)
         for (size_t ki = 0; ki < bands.size() && e == hipSuccess && !rc; ++ki) {
-            ctx->tile_narrow = widths[wi] == 11;
+            ctx->tile_wx = widths[wi];
             ctx->band_steps = bands[ki];
             float ms = 0.0f;
             // twice: the first run also pays for plan, rings and code loading
@@ -169,7 +171,7 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
         if (x) (void)hipEventDestroy(x);
     (void)hipFree(saved);
     ctx->band_steps = band0;
-    ctx->tile_narrow = narrow0;
+    ctx->tile_wx = wx0;
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
     if (!have) return fail(ctx, FDTD_EUNSUPPORTED, "autotune: no candidate runs on this grid");
@@ -177,7 +179,7 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
         ctx->scheme = FDTD_SCHEME_PLAIN;
         best_w = best_k = 0;
     } else {
-        ctx->tile_narrow = best_w == 11;
+        ctx->tile_wx = best_w;
         ctx->band_steps = best_k;
     }
     {

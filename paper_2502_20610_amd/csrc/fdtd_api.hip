@@ -944,11 +944,11 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
         ctx->spin_limit = value;
         return FDTD_OK;
     case FDTD_OPT_TILE_X:
-        if (value != 0 && value != 11 && value != 15)
-            return fail(ctx, FDTD_EINVAL, "set_option: tile width is 0 (default), 11 or 15");
-        if (value == 11 && ctx->storage != FDTD_FP32)
-            return fail(ctx, FDTD_EUNSUPPORTED, "set_option: the 11-wide tile needs FP32 storage");
-        ctx->tile_narrow = value == 11;
+        if (value != 0 && value != 11 && value != 15 && value != 19)
+            return fail(ctx, FDTD_EINVAL, "set_option: tile width is 0 (default), 11, 15 or 19");
+        if ((value == 11 || value == 19) && ctx->storage != FDTD_FP32)
+            return fail(ctx, FDTD_EUNSUPPORTED, "set_option: the 11- and 19-wide tiles need FP32 storage");
+        ctx->tile_wx = (int)value;
         return FDTD_OK;
     case FDTD_OPT_AUTOTUNE_PLAIN:
         if (value != 0 && value != 1) return fail(ctx, FDTD_EINVAL, "set_option: autotune-plain is 0 or 1");

@@ -63,6 +63,7 @@ namespace {
 constexpr int PX = 16, PZ = 16;         // slots along x (registers) and z (lanes)
 constexpr int WX = PX - 1, WZ = PZ - 1; // updated cells along x and z
 constexpr int WX_LOSSY = 11;              // updated cells along x with conductivity
+constexpr int WX_WIDE = 19;               // updated cells along x of the wide tile
 constexpr unsigned kOOB = 0xFFFFFFF0u;  // buffer offset that reads 0 / drops stores
 constexpr int kErrTimeout = 2;          // error-word bit: a bounded wait expired
 
@@ -391,46 +392,59 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     return *s_abort == 0;
 }
 
-template <int NW, bool DEV, bool PER, bool LOSSY, bool F16, bool MAT, bool NARROW>
+template <int NW, bool DEV, bool PER, bool LOSSY, bool F16, bool MAT, int XW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void systolic_kernel(SysArgs A)
 {
-    // NARROW: the 11-wide x tile of the conductive variant on a lossless grid
-    static_assert(!(NARROW && (LOSSY || F16)), "narrow tile: lossless FP32 only");
+    // XW: updated cells of the tile along x (registers): 15; 11 with
+    // conductivity (which frees the registers of the per-cell decay ca) or
+    // when asked for; 19 with material indices held in registers
+    static_assert(XW == WX || XW == WX_LOSSY || XW == WX_WIDE, "tile widths 15, 11, 19");
+    static_assert(!LOSSY || XW == WX_LOSSY, "conductive grids: the 11-wide tile");
+    static_assert(!(XW == WX_LOSSY && F16), "11-wide tile: FP32 storage only");
     // MAT: the coefficients enter as per-cell material indices into a table
-    // (lossless FP32 grids); the z face still carries the values themselves
+    // (lossless grids).  IDR (the wide tile): the registers hold each cell's
+    // index instead of its three coefficients, and the z face carries it;
+    // otherwise the z face carries the values themselves.
     static_assert(!(MAT && LOSSY), "material indices: lossless grids only");
+    constexpr bool IDR = XW == WX_WIDE;
+    static_assert(!IDR || (MAT && !F16), "19-wide tile: material indices, FP32 storage");
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
     constexpr int PY = 4 * NW;
     constexpr int WY = PY - 1;
-    static_assert(PY == 16, "face staging assumes 16 slots on every axis");
-    // x slots in registers: 16 (15 updated); with conductivity 12 (11
-    // updated), which frees the registers of the per-cell decay ca
-    constexpr int PXk = (LOSSY || NARROW) ? WX_LOSSY + 1 : PX;
-    constexpr int WXk = PXk - 1;
-    // staged components: E, H, cb (cE), and ca with conductivity
-    constexpr int NQA = LOSSY ? 12 : 9;
-    constexpr int LS = 16;  // row stride of the LDS and ring face layouts
-    // rows (x slots) of the incoming y face: whole wavefronts of four rows,
-    // so that the conductive variant fits two workgroups in a CU's LDS
+    static_assert(PY == 16, "face staging assumes 16 slots on y and z");
+    constexpr int PXk = XW + 1;  // x slots in registers
+    constexpr int WXk = XW;
+    // staged components: E, H, then cb (cE; with IDR the index), and ca
+    // with conductivity
+    constexpr int NQA = LOSSY ? 12 : (IDR ? 7 : 9);
+    // rows of the y and z faces (one per x slot): whole groups of four, a
+    // wavefront's rows; each wavefront handles NG groups (w, w + NW, ...)
     constexpr int YR = (PXk + 3) & ~3;
+    constexpr int NG = (YR / 4 + NW - 1) / NW;
+    constexpr int FR = YR > 16 ? YR : 16;  // rows of a y or z face block on its ring
     // y-neighbour exchange, two components per half-step
     __shared__ float xch[2][WXk][PY][PZ];
-    // incoming faces of the next box: y face [comp][x][z], z face [comp][y][x]
-    // (with material indices the x and y faces stage E, H and the index)
+    // incoming faces of the next box: x face [comp][y slot][z slot], y face
+    // [comp][x][z slot], z face [comp][x][y slot] (with material indices the
+    // x and y faces stage E, H and the index)
     constexpr int NQS = MAT ? 7 : NQA;
-    __shared__ float xst[NQS][PY][PZ];   // x face [comp][y slot][z slot]
+    __shared__ float xst[NQS][PY][PZ];
     __shared__ float yst[NQS][YR][PZ];
-    __shared__ float s_tab[MAT ? kMaxMaterials * 3 : 1];  // material table (cEx, cEy, cEz)
-    __shared__ __attribute__((aligned(16))) float zst[NQA][PY][LS];
-    // outgoing faces of the first layer: y face [comp][x][z], z face [comp][y][x]
-    // (with FP16 storage the y face carries the coefficients as well)
+    __shared__ float4 s_tab[MAT ? kMaxMaterials : 1];  // material table (cEx, cEy, cEz, -)
+    __shared__ __attribute__((aligned(16))) float zst[NQA][YR][PY];
+    // outgoing faces of the first layer, one half-step's components at a
+    // time (E; then H and the coefficients): y face [comp][x][z slot], z face
+    // [comp][x][y slot] (with FP16 storage the y face carries the
+    // coefficients as well)
     constexpr int NQY = (F16 && !MAT) ? 9 : 6;
-    __shared__ float ytr[NQY][LS][PZ];
-    __shared__ __attribute__((aligned(16))) float ztr[NQA][PY][LS];
+    __shared__ float ytr[NQY - 3][YR][PZ];
+    __shared__ __attribute__((aligned(16))) float ztr[NQA - 3][YR][PY];
     __shared__ int s_ticket;
     __shared__ int s_abort;
     __shared__ unsigned s_up;  // lower bound of the upwind neighbours' progress
-    constexpr int kLdsSrc = 16;  // point sources kept in LDS (more are read from memory)
+    // point sources kept in LDS (more are read from memory; the wide tile
+    // keeps fewer, for its LDS budget)
+    constexpr int kLdsSrc = IDR ? 8 : 16;
     __shared__ int s_src[kLdsSrc][4];        // comp, i, j, k
     __shared__ long long s_srcw[kLdsSrc][2]; // first, len
     __shared__ const float* s_srcp[kLdsSrc];
@@ -447,8 +461,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     // Face rings, one per face orientation: per (slot, local step) the x
     // face holds E and H as [comp][dy][dz] (the producer's own slots), the y
     // face E and H as [comp][x register][dz], the z face E and H as
-    // [comp][next-box y slot][x register], and a fourth ring the z face's
-    // coefficients (cE, and ca) in the same layout.  Every ring holds at most
+    // [comp][x register][next-box y slot], and a fourth ring the z face's
+    // coefficients (cE, and ca; with IDR the index) in the same layout.  Every ring holds at most
     // six components per (slot, step), which keeps each within the 32-bit
     // offsets of a buffer descriptor on large grids.
     const __amdgpu_buffer_rsrc_t rrx = make_rsrc(A.ring[0], A.ring_bytes[0]);
@@ -459,21 +473,25 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     // coefficient arrays are binary16, which the LDS loads cannot convert)
     const __amdgpu_buffer_rsrc_t rrxc = make_rsrc(A.ring[4], A.ring_bytes[4]);
     const __amdgpu_buffer_rsrc_t rryc = make_rsrc(A.ring[5], A.ring_bytes[5]);
-    constexpr unsigned step_c3 = 3u * 16u * 16u;  // floats per (slot, step) of rrxc, rryc
     constexpr unsigned ES = F16 ? 2u : 4u;         // bytes per stored field element
-    constexpr unsigned ring_comp = PY * LS;      // floats per component
-    constexpr unsigned step_f = 6u * ring_comp;  // floats per (slot, local step): E and H
-    constexpr unsigned step_c = (unsigned)(NQA - 6) * ring_comp;  // the z face's coefficients
-    constexpr unsigned cb = ring_comp * 4u;      // bytes per component
+    // floats per component of an x face block (16 x 16) and of a y or z
+    // face block (FR x 16), the blocks of a (slot, local step) and the bytes
+    // per component
+    constexpr unsigned rcx = PY * 16u, rcyz = FR * 16u;
+    constexpr unsigned step_fx = 6u * rcx, step_fyz = 6u * rcyz;        // E and H
+    constexpr unsigned step_c = (unsigned)(NQA - 6) * rcyz;             // the z face's coefficients
+    constexpr unsigned step_c3x = 3u * rcx, step_c3y = 3u * rcyz;       // rrxc, rryc
+    constexpr unsigned cbx = rcx * 4u, cbyz = rcyz * 4u;
     // Lazy publishing (grids with no periodic axis): a level goes out once
     // its stores have completed in the shadow of later work.  The global
     // stores each half-step issues after its prefetch: the x face (3, with
     // FP16 storage also its 3 coefficients), then the y and z faces.
     constexpr bool LAZY = !PER;
-    constexpr int kStoresE = 3 + 3 + 3;
-    constexpr int kStoresH = 3 + ((F16 && !MAT) ? 3 : 0) + (NQY - 3) + (NQA - 3);
+    constexpr int kStoresE = 3 + NG * (3 + 3);
+    constexpr int kStoresH = 3 + ((F16 && !MAT) ? 3 : 0) + NG * ((NQY - 3) + (NQA - 3));
 
-    float E[3][PXk], H[3][PXk], C[3][PXk];
+    float E[3][PXk], H[3][PXk], C[3][PXk];  // (C unused with IDR)
+    unsigned ID[IDR ? PXk : 1];              // material index per cell (IDR)
     float CA[LOSSY ? 3 : 1][PXk];  // conductive decay per cell (unused when lossless)
 
     int staged_sim = -1, staged_band = -1;  // what the LDS copies below hold
@@ -545,30 +563,33 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 s_srcp[tid] = sq.wave;
             }
             if (MAT)
-                for (int i = tid; i < kMaxMaterials * 3; i += 64 * NW) s_tab[i] = P.mtab[i];
+                for (int i = tid; i < kMaxMaterials; i += 64 * NW)
+                    s_tab[i] = make_float4(P.mtab[3 * i], P.mtab[3 * i + 1], P.mtab[3 * i + 2], 0.f);
             __syncthreads();
         }
         const int me = t;  // progress counters are per ticket
         const int ox = a * WXk, oy = b * WY, oz = c * WZ;
 
         // upwind neighbours that exist in this band, and the ring slot of
-        // each (d: bit 0 = +x, bit 1 = +y, bit 2 = +z; -1 when absent)
-        int ups[8], sl_up[8];
+        // each (d: bit 0 = +x, bit 1 = +y, bit 2 = +z; -1 when absent): lane
+        // d (mod 8) of every wavefront holds direction d's slot in slv, which
+        // a lane's choice of producer reads back with a cross-lane permute.
+        // (Not an array: a per-lane choice among the elements of an array can
+        // become a load from scratch memory, whose wait would drain the
+        // vector memory counter in every half-step.)
+        int ups[8];
         int nup = 0;
-        sl_up[0] = -1;
-        {
-            const int upv = corner_tickets<PER>(A, P, bi, a, b, c, 1);
+        const int upv = corner_tickets<PER>(A, P, bi, a, b, c, 1);
+        const int slv = upv >= 0 ? upv % A.R : -1;
+        const int su4 = __builtin_amdgcn_readlane(slv, 4);  // the z face's producer (wavefront-uniform)
 #pragma unroll
-            for (int d = 1; d < 8; ++d) {
-                const int pi = __builtin_amdgcn_readlane(upv, d);
-                sl_up[d] = -1;
-                if (pi >= 0) {
+        for (int d = 1; d < 8; ++d) {
+            const int pi = __builtin_amdgcn_readlane(upv, d);
+            if (pi >= 0) {
 #pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        if (k == nup) ups[k] = pi;
-                    ++nup;
-                    sl_up[d] = pi % A.R;
-                }
+                for (int k = 0; k < 8; ++k)
+                    if (k == nup) ups[k] = pi;
+                ++nup;
             }
         }
 #pragma unroll
@@ -705,12 +726,23 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     const unsigned ioff = (F16 && off != kOOB) ? off * 2u : off;
                     const unsigned id = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(rid, (int)ioff, 0, 0) &
                                         (unsigned)(kMaxMaterials - 1);
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) C[q][j] = s_tab[3 * id + q];
+                    if (IDR) {
+                        ID[j] = id;
+                    } else {
+                        const float4 t4 = s_tab[id];
+                        C[0][j] = t4.x;
+                        C[1][j] = t4.y;
+                        C[2][j] = t4.z;
+                    }
                 }
             }
         }
         if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up)) break;
+        // The box has landed before the step loop (a wait the compiler sees:
+        // left to its own accounting, loads still in flight at the loop's
+        // entry would make it drain the vector memory counter inside the
+        // loop on every step).
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 
         // (s_srcmask is complete: wait_tiles ends with a barrier)
         const unsigned srcmask = __builtin_amdgcn_readfirstlane(s_srcmask);
@@ -752,10 +784,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             (void)zf;
 
             // Issue the loads of the next box's forward shell for components
-            // [Q0, Q0 + NQ) (0..2 = E, 3..5 = H, 6..8 = cE, 9..11 = ca)
-            // straight into LDS: E and H from the producers' face rings, the
-            // coefficients from their arrays.  Wavefront w loads rows
-            // 4w..4w+3 of every component of the three faces.
+            // [Q0, Q0 + NQ) (0..2 = E, 3..5 = H, 6..8 = cE, 9..11 = ca; with
+            // material indices 6 = the index) straight into LDS: E and H from
+            // the producers' face rings, the coefficients from their arrays
+            // (or rings).  Wavefront w loads rows 4w..4w+3 of the x face and
+            // the row groups w, w + NW, ... of the y and z faces.
             auto prefetch = [&](auto q0c, auto nqc) {
                 constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
                 // x face: rows of the wavefront are y slots, lanes are z
@@ -767,96 +800,112 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 const bool okxf = axis_pos<PER>(Ux, Xw, P.nx, perx, wxr, xf);
                 const unsigned oxf = (okyz1 && okxf) ? ((unsigned)(xf - xlo) * plane + yz1) * 4u : kOOB;
                 const bool fwy = dy1 == wyr, fwz = dz1 == wzr;
-                const int sx = fwy ? (fwz ? sl_up[7] : sl_up[3]) : (fwz ? sl_up[5] : sl_up[1]);
+                const int sx = __builtin_amdgcn_ds_bpermute((1 | (fwy ? 2 : 0) | (fwz ? 4 : 0)) << 2, slv);
                 const bool okxr = okyz1 && okxf && dy1 <= wyr && dz1 <= wzr && sx >= 0;
-                const unsigned xin = (unsigned)(fwy ? 1 : dy1 + 1) * LS + (unsigned)(fwz ? 1 : dz1 + 1);
-                const unsigned oxr = (sls_of(sx) * step_f + xin) * 4u;
-                const unsigned oxc = (sls_of(sx) * step_c3 + xin) * 4u;
-                // y face: rows of the wavefront are x registers, lanes are z;
-                // the +y neighbour's (or, on the forward z lane, the +y+z
-                // neighbour's) first y row
-                const int j = 4 * w + r;
-                const bool ydo = YR == PY || 4 * w < YR;  // wavefront-uniform
-                int x;
-                const bool okx = j < WXk && axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
-                const unsigned oyf = (oky_f && okz_l && okx)
-                                         ? (((unsigned)(x - xlo) * (unsigned)P.ny + (unsigned)yf) * (unsigned)P.nz + (unsigned)zl) * 4u
-                                         : kOOB;
-                const bool fwzl = dz1 == wzr;
-                const int sy = fwzl ? sl_up[6] : sl_up[2];
-                const bool okyr = oky_f && okz_l && okx && dz1 <= wzr && sy >= 0;
-                const unsigned yin = (unsigned)j * LS + (unsigned)(fwzl ? 1 : dz1 + 1);
-                const unsigned oyr = (sls_of(sy) * step_f + yin) * 4u;
-                const unsigned oyc = (sls_of(sy) * step_c3 + yin) * 4u;
-                // z face: rows are y, lanes are x, from the +z neighbour's ring slot
-                const int yy = 4 * w + r;
-                int xr, yr;
-                const bool okz = sl_up[4] >= 0 && okz_f && zs < WXk && yy < WY &&
-                                 axis_pos<PER>(Ux, Xw, P.nx, perx, zs, xr) &&
-                                 axis_pos<PER>(Uy, Yw, P.ny, pery, yy, yr);
-                const unsigned ozf = (sls_of(sl_up[4]) * step_f + (unsigned)yy * LS + (unsigned)zs) * 4u;
-                const unsigned ozc = (sls_of(sl_up[4]) * step_c + (unsigned)yy * LS + (unsigned)zs) * 4u;
+                const unsigned xin = (unsigned)(fwy ? 1 : dy1 + 1) * 16u + (unsigned)(fwz ? 1 : dz1 + 1);
+                const unsigned oxr = (sls_of(sx) * step_fx + xin) * 4u;
+                const unsigned oxc = (sls_of(sx) * step_c3x + xin) * 4u;
                 const unsigned lxb = lds_offset(&xst[0][4 * w][0]);
-                const unsigned lyb = lds_offset(&yst[0][ydo ? 4 * w : 0][0]);
-                const unsigned lzb = lds_offset(&zst[0][4 * w][0]);
 #pragma unroll
                 for (int q = Q0; q < Q0 + NQ; ++q) {
-                    const unsigned ly = lds_here(lyb) + (unsigned)q * (unsigned)sizeof(yst[0]);
                     const unsigned lx = lds_here(lxb) + (unsigned)q * (unsigned)sizeof(xst[0]);
-                    const unsigned lz = lds_here(lzb) + (unsigned)q * (unsigned)sizeof(zst[0]);
-                    if (q < 6) {
-                        dma_dword<DEV>(rrx, lx, okxr ? oxr + (unsigned)q * cb : kOOB);
-                        if (ydo) dma_dword<DEV>(rry, ly, okyr ? oyr + (unsigned)q * cb : kOOB);
-                    } else if (MAT) {
-                        if (q == 6) {  // the material index (one word per cell)
-                            dma_dword<false>(rid, lx, oxf);
-                            if (ydo) dma_dword<false>(rid, ly, oyf);
-                        }
-                    } else if (q < 9 && F16) {
-                        dma_dword<DEV>(rrxc, lx, okxr ? oxc + (unsigned)(q - 6) * cb : kOOB);
-                        if (ydo) dma_dword<DEV>(rryc, ly, okyr ? oyc + (unsigned)(q - 6) * cb : kOOB);
-                    } else if (q < 9) {
-                        dma_dword<false>(rc[q - 6], lx, oxf);
-                        if (ydo) dma_dword<false>(rc[q - 6], ly, oyf);
-                    } else if (LOSSY) {
-                        dma_dword<false>(rca[q - 9], lx, oxf);
-                        if (ydo) dma_dword<false>(rca[q - 9], ly, oyf);
-                    }
                     if (q < 6)
-                        dma_dword<DEV>(rrz, lz, okz ? ozf + (unsigned)q * cb : kOOB);
-                    else
-                        dma_dword<DEV>(rrc, lz, okz ? ozc + (unsigned)(q - 6) * cb : kOOB);
+                        dma_dword<DEV>(rrx, lx, okxr ? oxr + (unsigned)q * cbx : kOOB);
+                    else if (MAT) {
+                        if (q == 6) dma_dword<false>(rid, lx, oxf);  // the material index (one word per cell)
+                    } else if (q < 9 && F16)
+                        dma_dword<DEV>(rrxc, lx, okxr ? oxc + (unsigned)(q - 6) * cbx : kOOB);
+                    else if (q < 9)
+                        dma_dword<false>(rc[q - 6], lx, oxf);
+                    else if (LOSSY)
+                        dma_dword<false>(rca[q - 9], lx, oxf);
+                }
+                // y face: rows are x registers, lanes are z slots; the +y
+                // neighbour's (or, on the forward z lane, the +y+z
+                // neighbour's) first y row.  z face: rows are x registers,
+                // lanes are y slots, from the +z neighbour's ring slot.
+                const bool fwzl = dz1 == wzr;
+                const int sy = __builtin_amdgcn_ds_bpermute((2 | (fwzl ? 4 : 0)) << 2, slv);
+                int yr;
+                const bool okzy = su4 >= 0 && okz_f && zs < WY && axis_pos<PER>(Uy, Yw, P.ny, pery, zs, yr);
+#pragma unroll
+                for (int k = 0; k < NG; ++k) {
+                    const int g = w + NW * k;  // wavefront-uniform
+                    if (g >= YR / 4) break;
+                    const int j = 4 * g + r;
+                    int x;
+                    const bool okx = j < WXk && axis_pos<PER>(Ux, Xw, P.nx, perx, j, x);
+                    const unsigned oyf = (oky_f && okz_l && okx)
+                                             ? (((unsigned)(x - xlo) * (unsigned)P.ny + (unsigned)yf) * (unsigned)P.nz + (unsigned)zl) * 4u
+                                             : kOOB;
+                    const bool okyr = oky_f && okz_l && okx && dz1 <= wzr && sy >= 0;
+                    const unsigned yin = (unsigned)j * 16u + (unsigned)(fwzl ? 1 : dz1 + 1);
+                    const unsigned oyr = (sls_of(sy) * step_fyz + yin) * 4u;
+                    const unsigned oyc = (sls_of(sy) * step_c3y + yin) * 4u;
+                    const bool okz = okzy && okx;
+                    const unsigned ozf = (sls_of(su4) * step_fyz + (unsigned)j * 16u + (unsigned)zs) * 4u;
+                    const unsigned ozc = (sls_of(su4) * step_c + (unsigned)j * 16u + (unsigned)zs) * 4u;
+                    const unsigned lyb = lds_offset(&yst[0][4 * g][0]);
+                    const unsigned lzb = lds_offset(&zst[0][4 * g][0]);
+#pragma unroll
+                    for (int q = Q0; q < Q0 + NQ; ++q) {
+                        const unsigned ly = lds_here(lyb) + (unsigned)q * (unsigned)sizeof(yst[0]);
+                        const unsigned lz = lds_here(lzb) + (unsigned)q * (unsigned)sizeof(zst[0]);
+                        if (q < 6) {
+                            dma_dword<DEV>(rry, ly, okyr ? oyr + (unsigned)q * cbyz : kOOB);
+                            dma_dword<DEV>(rrz, lz, okz ? ozf + (unsigned)q * cbyz : kOOB);
+                        } else {
+                            if (MAT) {
+                                if (q == 6) dma_dword<false>(rid, ly, oyf);
+                            } else if (q < 9 && F16)
+                                dma_dword<DEV>(rryc, ly, okyr ? oyc + (unsigned)(q - 6) * cbyz : kOOB);
+                            else if (q < 9)
+                                dma_dword<false>(rc[q - 6], ly, oyf);
+                            else if (LOSSY)
+                                dma_dword<false>(rca[q - 9], ly, oyf);
+                            dma_dword<DEV>(rrc, lz, okz ? ozc + (unsigned)(q - 6) * cbyz : kOOB);
+                        }
+                    }
                 }
             };
             // Write the staged first-layer faces for components [Q0, Q0+NQ)
-            // (z face: [Q0, Q0+NQZ)) to memory, after a barrier that makes the
-            // LDS writes visible.  Wavefront w writes rows 4w..4w+3.
+            // (z face: [Q0, Q0+NQZ)), staged in LDS from slot 0 on, to memory,
+            // after a barrier that makes the LDS writes visible.  Wavefront w
+            // writes the row groups w, w + NW, ... (every wavefront issues the
+            // same number of stores: rows past the face are dropped, their
+            // LDS reads clamped).
             auto store_faces = [&](auto q0c, auto nqc, auto nqzc) {
                 constexpr int Q0 = decltype(q0c)::value, NQ = decltype(nqc)::value;
                 constexpr int NQZ = decltype(nqzc)::value;
                 lds_barrier();
-                const int j = 4 * w + r;
-                // y face (the first y row) as [x register][dz]
                 const int dzl = (zs - oz - tau + 1) & (PZ - 1);
-                const bool oky_ = has_yc && j < WXk;
-                const unsigned oy_ = (sls * step_f + (unsigned)j * LS + (unsigned)dzl) * 4u;
-                const unsigned oyc_ = (sls * step_c3 + (unsigned)j * LS + (unsigned)dzl) * 4u;
 #pragma unroll
-                for (int q = Q0; q < Q0 + NQ; ++q) {
-                    if (q < 6)
-                        bst<SP>(rry, oky_ ? oy_ + (unsigned)q * cb : kOOB, ytr[q][j][zs]);
-                    else
-                        bst<SP>(rryc, oky_ ? oyc_ + (unsigned)(q - 6) * cb : kOOB, ytr[q][j][zs]);
-                }
-                // (dropped offsets when there is no consumer: no branch)
-                const unsigned oz_ = (sls * step_f + (unsigned)j * LS + (unsigned)zs) * 4u;
-                const unsigned oc_ = (sls * step_c + (unsigned)j * LS + (unsigned)zs) * 4u;
+                for (int k = 0; k < NG; ++k) {
+                    const int j = 4 * (w + NW * k) + r;
+                    const int jl = min(j, YR - 1);
+                    // y face (the first y row) as [x register][dz]
+                    const bool oky_ = has_yc && j < WXk;
+                    const unsigned oy_ = (sls * step_fyz + (unsigned)j * 16u + (unsigned)dzl) * 4u;
+                    const unsigned oyc_ = (sls * step_c3y + (unsigned)j * 16u + (unsigned)dzl) * 4u;
 #pragma unroll
-                for (int q = Q0; q < Q0 + NQZ; ++q) {
-                    if (q < 6)
-                        bst<SP>(rrz, has_consumer ? oz_ + (unsigned)q * cb : kOOB, ztr[q][j][zs]);
-                    else
-                        bst<SP>(rrc, has_consumer ? oc_ + (unsigned)(q - 6) * cb : kOOB, ztr[q][j][zs]);
+                    for (int q = Q0; q < Q0 + NQ; ++q) {
+                        if (q < 6)
+                            bst<SP>(rry, oky_ ? oy_ + (unsigned)q * cbyz : kOOB, ytr[q - Q0][jl][zs]);
+                        else
+                            bst<SP>(rryc, oky_ ? oyc_ + (unsigned)(q - 6) * cbyz : kOOB, ytr[q - Q0][jl][zs]);
+                    }
+                    // z face as [x register][y slot] (dropped offsets when
+                    // there is no consumer: no branch)
+                    const bool okz_ = has_consumer && j < WXk;
+                    const unsigned oz_ = (sls * step_fyz + (unsigned)j * 16u + (unsigned)zs) * 4u;
+                    const unsigned oc_ = (sls * step_c + (unsigned)j * 16u + (unsigned)zs) * 4u;
+#pragma unroll
+                    for (int q = Q0; q < Q0 + NQZ; ++q) {
+                        if (q < 6)
+                            bst<SP>(rrz, okz_ ? oz_ + (unsigned)q * cbyz : kOOB, ztr[q - Q0][jl][zs]);
+                        else
+                            bst<SP>(rrc, okz_ ? oc_ + (unsigned)(q - 6) * cbyz : kOOB, ztr[q - Q0][jl][zs]);
+                    }
                 }
             };
             auto ensure_up = [&](unsigned level) -> bool {
@@ -876,7 +925,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             // periodic variant, short of registers already, would spill.)
             const bool skip = !PER && (ox + tau + WXk - 1 < 0 || oy + tau + WY - 1 < 0 || oz + tau + WZ - 1 < 0);
             // offset of this lane's cell in the x face ring block
-            const unsigned ox_ = (sls * step_f + (unsigned)dy * LS + (unsigned)dz) * 4u;
+            const unsigned ox_ = (sls * step_fx + (unsigned)dy * 16u + (unsigned)dz) * 4u;
 
             // ================= E half-step (H frame: register j <-> x = ox+tau-1+j)
             const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
@@ -901,15 +950,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                         const float e0 = LOSSY ? CA[0][j] * E[0][j] : E[0][j];
                         const float e1 = LOSSY ? CA[1][j] * E[1][j] : E[1][j];
                         const float e2 = LOSSY ? CA[2][j] * E[2][j] : E[2][j];
-                        const float ex = (e0 + C[0][j] * (H[2][j] - hz_ym)) - C[0][j] * (H[1][j] - hy_zm);
-                        const float ey = (e1 + C[1][j] * (H[0][j] - hx_zm)) - C[1][j] * (H[2][j] - H[2][j - 1]);
-                        const float ez = (e2 + C[2][j] * (H[1][j] - H[1][j - 1])) - C[2][j] * (H[0][j] - hx_ym);
+                        float c0, c1, c2;
+                        if (IDR) {
+                            const float4 t4 = s_tab[ID[j]];
+                            c0 = t4.x;
+                            c1 = t4.y;
+                            c2 = t4.z;
+                        } else {
+                            c0 = C[0][j];
+                            c1 = C[1][j];
+                            c2 = C[2][j];
+                        }
+                        const float ex = (e0 + c0 * (H[2][j] - hz_ym)) - c0 * (H[1][j] - hy_zm);
+                        const float ey = (e1 + c1 * (H[0][j] - hx_zm)) - c1 * (H[2][j] - H[2][j - 1]);
+                        const float ez = (e2 + c2 * (H[1][j] - H[1][j - 1])) - c2 * (H[0][j] - hx_ym);
                         E[0][j - 1] = ex;
                         E[1][j - 1] = ey;
                         E[2][j - 1] = ez;
+                        if (IDR) ID[j - 1] = ID[j];
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
-                            C[q][j - 1] = C[q][j];
+                            if (!IDR) C[q][j - 1] = C[q][j];
                             if (LOSSY) CA[q][j - 1] = CA[q][j];
                         }
                     }
@@ -968,7 +1029,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             if (!skip) {
                 // E of the first x layer of the tile (every lane: slot [dy][dz])
 #pragma unroll
-                for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)q * cb : kOOB, E[q][0]);
+                for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)q * cbx : kOOB, E[q][0]);
                 if (dy == 1) {
 #pragma unroll
                     for (int j = 0; j < WXk; ++j)
@@ -979,7 +1040,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
 #pragma unroll
-                        for (int j = 0; j < WXk; ++j) ztr[q][dy1][j] = E[q][j];
+                        for (int j = 0; j < WXk; ++j) ztr[q][j][dy1] = E[q][j];
                 }
                 store_faces(std::integral_constant<int, 0>(), std::integral_constant<int, 3>(), std::integral_constant<int, 3>());
                 // (lazy: the early prefetch lands; this half-step's stores may fly on)
@@ -1028,7 +1089,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
-                    for (int j = 0; j < WXk; ++j) E[q][j] = zst[q][dy1][j];
+                    for (int j = 0; j < WXk; ++j) E[q][j] = zst[q][j][dy1];
             }
             if (!PER || wxr == WXk) {
 #pragma unroll
@@ -1073,19 +1134,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 
                 // H (and, on the z face, the coefficients) of the first layer
 #pragma unroll
-                for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)(3 + q) * cb : kOOB, H[q][0]);
+                for (int q = 0; q < 3; ++q) bst<SP>(rrx, has_xc ? ox_ + (unsigned)(3 + q) * cbx : kOOB, H[q][0]);
                 if (F16 && !MAT) {
-                    const unsigned oxc_ = (sls * step_c3 + (unsigned)dy * LS + (unsigned)dz) * 4u;
+                    const unsigned oxc_ = (sls * step_c3x + (unsigned)dy * 16u + (unsigned)dz) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) bst<SP>(rrxc, has_xc ? oxc_ + (unsigned)q * cb : kOOB, C[q][0]);
+                    for (int q = 0; q < 3; ++q) bst<SP>(rrxc, has_xc ? oxc_ + (unsigned)q * cbx : kOOB, C[q][0]);
                 }
                 if (dy == 1) {
 #pragma unroll
                     for (int j = 0; j < WXk; ++j)
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
-                            ytr[3 + q][j][zs] = H[q][j];
-                            if (F16 && !MAT) ytr[6 + q][j][zs] = C[q][j];
+                            ytr[q][j][zs] = H[q][j];
+                            if (F16 && !MAT) ytr[3 + q][j][zs] = C[q][j];
                         }
                 }
                 if (dz == 1) {
@@ -1093,9 +1154,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                     for (int q = 0; q < 3; ++q)
 #pragma unroll
                         for (int j = 0; j < WXk; ++j) {
-                            ztr[3 + q][dy1][j] = H[q][j];
-                            ztr[6 + q][dy1][j] = C[q][j];
-                            if (LOSSY) ztr[9 + q][dy1][j] = CA[q][j];
+                            ztr[q][j][dy1] = H[q][j];
+                            if (IDR) {
+                                if (q == 0) ztr[3][j][dy1] = __builtin_bit_cast(float, ID[j]);
+                            } else {
+                                ztr[3 + q][j][dy1] = C[q][j];
+                            }
+                            if (LOSSY) ztr[6 + q][j][dy1] = CA[q][j];
                         }
                 }
                 store_faces(std::integral_constant<int, 3>(), std::integral_constant<int, NQY - 3>(),
@@ -1149,15 +1214,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 complete_loads();
             }
 
-            // forward shell's H^(tau+1/2) and coefficients into the registers
+            // forward shell's H^(tau+1/2) and coefficients (or indices) into
+            // the registers
+            auto tab = [&](unsigned id, int q) -> float {
+                const float4 t4 = s_tab[id];
+                return q == 0 ? t4.x : (q == 1 ? t4.y : t4.z);
+            };
             if (dy == fy) {
 #pragma unroll
                 for (int j = 0; j < WXk; ++j) {
                     const unsigned id = MAT ? (__builtin_bit_cast(unsigned, yst[6][j][zs]) & (unsigned)(kMaxMaterials - 1)) : 0u;
+                    if (IDR) ID[j] = id;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         H[q][j] = yst[3 + q][j][zs];
-                        C[q][j] = MAT ? s_tab[3 * id + q] : yst[6 + q][j][zs];
+                        if (!IDR) C[q][j] = MAT ? tab(id, q) : yst[6 + q][j][zs];
                         if (LOSSY) CA[q][j] = yst[9 + q][j][zs];
                     }
                 }
@@ -1166,28 +1237,37 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
                     for (int j = 0; j < WXk; ++j) {
-                        H[q][j] = zst[3 + q][dy1][j];
-                        C[q][j] = zst[6 + q][dy1][j];
-                        if (LOSSY) CA[q][j] = zst[9 + q][dy1][j];
+                        H[q][j] = zst[3 + q][j][dy1];
+                        if (IDR) {
+                            if (q == 0) ID[j] = __builtin_bit_cast(unsigned, zst[6][j][dy1]) & (unsigned)(kMaxMaterials - 1);
+                        } else {
+                            C[q][j] = zst[6 + q][j][dy1];
+                        }
+                        if (LOSSY) CA[q][j] = zst[9 + q][j][dy1];
                     }
             }
             const unsigned xid = MAT ? (__builtin_bit_cast(unsigned, xst[6][ys][zs]) & (unsigned)(kMaxMaterials - 1)) : 0u;
             if (!PER || wxr == WXk) {
+                if (IDR) ID[WXk] = xid;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     H[q][WXk] = xst[3 + q][ys][zs];
-                    C[q][WXk] = MAT ? s_tab[3 * xid + q] : xst[6 + q][ys][zs];
+                    if (!IDR) C[q][WXk] = MAT ? tab(xid, q) : xst[6 + q][ys][zs];
                     if (LOSSY) CA[q][WXk] = xst[9 + q][ys][zs];
                 }
             } else {
+                if (IDR) {
+#pragma unroll
+                    for (int j = 0; j < WXk; ++j) ID[j] = j == wxr ? xid : ID[j];
+                }
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    const float vh = xst[3 + q][ys][zs], vc = MAT ? s_tab[3 * xid + q] : xst[6 + q][ys][zs];
+                    const float vh = xst[3 + q][ys][zs], vc = (MAT && !IDR) ? tab(xid, q) : (IDR ? 0.f : xst[6 + q][ys][zs]);
                     const float va = LOSSY ? xst[9 + q][ys][zs] : 0.f;
 #pragma unroll
                     for (int j = 0; j < WXk; ++j) {
                         H[q][j] = j == wxr ? vh : H[q][j];
-                        C[q][j] = j == wxr ? vc : C[q][j];
+                        if (!IDR) C[q][j] = j == wxr ? vc : C[q][j];
                         if (LOSSY) CA[q][j] = j == wxr ? va : CA[q][j];
                     }
                 }
@@ -1281,10 +1361,12 @@ void free_launch(SystolicState* s)
 
 // updated cells along x of a tile of this context: conductive grids use the
 // narrower register tile that leaves room for the per-cell decay
-// (a lossless FP32 context may ask for the narrow tile too: FDTD_OPT_TILE_X)
+// (a lossless FP32 context may ask for the narrow tile too, or for the
+// 19-wide one, which needs material indices: FDTD_OPT_TILE_X)
 int tile_x(const fdtd_ctx* c)
 {
-    return (c->ca[0] || (c->tile_narrow && c->storage == FDTD_FP32)) ? WX_LOSSY : WX;
+    if (c->ca[0]) return WX_LOSSY;
+    return (c->tile_wx == WX_LOSSY || c->tile_wx == WX_WIDE) && c->storage == FDTD_FP32 ? c->tile_wx : WX;
 }
 
 void tile_of(const fdtd_ctx* c, int W[3])
@@ -1475,31 +1557,41 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     // material indices when every member has them (and allows them)
     bool mat = !lossy;
     for (int i = 0; i < n && mat; ++i) mat = cs[i]->use_mat && cs[i]->nmat > 0 && cs[i]->mat_id;
-    // the narrow tile on a lossless FP32 grid (every member shares the width)
-    const bool narrow = !lossy && !h16 && tile_x(lead) == WX_LOSSY;
-    // variants: [sync][periodic][FP32, conductive, FP16 storage, FP32 with
-    // material indices, the last two with the narrow tile, FP16 storage with
-    // material indices (the last three: device-scope synchronisation only)]
-    using Kern = void (*)(SysArgs);
-    static const Kern kernels[2][2][7] = {
-        {{systolic_kernel<kNW, false, false, false, false, false, false>, systolic_kernel<kNW, false, false, true, false, false, false>,
-          systolic_kernel<kNW, false, false, false, true, false, false>, systolic_kernel<kNW, false, false, false, false, true, false>,
-          nullptr, nullptr, nullptr},
-         {systolic_kernel<kNW, false, true, false, false, false, false>, systolic_kernel<kNW, false, true, true, false, false, false>,
-          systolic_kernel<kNW, false, true, false, true, false, false>, systolic_kernel<kNW, false, true, false, false, true, false>,
-          nullptr, nullptr, nullptr}},
-        {{systolic_kernel<kNW, true, false, false, false, false, false>, systolic_kernel<kNW, true, false, true, false, false, false>,
-          systolic_kernel<kNW, true, false, false, true, false, false>, systolic_kernel<kNW, true, false, false, false, true, false>,
-          systolic_kernel<kNW, true, false, false, false, false, true>, systolic_kernel<kNW, true, false, false, false, true, true>,
-          systolic_kernel<kNW, true, false, false, true, true, false>},
-         {systolic_kernel<kNW, true, true, false, false, false, false>, systolic_kernel<kNW, true, true, true, false, false, false>,
-          systolic_kernel<kNW, true, true, false, true, false, false>, systolic_kernel<kNW, true, true, false, false, true, false>,
-          systolic_kernel<kNW, true, true, false, false, false, true>, systolic_kernel<kNW, true, true, false, false, true, true>,
-          systolic_kernel<kNW, true, true, false, true, true, false>}}};
+    // the tile width (every member shares it): 11 on a lossless FP32 grid
+    // when asked for, 19 (indices in registers) with material indices
+    const int wx = tile_x(lead);
+    const bool narrow = !lossy && !h16 && wx == WX_LOSSY;
+    const bool wide = wx == WX_WIDE;
     // (FP16 storage with material indices: device-scope synchronisation only;
     // the fence variant streams the binary16 coefficients)
     if (h16 && !dev) mat = false;
-    const int var = h16 ? (mat ? 6 : 2) : (lossy ? 1 : (mat ? 3 : 0)) + (narrow ? (mat ? 2 : 4) : 0);
+    if (wide && !(mat && dev))
+        return fail(lead, FDTD_EUNSUPPORTED,
+                    "systolic: the 19-wide tile needs material indices (at most 256 coefficient triples, "
+                    "FDTD_OPT_MATERIAL_IDS) and device-scope synchronisation");
+    // (a periodic x axis wraps positions once per access: it needs at least
+    // as many cells as the tile has x slots)
+    for (int i = 0; i < n; ++i)
+        if (cs[i]->sys->pl.per[0] && cs[i]->nx < wx + 1)
+            return fail(lead, FDTD_EUNSUPPORTED,
+                        "systolic: a periodic x axis needs at least " + std::to_string(wx + 1) +
+                            " cells with a " + std::to_string(wx) + "-wide tile");
+    // variants: [sync][periodic][FP32, conductive, FP16 storage, FP32 with
+    // material indices, the next two with the 11-wide tile, FP16 storage with
+    // material indices, material indices with the 19-wide tile (the last
+    // four: device-scope synchronisation only)]
+    using Kern = void (*)(SysArgs);
+#define FDTD_SYS_ROW(D, P)                                                                                  \
+    {systolic_kernel<kNW, D, P, false, false, false, WX>, systolic_kernel<kNW, D, P, true, false, false, WX_LOSSY>, \
+     systolic_kernel<kNW, D, P, false, true, false, WX>, systolic_kernel<kNW, D, P, false, false, true, WX>,       \
+     D ? systolic_kernel<kNW, D, P, false, false, false, WX_LOSSY> : nullptr,                                   \
+     D ? systolic_kernel<kNW, D, P, false, false, true, WX_LOSSY> : nullptr,                                    \
+     D ? systolic_kernel<kNW, D, P, false, true, true, WX> : nullptr,                                           \
+     D ? systolic_kernel<kNW, D, P, false, false, true, WX_WIDE> : nullptr}
+    static const Kern kernels[2][2][8] = {{FDTD_SYS_ROW(false, false), FDTD_SYS_ROW(false, true)},
+                                          {FDTD_SYS_ROW(true, false), FDTD_SYS_ROW(true, true)}};
+#undef FDTD_SYS_ROW
+    const int var = wide ? 7 : h16 ? (mat ? 6 : 2) : (lossy ? 1 : (mat ? 3 : 0)) + (narrow ? (mat ? 2 : 4) : 0);
     const Kern kern = kernels[dev][anyper][var];
     if (!kern) return fail(lead, FDTD_EUNSUPPORTED, "systolic: the narrow tile needs device-scope synchronisation");
     hipError_t e;
@@ -1530,15 +1622,22 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     const int R = std::max(1, std::min(L->up_D + 2 * grid, nt));
     // four face rings in one allocation (x, y, z faces of E and H; the z
     // face's coefficients), each addressed with 32-bit offsets
-    const size_t face = (size_t)(4 * kNW) * 16 * sizeof(float);  // one component of one face
-    const size_t rf6 = (size_t)R * Kmax * 6 * face;
-    const size_t rc3 = (size_t)R * Kmax * 3 * face;
+    // (one component of an x face block is 16 x 16 words; of a y or z face
+    // block, one row per x slot rounded up to four, at least 16, x 16)
+    const size_t face = (size_t)(4 * kNW) * 16 * sizeof(float);
+    const size_t face_yz = (size_t)std::max(16, (wx + 1 + 3) & ~3) * 16 * sizeof(float);
+    const size_t rf6 = (size_t)R * Kmax * 6 * face_yz;
+    // the z face's coefficients: cE (with conductivity ca too; with the wide
+    // tile the index alone)
+    const int ncz = lossy ? 6 : (wide ? 1 : 3);
     // (with FP16 storage the x and y faces' coefficients travel on rings of
     // their own, unless material indices replace them)
-    const size_t rb[6] = {rf6, rf6, rf6, lossy ? rf6 : rc3, (h16 && !mat) ? rc3 : 0, (h16 && !mat) ? rc3 : 0};
+    const size_t rb[6] = {(size_t)R * Kmax * 6 * face, rf6, rf6, (size_t)R * Kmax * ncz * face_yz,
+                          (h16 && !mat) ? (size_t)R * Kmax * 3 * face : 0,
+                          (h16 && !mat) ? (size_t)R * Kmax * 3 * face_yz : 0};
     if (rf6 >= ((size_t)1 << 32) && lead->band_steps == 0 && Kmax > 1) {
         // an automatic band: take the longest one whose rings fit
-        const size_t per_step = (size_t)R * 6 * face;
+        const size_t per_step = (size_t)R * 6 * face_yz;
         const int fit = (int)std::min<size_t>((((size_t)1 << 32) - 1) / per_step, (size_t)Kmax - 1);
         return launch(cs, n, nsteps, std::max(1, fit), run);
     }

@@ -6,6 +6,7 @@
   the FP32 oracle after 128 steps -- the workload as defined (zero fields),
   and again from random fields so that every ring seam carries data from the
   first step.
+  With the 19-wide tile too (ring groups of 14 x 18 tiles).
 * The batched sweep: 64 PEC grids with axes drawn from {64, 80, ..., 192},
   each with its own permittivity map and dipole, in one persistent launch,
   every member against the FP32 oracle after 160 steps (the workload runs
@@ -51,6 +52,19 @@ def test_periodic_256_cube_systolic_bitwise(noise):
     got, (band, grid) = _run(w, "systolic", 128)
     assert band > 0 and grid >= 18 * 18    # a whole ring group is resident
     assert_bitwise(got, oracle_f32(w, 128), "256^3 periodic x/y (noise=%s)" % noise)
+
+
+def test_periodic_256_cube_wide_tile_bitwise():
+    """The 19-wide tile (material indices in registers): a ring group is then
+    14 x 18 = 252 tiles, so two groups are resident at once; from random
+    fields, against the FP32 oracle after 128 steps."""
+    w = wl.c2_periodic_dielectric(nsteps=128)
+    rng = np.random.default_rng(78)
+    f = [rng.uniform(-0.1, 0.1, size=w.shape).astype(np.float32) for _ in range(6)]
+    w.fields = tuple(wl.zero_pec(f, w.bc))
+    got, (band, grid) = _run(w, "systolic", 128, {fdtd.OPT_TILE_X: 19})
+    assert band > 0 and grid >= 2 * 14 * 18
+    assert_bitwise(got, oracle_f32(w, 128), "256^3 periodic x/y, 19-wide tile")
 
 
 def test_periodic_256_cube_systolic_split_calls_and_band():

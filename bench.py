@@ -79,14 +79,16 @@ def systolic_bytes_per_update(tile, band, conductive=False, fp16=False, material
     and in, the coefficients in (60 B per cell in FP32, 72 B when conductive,
     30 B with FP16 storage).  With material indices the x and y faces and
     the band start read the 4-byte index instead of the coefficients (the z
-    face still carries the 12 B of values)."""
+    face still carries the 12 B of values, except with the 19-wide tile,
+    whose registers and z face hold the index)."""
     wx, wy, wz = tile
     axy, v = wx * wy, wx * wy * wz
     c = 24 if conductive else 12            # coefficient bytes per cell (FP32)
     if materials:
         # (the faces travel in FP32 whatever the storage; the band's state is
         # E and H in the stored format and the index)
-        per_step = (wy * wz + wx * wz) * (24 + 4 + 24) + axy * (24 + c) * 2
+        cz = 4 if wx == 19 else c
+        per_step = (wy * wz + wx * wz) * (24 + 4 + 24) + axy * (24 + cz) * 2
         return per_step / v + (2 * (12 if fp16 else 24) + 4) / band
     if fp16:
         per_step = (wy * wz + wx * wz + axy) * (24 + c) * 2
@@ -569,7 +571,8 @@ def main():
         flops = FLOPS_PER_CELL * updates / avg_s / 1e12
         launch = {"workload": w.name + ("_conductive" if sigma is not None else "")
                   + ("_fp16" if args.storage == "fp16" else ""),
-                  "steps": int(round(steps_per_launch)), "band": band, "materials": int(mats)}
+                  "steps": int(round(steps_per_launch)), "band": band, "materials": int(mats),
+                  "tile_x": stats["info"]["tile"][0]}
         traffic = counter_traffic("systolic_kernel", "paper_2502_20610_amd/csrc/systolic.hip",
                                   dict(launch, cells=cells))
         # arithmetic intensity 36 / b_alg flop/B is below the machine balance

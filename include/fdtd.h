@@ -389,9 +389,16 @@ enum {
                                  launch per kernel.  Same results; per-kernel
                                  timing (FDTD_OPT_PROFILE) launches directly. */
     FDTD_OPT_TILE_X = 7,      /* systolic: updated cells per tile along x on a
-                                 lossless FP32 grid, 15 or 11 (0 = default, 15;
-                                 conductive grids always take 11, FP16 storage
-                                 15).  A batch needs one width for all.        */
+                                 lossless FP32 grid, 15, 11 or 19.  19 holds
+                                 the material indices in registers: it needs
+                                 them (FDTD_INFO_MATERIALS > 0), device-scope
+                                 synchronisation and, on a periodic x axis,
+                                 at least 20 cells, else the step returns
+                                 FDTD_EUNSUPPORTED.  0 = default: 19 when
+                                 every member of the launch allows it, else
+                                 15.  Conductive grids always take 11, FP16
+                                 storage 15.  A batch needs one width for
+                                 all.                                          */
     FDTD_OPT_AUTOTUNE_PLAIN = 8 /* 1 = fdtd_autotune also times the plain
                                  two-launch scheme (FP32 storage only, where
                                  every scheme gives the same bits) and switches
@@ -407,7 +414,8 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value);
  * subdomain size and steps per exchange that Section 4 fixes by hand for one
  * GPU) by timing the candidates on this context's grid, for calls of nsteps
  * steps (runs of min(nsteps, 64) steps): widths 15 and 11 on lossless FP32
- * grids (11 when conductive, 15 with FP16 storage), bands of 8, 12, 16, 24,
+ * grids, and 19 when the grid has material indices (11 when conductive, 15
+ * with FP16 storage), bands of 8, 12, 16, 24,
  * 32, 48, 64 steps and the run length itself, each run twice from the
  * current state.  The fields and step count are restored after every run
  * (a device copy of the six field arrays is held meanwhile), and the
@@ -443,7 +451,7 @@ enum {
     FDTD_INFO_SYSTOLIC_TICKETS = 2,/* (band, tile) tickets of the last systolic launch    */
     FDTD_INFO_RING_SLOTS = 3,      /* face-ring slots of the last systolic launch        */
     FDTD_INFO_TILE_X = 4,          /* updated cells per systolic tile along x, y, z (x:  */
-                                   /* 15, or 11 for a context with conductivity)         */
+                                   /* 15, 11 or 19: FDTD_OPT_TILE_X; y and z: 15)         */
     FDTD_INFO_TILE_Y = 5,
     FDTD_INFO_TILE_Z = 6,
     FDTD_INFO_MATERIALS = 7,       /* entries of the context's material table, entry 0 */

@@ -93,7 +93,8 @@ struct fdtd_ctx {
     float* mat_tab;   // kMaxMaterials x 3 floats, entry 0 = (+0, +0, +0)
     int nmat;
     bool use_mat;     // FDTD_OPT_MATERIAL_IDS
-    int tile_wx;      // FDTD_OPT_TILE_X: 0 (default, 15), 11 or 19 on a lossless FP32 grid
+    int tile_wx;      // FDTD_OPT_TILE_X: 0 (the launch's default), 11, 15 or 19
+    int auto_wx;      // the default width of the last systolic launch (19 or 15; 0 before)
     bool tune_plain;  // FDTD_OPT_AUTOTUNE_PLAIN
 
     // plain schemes: step loops replayed as a HIP graph (FDTD_OPT_GRAPHS)

@@ -1362,11 +1362,14 @@ void free_launch(SystolicState* s)
 // updated cells along x of a tile of this context: conductive grids use the
 // narrower register tile that leaves room for the per-cell decay
 // (a lossless FP32 context may ask for the narrow tile too, or for the
-// 19-wide one, which needs material indices: FDTD_OPT_TILE_X)
+// 19-wide one, which needs material indices: FDTD_OPT_TILE_X; without a
+// request the launch picks 19 when its members allow it, else 15)
 int tile_x(const fdtd_ctx* c)
 {
     if (c->ca[0]) return WX_LOSSY;
-    return (c->tile_wx == WX_LOSSY || c->tile_wx == WX_WIDE) && c->storage == FDTD_FP32 ? c->tile_wx : WX;
+    if (c->storage != FDTD_FP32) return WX;
+    if (c->tile_wx == WX_LOSSY || c->tile_wx == WX_WIDE || c->tile_wx == WX) return c->tile_wx;
+    return c->auto_wx == WX_WIDE ? WX_WIDE : WX;  // (the last launch's default)
 }
 
 void tile_of(const fdtd_ctx* c, int W[3])
@@ -1527,6 +1530,20 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
         if (tile_x(cs[i]) != tile_x(lead))
             return fail(lead, FDTD_EUNSUPPORTED, "systolic batch: every member needs the same tile width");
     }
+    // synchronisation variant: device-scope accesses (default) or cached
+    // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
+    const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
+    const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
+    // The default tile width: 19 when every member can hold material indices
+    // in registers (lossless FP32 grids with at most 256 coefficient triples
+    // whose periodic x axes, if any, have 20 cells or more), else 15.  A
+    // member that asked for a width keeps it (and a batch still needs one
+    // width for all).
+    bool wide_ok = !lossy && !h16 && dev;
+    for (int i = 0; i < n && wide_ok; ++i)
+        wide_ok = cs[i]->use_mat && cs[i]->nmat > 0 && cs[i]->mat_id &&
+                  !(cs[i]->cfg.bc[0] == FDTD_BC_PERIODIC && cs[i]->nx < WX_WIDE + 1);
+    for (int i = 0; i < n; ++i) cs[i]->auto_wx = wide_ok ? WX_WIDE : WX;
     // band length per simulation: the lead's option for all, else each
     // simulation's own choice of the cost model
     int Kmax = 1;
@@ -1550,10 +1567,6 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     bool anyper = false;
     for (int i = 0; i < n; ++i) anyper = anyper || cs[i]->sys->pl.per[0] || cs[i]->sys->pl.per[1] || cs[i]->sys->pl.per[2];
 
-    // synchronisation variant: device-scope accesses (default) or cached
-    // accesses with agent-scope fences (FDTD_SYSTOLIC_SYNC=fence)
-    const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
-    const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
     // material indices when every member has them (and allows them)
     bool mat = !lossy;
     for (int i = 0; i < n && mat; ++i) mat = cs[i]->use_mat && cs[i]->nmat > 0 && cs[i]->mat_id;

@@ -44,6 +44,12 @@ def test_systolic_algorithmic_bytes_follow_the_face_and_band_formula():
     # this design with indices: x and y faces read the index, the z face keeps the values
     assert bench.systolic_bytes_per_update((15, 15, 15), 20, materials=True) == pytest.approx(
         (2 * 225 * 52 + 225 * 72) / 3375 + 52 / 20)
+    # the 19-wide tile: A = 225 + 285 + 285, V = 4275; its z face carries the
+    # index (4 B) instead of the three coefficient values
+    assert bench.systolic_alg_bytes_per_update((19, 15, 15), 20, materials=True) == pytest.approx(
+        52 * 795 / 4275 + 52 / 20)
+    assert bench.systolic_bytes_per_update((19, 15, 15), 20, materials=True) == pytest.approx(
+        (510 * 52 + 285 * 56) / 4275 + 52 / 20)
     # the paper's 31x15x15 block: A = 225 + 465 + 465
     assert bench.systolic_alg_bytes_per_update((31, 15, 15), 64) == pytest.approx(
         60 * 1155 / 6975 + 60 / 64)

@@ -1,8 +1,8 @@
 """Parity of the workload configurations at their stated sizes, every element.
 
 * 256^3 with periodic x and y and PEC z (40 boxes of eps 12.25 in 2.08, a
-  central Ez dipole): the systolic scheme, whose ring groups are whole
-  18 x 18-tile z-layers with a ragged last tile (256 = 17 * 15 + 1), against
+  central Ez dipole): the systolic scheme on the 15-wide tile, whose ring
+  groups are whole 18 x 18-tile z-layers with a ragged last tile (256 = 17 * 15 + 1), against
   the FP32 oracle after 128 steps -- the workload as defined (zero fields),
   and again from random fields so that every ring seam carries data from the
   first step.
@@ -49,7 +49,7 @@ def test_periodic_256_cube_systolic_bitwise(noise):
         rng = np.random.default_rng(77)
         f = [rng.uniform(-0.1, 0.1, size=w.shape).astype(np.float32) for _ in range(6)]
         w.fields = tuple(wl.zero_pec(f, w.bc))
-    got, (band, grid) = _run(w, "systolic", 128)
+    got, (band, grid) = _run(w, "systolic", 128, {fdtd.OPT_TILE_X: 15})
     assert band > 0 and grid >= 18 * 18    # a whole ring group is resident
     assert_bitwise(got, oracle_f32(w, 128), "256^3 periodic x/y (noise=%s)" % noise)
 

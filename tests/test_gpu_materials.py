@@ -32,10 +32,11 @@ if not _gpu_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 
-def _run(w, ids=True, eps=None, steps=None):
+def _run(w, ids=True, eps=None, steps=None, wx=0):
     sim = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic")
     try:
         sim.set_option(fdtd.OPT_MATERIAL_IDS, 1 if ids else 0)
+        sim.set_option(fdtd.OPT_TILE_X, wx)
         sim.set_materials(w.eps if eps is None else eps)
         if w.fields is not None:
             sim.set_fields(w.fields)
@@ -61,9 +62,10 @@ def _distinct_triples(w):
 def test_indices_and_arrays_both_bitwise(bc):
     w = wl.small_case((47, 38, 41), bc, seed=31 + bc[0] + 2 * bc[1], nsteps=21, dipoles=[(23, 19, 20)])
     ref = oracle_f32(w)
-    got, nmat = _run(w, ids=True)
-    assert nmat == _distinct_triples(w)
-    assert_bitwise(got, ref, "material indices %s" % (bc,))
+    for wx in (0, 15):   # the default (19-wide: indices in registers) and 15-wide
+        got, nmat = _run(w, ids=True, wx=wx)
+        assert nmat == _distinct_triples(w)
+        assert_bitwise(got, ref, "material indices %s wx=%d" % (bc, wx))
     got, _ = _run(w, ids=False)
     assert_bitwise(got, ref, "coefficient arrays %s" % (bc,))
 

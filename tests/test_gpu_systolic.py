@@ -30,6 +30,8 @@ def run_sys(w, nsteps=None, **opts):
         o[fdtd.OPT_BAND_STEPS] = opts["band"]
     if "wg" in opts:
         o[fdtd.OPT_WORKGROUPS] = opts["wg"]
+    if opts.get("wx"):
+        o[fdtd.OPT_TILE_X] = opts["wx"]
     return fdtd.run_workload(w, "systolic", nsteps=nsteps, options=o)
 
 
@@ -42,7 +44,8 @@ def run_sys(w, nsteps=None, **opts):
     ((1, 30, 30), 6, 3, 6),          # one-cell-thick axis
     ((45, 45, 45), 33, 10, 7),
 ])
-def test_systolic_bitwise_small(shape, nsteps, band, seed):
+@pytest.mark.parametrize("wx", [0, 15])   # the default (19 with material indices) and 15
+def test_systolic_bitwise_small(shape, nsteps, band, seed, wx):
     dips = [tuple(s // 2 for s in shape)]
     # sources on tile edges and corners of the initial tiling
     for p in [(15, 15, 15), (14, 1, 29), (1, 16, 1)]:
@@ -50,7 +53,7 @@ def test_systolic_bitwise_small(shape, nsteps, band, seed):
             dips.append(p)
     dips = [d for d in dips if d[0] >= 1 and d[1] >= 1]
     w = wl.small_case(shape, (PEC, PEC, PEC), seed=seed, nsteps=nsteps, dipoles=dips)
-    assert_bitwise(run_sys(w, band=band), oracle_f32(w), "systolic %s" % (shape,))
+    assert_bitwise(run_sys(w, band=band, wx=wx), oracle_f32(w), "systolic %s wx=%d" % (shape, wx))
 
 
 @pytest.mark.parametrize("wg", [1, 2, 7, 64])
@@ -103,13 +106,14 @@ def test_systolic_split_calls_and_scheme_switch():
     ((64, 64, 30), (PER, PER, PEC), 40, 6, 25),     # the boundary pattern of the C2 workload
     ((30, 30, 30), (PER, PER, PER), 12, 1, 26),     # rings with no ragged tile, band of 1
 ])
-def test_systolic_periodic_bitwise(shape, bc, nsteps, band, seed):
+@pytest.mark.parametrize("wx", [0, 15])
+def test_systolic_periodic_bitwise(shape, bc, nsteps, band, seed, wx):
     # dipoles at the interior, on tile edges and across the periodic seams
     pts = [tuple(s // 2 for s in shape), (0, 15, 14), (shape[0] - 1, 1, shape[2] - 1), (15, 0, 0)]
     dips = [p for p in pts if all(bc[a] == PER or p[a] >= 1 for a in (0, 1))
             and all(p[a] < shape[a] for a in range(3))]
     w = wl.small_case(shape, bc, seed=seed, nsteps=nsteps, dipoles=dips)
-    assert_bitwise(run_sys(w, band=band), oracle_f32(w), "systolic periodic %s %s" % (shape, bc))
+    assert_bitwise(run_sys(w, band=band, wx=wx), oracle_f32(w), "systolic periodic %s %s wx=%d" % (shape, bc, wx))
 
 
 def test_systolic_periodic_ring_group_needs_resident_grid():

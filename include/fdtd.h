@@ -389,16 +389,16 @@ enum {
                                  launch per kernel.  Same results; per-kernel
                                  timing (FDTD_OPT_PROFILE) launches directly. */
     FDTD_OPT_TILE_X = 7,      /* systolic: updated cells per tile along x on a
-                                 lossless FP32 grid, 15, 11 or 19.  19 holds
+                                 lossless grid, 15, 11 or 19.  19 holds
                                  the material indices in registers: it needs
                                  them (FDTD_INFO_MATERIALS > 0), device-scope
                                  synchronisation and, on a periodic x axis,
                                  at least 20 cells, else the step returns
                                  FDTD_EUNSUPPORTED.  0 = default: 19 when
                                  every member of the launch allows it, else
-                                 15.  Conductive grids always take 11, FP16
-                                 storage 15.  A batch needs one width for
-                                 all.                                          */
+                                 15.  Conductive grids always take 11; FP16
+                                 storage takes 15 or 19.  A batch needs one
+                                 width for all.                                */
     FDTD_OPT_AUTOTUNE_PLAIN = 8 /* 1 = fdtd_autotune also times the plain
                                  two-launch scheme (FP32 storage only, where
                                  every scheme gives the same bits) and switches
@@ -415,7 +415,7 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value);
  * GPU) by timing the candidates on this context's grid, for calls of nsteps
  * steps (runs of min(nsteps, 64) steps): widths 15 and 11 on lossless FP32
  * grids, and 19 when the grid has material indices (11 when conductive, 15
- * with FP16 storage), bands of 8, 12, 16, 24,
+ * and 19 with FP16 storage), bands of 8, 12, 16, 24,
  * 32, 48, 64 steps and the run length itself, each run twice from the
  * current state.  The fields and step count are restored after every run
  * (a device copy of the six field arrays is held meanwhile), and the

@@ -63,15 +63,14 @@ int autotune_run(fdtd_ctx* ctx, int64_t nsteps, int64_t* out_tile, int64_t* out_
     }
     const bool h16 = ctx->storage == FDTD_FP16_STORAGE;
     const bool lossy = ctx->ca[0] != nullptr;
+    const bool ids = ctx->use_mat && ctx->nmat > 0 && ctx->mat_id;  // (the 19-wide tile needs them)
     std::vector<int> widths;
     if (lossy)
         widths = {11};
     else if (h16)
-        widths = {15};
-    else if (ctx->use_mat && ctx->nmat > 0 && ctx->mat_id)
-        widths = {15, 11, 19};  // (the 19-wide tile needs material indices)
+        widths = ids ? std::vector<int>{15, 19} : std::vector<int>{15};
     else
-        widths = {15, 11};
+        widths = ids ? std::vector<int>{15, 11, 19} : std::vector<int>{15, 11};
     std::vector<int> bands;
     for (int K : {8, 12, 16, 24, 32, 48, 64})
         if (K < probe) bands.push_back(K);

@@ -946,8 +946,8 @@ int fdtd_set_option(fdtd_ctx* ctx, int option, int64_t value)
     case FDTD_OPT_TILE_X:
         if (value != 0 && value != 11 && value != 15 && value != 19)
             return fail(ctx, FDTD_EINVAL, "set_option: tile width is 0 (default), 11, 15 or 19");
-        if ((value == 11 || value == 19) && ctx->storage != FDTD_FP32)
-            return fail(ctx, FDTD_EUNSUPPORTED, "set_option: the 11- and 19-wide tiles need FP32 storage");
+        if (value == 11 && ctx->storage != FDTD_FP32)
+            return fail(ctx, FDTD_EUNSUPPORTED, "set_option: the 11-wide tile needs FP32 storage");
         ctx->tile_wx = (int)value;
         return FDTD_OK;
     case FDTD_OPT_AUTOTUNE_PLAIN:

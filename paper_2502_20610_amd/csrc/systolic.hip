@@ -407,7 +407,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     // otherwise the z face carries the values themselves.
     static_assert(!(MAT && LOSSY), "material indices: lossless grids only");
     constexpr bool IDR = XW == WX_WIDE;
-    static_assert(!IDR || (MAT && !F16), "19-wide tile: material indices, FP32 storage");
+    static_assert(!IDR || MAT, "19-wide tile: material indices");
     constexpr int SP = DEV ? 16 : 0;  // cache policy of shared-data accesses
     constexpr int PY = 4 * NW;
     constexpr int WY = PY - 1;
@@ -1367,8 +1367,8 @@ void free_launch(SystolicState* s)
 int tile_x(const fdtd_ctx* c)
 {
     if (c->ca[0]) return WX_LOSSY;
-    if (c->storage != FDTD_FP32) return WX;
-    if (c->tile_wx == WX_LOSSY || c->tile_wx == WX_WIDE || c->tile_wx == WX) return c->tile_wx;
+    if (c->tile_wx == WX_WIDE || c->tile_wx == WX) return c->tile_wx;
+    if (c->tile_wx == WX_LOSSY && c->storage == FDTD_FP32) return WX_LOSSY;
     return c->auto_wx == WX_WIDE ? WX_WIDE : WX;  // (the last launch's default)
 }
 
@@ -1535,11 +1535,11 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
     const char* sync_env = getenv("FDTD_SYSTOLIC_SYNC");
     const bool dev = !(sync_env && strcmp(sync_env, "fence") == 0);
     // The default tile width: 19 when every member can hold material indices
-    // in registers (lossless FP32 grids with at most 256 coefficient triples
-    // whose periodic x axes, if any, have 20 cells or more), else 15.  A
+    // in registers (lossless grids with at most 256 coefficient triples whose
+    // periodic x axes, if any, have 20 cells or more), else 15.  A
     // member that asked for a width keeps it (and a batch still needs one
     // width for all).
-    bool wide_ok = !lossy && !h16 && dev;
+    bool wide_ok = !lossy && dev;
     for (int i = 0; i < n && wide_ok; ++i)
         wide_ok = cs[i]->use_mat && cs[i]->nmat > 0 && cs[i]->mat_id &&
                   !(cs[i]->cfg.bc[0] == FDTD_BC_PERIODIC && cs[i]->nx < WX_WIDE + 1);
@@ -1591,8 +1591,8 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
                             " cells with a " + std::to_string(wx) + "-wide tile");
     // variants: [sync][periodic][FP32, conductive, FP16 storage, FP32 with
     // material indices, the next two with the 11-wide tile, FP16 storage with
-    // material indices, material indices with the 19-wide tile (the last
-    // four: device-scope synchronisation only)]
+    // material indices, material indices with the 19-wide tile in FP32 and
+    // FP16 storage (the last five: device-scope synchronisation only)]
     using Kern = void (*)(SysArgs);
 #define FDTD_SYS_ROW(D, P)                                                                                  \
     {systolic_kernel<kNW, D, P, false, false, false, WX>, systolic_kernel<kNW, D, P, true, false, false, WX_LOSSY>, \
@@ -1600,11 +1600,12 @@ int launch(fdtd_ctx* const* cs, int n, int64_t nsteps, int kcap = kMaxBand, bool
      D ? systolic_kernel<kNW, D, P, false, false, false, WX_LOSSY> : nullptr,                                   \
      D ? systolic_kernel<kNW, D, P, false, false, true, WX_LOSSY> : nullptr,                                    \
      D ? systolic_kernel<kNW, D, P, false, true, true, WX> : nullptr,                                           \
-     D ? systolic_kernel<kNW, D, P, false, false, true, WX_WIDE> : nullptr}
-    static const Kern kernels[2][2][8] = {{FDTD_SYS_ROW(false, false), FDTD_SYS_ROW(false, true)},
+     D ? systolic_kernel<kNW, D, P, false, false, true, WX_WIDE> : nullptr,                                     \
+     D ? systolic_kernel<kNW, D, P, false, true, true, WX_WIDE> : nullptr}
+    static const Kern kernels[2][2][9] = {{FDTD_SYS_ROW(false, false), FDTD_SYS_ROW(false, true)},
                                           {FDTD_SYS_ROW(true, false), FDTD_SYS_ROW(true, true)}};
 #undef FDTD_SYS_ROW
-    const int var = wide ? 7 : h16 ? (mat ? 6 : 2) : (lossy ? 1 : (mat ? 3 : 0)) + (narrow ? (mat ? 2 : 4) : 0);
+    const int var = wide ? (h16 ? 8 : 7) : h16 ? (mat ? 6 : 2) : (lossy ? 1 : (mat ? 3 : 0)) + (narrow ? (mat ? 2 : 4) : 0);
     const Kern kern = kernels[dev][anyper][var];
     if (!kern) return fail(lead, FDTD_EUNSUPPORTED, "systolic: the narrow tile needs device-scope synchronisation");
     hipError_t e;

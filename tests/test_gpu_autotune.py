@@ -10,7 +10,7 @@ of tile width and band length (fdtd_autotune).
 * fdtd_autotune leaves the fields and the step count as they were, returns a
   candidate pair, keeps it for a second context of the same key, and the run
   that follows stays bitwise.
-* Refusals: the 11- and 19-wide tiles with FP16 storage, a batch mixing widths.
+* Refusals: the 11-wide tile with FP16 storage, a batch mixing widths.
 """
 import numpy as np
 import pytest
@@ -121,7 +121,7 @@ def test_autotune_with_the_plain_scheme_as_a_candidate():
         h.set_option(fdtd.OPT_AUTOTUNE_PLAIN, 1)
         h.set_materials(w.eps)
         tile, band = h.autotune(16)
-        assert h.info(fdtd.INFO_SCHEME) == fdtd.SCHEME_SYSTOLIC and tile == 15
+        assert h.info(fdtd.INFO_SCHEME) == fdtd.SCHEME_SYSTOLIC and tile in (15, 19)
     finally:
         h.close()
 
@@ -137,10 +137,9 @@ def test_autotune_refusals_and_narrow_tile_refusals():
         plain.close()
     h = fdtd.Simulation(w.shape, w.dt, w.dx, w.bc, scheme="systolic", storage="fp16")
     try:
-        for width in (11, 19):
-            with pytest.raises(fdtd.FdtdError) as e:
-                h.set_option(fdtd.OPT_TILE_X, width)
-            assert e.value.code == fdtd.FDTD_EUNSUPPORTED
+        with pytest.raises(fdtd.FdtdError) as e:
+            h.set_option(fdtd.OPT_TILE_X, 11)
+        assert e.value.code == fdtd.FDTD_EUNSUPPORTED
     finally:
         h.close()
     # the 19-wide tile without material indices, and on a periodic x axis of

@@ -358,12 +358,7 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
                                            unsigned target, int* s_abort, unsigned* s_min)
 {
     const int tid = threadIdx.x;
-    if (s_min) {
-        // every wavefront has finished reading *s_min before it is reset
-        wait_barrier<DEV>();
-        if (tid == 0 && n) *s_min = 0xFFFFFFFFu;
-        wait_barrier<DEV>();
-    }
+    unsigned v = 0xFFFFFFFFu;  // (lanes that poll nothing)
     if (tid < n) {
         int my = idx[0];
 #pragma unroll
@@ -371,7 +366,6 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
             if (tid == k) my = idx[k];
         unsigned* p = A.progress + my;
         long long it = 0;
-        unsigned v;
         while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
             if (++it > A.spin_limit) {
                 atomicOr(A.error, kErrTimeout);
@@ -384,9 +378,18 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        // the lowest progress seen bounds every later wait of this ticket
-        if (s_min) atomicMin(s_min, v);
         if (!DEV) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    // The lowest progress seen bounds every later wait of this ticket: lane 0
+    // of the first wavefront writes the minimum over the polling lanes.  (The
+    // workgroup reads *s_min right after this function's barrier, into a
+    // register; successive calls alternate between two words, so the next
+    // call's barrier separates that read from the next write to the word.)
+    if (s_min && tid < 64) {
+        unsigned m = v;
+#pragma unroll
+        for (int k = 1; k < 8; ++k) m = min(m, (unsigned)__builtin_amdgcn_readlane((int)v, k));
+        if (tid == 0) *s_min = m;
     }
     wait_barrier<DEV>();
     return *s_abort == 0;
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     __shared__ __attribute__((aligned(16))) float ztr[NQA - 3][YR][PY];
     __shared__ int s_ticket;
     __shared__ int s_abort;
-    __shared__ unsigned s_up;  // lower bound of the upwind neighbours' progress
+    __shared__ unsigned s_up[2];  // lower bound of the upwind neighbours' progress (alternate calls)
     // point sources kept in LDS (more are read from memory; the wide tile
     // keeps fewer, for its LDS budget)
     constexpr int kLdsSrc = IDR ? 8 : 16;
@@ -694,7 +697,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
         // ---- load the slot box of step t0 + 1 (lower corner o + t0) and
         //      read the upwind progress once
-        if (tid == 0) s_up = nup ? 0u : 0xFFFFFFFFu;
         {
             const int by = oy + t0, bz = oz + t0;
             int y, z;
@@ -737,7 +739,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             }
         }
-        if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up)) break;
+        if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up[0])) break;
+        // (a register copy, the same in every wavefront: every wavefront takes
+        // the same branch at each progress check)
+        unsigned up_reg = __builtin_amdgcn_readfirstlane(s_up[0]);
+        int upar = 1;  // the word of s_up the next wait writes
         // The box has landed before the step loop (a wait the compiler sees:
         // left to its own accounting, loads still in flight at the loop's
         // entry would make it drain the vector memory counter inside the
@@ -909,8 +915,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             };
             auto ensure_up = [&](unsigned level) -> bool {
-                if (s_up >= level) return true;
-                return wait_tiles<DEV>(A, ups, nup, level, &s_abort, &s_up);
+                if (up_reg >= level) return true;
+                const bool ok = wait_tiles<DEV>(A, ups, nup, level, &s_abort, &s_up[upar]);
+                up_reg = __builtin_amdgcn_readfirstlane(s_up[upar]);
+                upar ^= 1;
+                return ok;
             };
 
             // Before the tile's first cell crosses the lower wall of a PEC
@@ -928,7 +937,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             const unsigned ox_ = (sls * step_fx + (unsigned)dy * 16u + (unsigned)dz) * 4u;
 
             // ================= E half-step (H frame: register j <-> x = ox+tau-1+j)
-            const bool earlyE = s_up >= 2u * (unsigned)tau - 1u;
+            const bool earlyE = up_reg >= 2u * (unsigned)tau - 1u;
             if (earlyE) prefetch(std::integral_constant<int, 0>(), std::integral_constant<int, 3>());
             if (!skip) {
 #pragma unroll
@@ -1105,7 +1114,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
 
             // ================= H half-step (E frame: register j <-> x = ox+tau+j)
-            const bool earlyH = tau < t1 && s_up >= 2u * (unsigned)tau;
+            const bool earlyH = tau < t1 && up_reg >= 2u * (unsigned)tau;
             if (earlyH) prefetch(std::integral_constant<int, 3>(), std::integral_constant<int, NQA - 3>());
             if (!skip) {
 #pragma unroll

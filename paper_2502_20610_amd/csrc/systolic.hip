@@ -15,9 +15,11 @@
 //     row_ror:1 / row_ror:15 operand modifier of the consuming VALU op;
 //   * y: 4 rows per wavefront x NW wavefronts = 4*NW slots; the +-1 y
 //     neighbour goes through LDS;
-//   * x: 16 slots in registers per lane; moving the tile one cell along x is
-//     a compile-time renaming (results of register j are written to j-1), so
-//     the x neighbour is a plain register operand.
+//   * x: 16 slots in registers per lane (12 or 20 for the 11- and 19-wide
+//     tiles; the 19-wide one holds each cell's material index instead of its
+//     three coefficients); moving the tile one cell along x is a compile-time
+//     renaming (results of register j are written to j-1), so the x
+//     neighbour is a plain register operand.
 //   Each axis holds W+1 slots for W updated cells: the extra slot is the
 //   layer below the tile (H needed by the E half-step), then receives the
 //   layer above it from the upwind neighbours (E needed by the H half-step,
@@ -25,9 +27,12 @@
 //   modulo 16 on y and z, so cells never move between lanes.
 //
 // Faces: after each half-step a tile publishes the first layer of its
-// subdomain (E and H; the z face also the coefficients) into per-ticket face
-// rings, one per face orientation, laid out so that every face is one
-// contiguous block per component.  A consumer assembles its forward shell
+// subdomain (E and H; the z face also the coefficients, or the index) into
+// per-ticket face rings, one per face orientation, laid out so that every
+// face is one contiguous block per component.  On grids without periodic
+// axes a step publishes one progress level, once its stores have completed
+// behind the next half-step's work; periodic rings, whose tiles wait on each
+// other in a cycle, publish after each half-step.  A consumer assembles its forward shell
 // from up to seven upwind producers (edges and the corner come from the
 // diagonal neighbours).  The field arrays are read only when a band starts
 // and written only when it ends, so within a band every hand-off keeps full

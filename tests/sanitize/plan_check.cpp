@@ -172,6 +172,11 @@ int main()
         {{64, 64, 64}, {0, 0, 0}, {15, 15, 15}, 100, 24},
         {{256, 256, 256}, {1, 1, 0}, {15, 15, 15}, 64, 48},
         {{128, 96, 80}, {0, 0, 0}, {15, 15, 15}, 128, 64},
+        // the 19-wide tile: PEC, a 256^3 grid periodic in x and y (ring groups
+        // of 14 x 18 tiles, a ragged width-9 x tile), every axis periodic
+        {{83, 45, 52}, {0, 0, 0}, {19, 15, 15}, 60, 24},
+        {{256, 256, 256}, {1, 1, 0}, {19, 15, 15}, 64, 64},
+        {{40, 33, 36}, {1, 1, 1}, {19, 15, 15}, 60, 32},
     };
     std::vector<Plan> plans;
     for (const Case& c : cases) {

@@ -455,7 +455,7 @@ def main():
     ap.add_argument("--schemes", default="systolic,systolic_arrays,plain,plain_fused")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--band", type=int, default=0, help="systolic band length (0 = default)")
-    ap.add_argument("--tile-x", type=int, default=0, help="systolic tile width along x (0 = default, 11, 15)")
+    ap.add_argument("--tile-x", type=int, default=0, help="systolic tile width along x (0 = default, 11, 15, 19)")
     ap.add_argument("--autotune", action="store_true",
                     help="systolic: time the tile widths and band lengths first (fdtd_autotune) and "
                          "run the fastest")

@@ -227,6 +227,22 @@ __device__ __forceinline__ const float* sload_ptr(const void* p)
     return (const float*)(((unsigned long long)(unsigned)v[1] << 32) | (unsigned)v[0]);
 }
 
+// A band's record: tile ranges (a0, a1, b0, b1) and (c0, c1, first ticket
+// index, -), read through the scalar data cache (the plan does not change
+// while the kernel runs), so that testing neighbours against it takes one
+// scalar round trip and no vector memory operation.
+struct BandRec {
+    v4i r0, r1;
+};
+__device__ __forceinline__ BandRec load_band(const int* bi)
+{
+    return BandRec{sload4(bi), sload4(bi + 4)};
+}
+__device__ __forceinline__ int band_has(const BandRec& B, int a, int b, int c)
+{
+    return a >= B.r0[0] && a <= B.r0[1] && b >= B.r0[2] && b <= B.r0[3] && c >= B.r1[0] && c <= B.r1[1];
+}
+
 // An LDS address made opaque at this point of the program, so that the
 // per-component destinations derived from it are formed where they are used
 // instead of being kept live (in scalar registers) across the step loop.
@@ -242,11 +258,6 @@ __device__ __forceinline__ unsigned lds_here(unsigned base)
 __device__ __forceinline__ void lds_barrier()
 {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-__device__ __forceinline__ int band_has(const int* bi, int a, int b, int c)
-{
-    return a >= bi[0] && a <= bi[1] && b >= bi[2] && b <= bi[3] && c >= bi[4] && c <= bi[5];
 }
 
 // Tile coordinate v + (-1, 0 or +1) on an axis: wrapped onto the ring of a
@@ -274,28 +285,28 @@ __device__ __forceinline__ bool axis_pos(int U, int Uw, int n, bool per, int k, 
     return (unsigned)p < (unsigned)n;
 }
 
-// Ticket index of tile (a, b, c) of the band whose record is bi (the tile
+// Ticket index of tile (a, b, c) of the band whose record is B (the tile
 // must be in the band: band_has).
-__device__ __forceinline__ int ticket_of(const SysArgs& A, const int* bi, int a, int b, int c)
+__device__ __forceinline__ int ticket_of(const SysArgs& A, const BandRec& B, int a, int b, int c)
 {
-    return A.tix[bi[6] + ((a - bi[0]) * (bi[3] - bi[2] + 1) + (b - bi[2])) * (bi[5] - bi[4] + 1) +
-                 (c - bi[4])];
+    return A.tix[B.r1[2] + ((a - B.r0[0]) * (B.r0[3] - B.r0[2] + 1) + (b - B.r0[2])) * (B.r1[1] - B.r1[0] + 1) +
+                 (c - B.r1[0])];
 }
 
 // Ticket indices of the tiles (a, b, c) + s * (d & 1, (d >> 1) & 1, (d >> 2) & 1),
-// s = +1 (upwind corner) or -1 (downwind), in the band whose record is bi: lane
+// s = +1 (upwind corner) or -1 (downwind), in the band whose record is B: lane
 // d = lane & 7 of each wavefront looks up one direction, so that the eight
 // lookups cost one round trip instead of eight dependent ones.  Every lane
 // returns its own direction's ticket, or -1 when the band lacks that tile;
 // readlane(v, d) gives direction d.
 template <bool PER>
-__device__ __forceinline__ int corner_tickets(const SysArgs& A, const SimArgs& P, const int* bi, int a, int b,
-                                              int c, int s)
+__device__ __forceinline__ int corner_tickets(const SysArgs& A, const SimArgs& P, const BandRec& B, int a,
+                                              int b, int c, int s)
 {
     const int d = (int)(threadIdx.x & 7);
     const int ua = wrap_tile<PER>(P, 0, a + s * (d & 1)), ub = wrap_tile<PER>(P, 1, b + s * ((d >> 1) & 1)),
               uc = wrap_tile<PER>(P, 2, c + s * ((d >> 2) & 1));
-    return band_has(bi, ua, ub, uc) ? ticket_of(A, bi, ua, ub, uc) : -1;
+    return band_has(B, ua, ub, uc) ? ticket_of(A, B, ua, ub, uc) : -1;
 }
 
 // Set the tile's progress counter (release): every wavefront has completed
@@ -392,6 +403,44 @@ __device__ __forceinline__ bool wait_tiles(const SysArgs& A, const int (&idx)[8]
     // call's barrier separates that read from the next write to the word.)
     if (s_min && tid < 64) {
         unsigned m = v;
+#pragma unroll
+        for (int k = 1; k < 8; ++k) m = min(m, (unsigned)__builtin_amdgcn_readlane((int)v, k));
+        if (tid == 0) *s_min = m;
+    }
+    wait_barrier<DEV>();
+    return *s_abort == 0;
+}
+
+// The ticket's waits before its box load, as one poll: each lane of the first
+// wavefront with my >= 0 waits until tile my's counter is >= target (acquire).
+// Lanes 1..7 are the upwind neighbours' (target 0: one read); the minimum of
+// what they read goes to *s_min.  Returns false (on every thread) if a wait
+// expired or another workgroup raised the error.
+template <bool DEV>
+__device__ __forceinline__ bool wait_lanes(const SysArgs& A, int my, unsigned target, int* s_abort,
+                                           unsigned* s_min)
+{
+    const int tid = threadIdx.x;
+    unsigned v = 0xFFFFFFFFu;  // (lanes that poll nothing)
+    if (tid < 64 && my >= 0) {
+        unsigned* p = A.progress + my;
+        long long it = 0;
+        while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
+            if (++it > A.spin_limit) {
+                atomicOr(A.error, kErrTimeout);
+                *s_abort = 1;
+                break;
+            }
+            if ((it & 255) == 0 && (__hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout)) {
+                *s_abort = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!DEV) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (tid < 64) {
+        unsigned m = 0xFFFFFFFFu;
 #pragma unroll
         for (int k = 1; k < 8; ++k) m = min(m, (unsigned)__builtin_amdgcn_readlane((int)v, k));
         if (tid == 0) *s_min = m;
@@ -531,7 +580,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         staged_band = bnd;
         const int t0 = t0_ * P.K;
         const int t1 = min(A.nsteps, t0 + P.K);
-        const int* bi = P.band + 8 * bnd;
+        const BandRec bi = load_band(P.band + 8 * bnd);
         const unsigned plane = (unsigned)P.ny * (unsigned)P.nz;
         const bool perx = PER && P.per[0], pery = PER && P.per[1], perz = PER && P.per[2];
         // Field and coefficient descriptors start at the first x-plane the
@@ -604,58 +653,37 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         for (int k = 0; k < 8; ++k)
             if (k >= nup) ups[k] = me;
 
-        // band start: this tile and its upwind neighbours finished the previous band
-        if (bnd > 0) {
-            const int* bp = P.band + 8 * (bnd - 1);
-            int wl[8];
-            int nw = 0;
-            const int bv = corner_tickets<PER>(A, P, bp, a, b, c, 1);
-#pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                const int pi = __builtin_amdgcn_readlane(bv, d);
-                if (pi >= 0) {
-#pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        if (k == nw) wl[k] = pi;
-                    ++nw;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (k >= nw) wl[k] = me;
-            if (!wait_tiles<DEV>(A, wl, nw, 2u * (unsigned)t0, &s_abort, nullptr)) break;
-        }
-        // ring slot reuse: the previous occupant has finished writing it and
-        // its consumers (its downwind neighbours) have finished reading it
+        // The waits before the box load, as one poll by the first wavefront:
+        // lanes 8..15 wait for the band start (this tile and its upwind
+        // neighbours finished the previous band), lanes 16..23 for the ring
+        // slot's reuse (its previous occupant has finished writing it and the
+        // occupant's consumers, its downwind neighbours, have finished reading
+        // it), and lanes 1..7 read the upwind progress once.  The lookups of
+        // the three lists are independent loads, in flight together.
         const int slot = t % A.R;
+        const int lane8 = tid & 7, lgrp = (tid & 63) >> 3;
+        int bv = -1, cv = -1;
+        unsigned pend = 0u;
+        if (bnd > 0) bv = corner_tickets<PER>(A, P, load_band(P.band + 8 * (bnd - 1)), a, b, c, 1);
         if (t >= A.R) {
             const int4 pk = A.tickets[t - A.R];
             const SimArgs PP = load_sim(A.sims + (A.tsim ? __builtin_amdgcn_readfirstlane(A.tsim[t - A.R]) : 0));
-            const int* pb = PP.band + 8 * pk.x;
-            const unsigned pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * PP.K);
-            int wl[8];
-            wl[0] = t - A.R;
-            int nw = 1;
-            const int cv = corner_tickets<PER>(A, PP, pb, pk.y, pk.z, pk.w, -1);
-#pragma unroll
-            for (int d = 1; d < 8; ++d) {
-                const int ci = __builtin_amdgcn_readlane(cv, d);
-                if (ci >= 0) {
-#pragma unroll
-                    for (int k = 1; k < 8; ++k)
-                        if (k == nw) wl[k] = ci;
-                    ++nw;
-                }
-            }
-#pragma unroll
-            for (int k = 1; k < 8; ++k)
-                if (k >= nw) wl[k] = wl[0];
-            if (!wait_tiles<DEV>(A, wl, nw, pend, &s_abort, nullptr)) break;
+            pend = 2u * (unsigned)min(A.nsteps, (pk.x + 1) * PP.K);
+            const int cd = corner_tickets<PER>(A, PP, load_band(PP.band + 8 * pk.x), pk.y, pk.z, pk.w, -1);
+            cv = lane8 ? cd : t - A.R;
         }
-        // consumers of this tile's x, y and z faces in this band
-        const int has_xc = band_has(bi, wrap_tile<PER>(P, 0, a - 1), b, c);
-        const int has_yc = band_has(bi, a, wrap_tile<PER>(P, 1, b - 1), c);
-        const int has_consumer = band_has(bi, a, b, wrap_tile<PER>(P, 2, c - 1));
+        int myw = -1;
+        unsigned tgw = 0u;
+        if (lgrp == 0) {
+            myw = lane8 ? upv : -1;
+        } else if (lgrp == 1) {
+            myw = bv;
+            tgw = 2u * (unsigned)t0;
+        } else if (lgrp == 2) {
+            myw = cv;
+            tgw = pend;
+        }
+        if (!wait_lanes<DEV>(A, myw, tgw, &s_abort, &s_up[0])) break;
         // updated cells per axis (the last tile of a periodic ring is ragged),
         // the lanes that take the forward y and z faces, and the tile frame
         // origin modulo n on periodic axes
@@ -668,40 +696,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         if (pery) Yw = (oy + t0 + 1) % P.ny;
         if (perz) Zw = (oz + t0 + 1) % P.nz;
 
-        // ---- the band's samples of the LDS-cached sources (step tau reads
-        //      sample step0 + tau - 1 - first; the range test is repeated at use)
-        {
-            const int nl = min(P.nsrc, kLdsSrc);
-            for (int i = restage ? tid : nl * kMaxBand; i < nl * kMaxBand; i += 64 * NW) {
-                const int q = i / kMaxBand, l = i % kMaxBand;
-                const long long m = P.step0 + t0 + l - s_srcw[q][0];
-                s_wv[q][l] = (l < t1 - t0 && m >= 0 && m < s_srcw[q][1]) ? s_srcp[q][m] : 0.f;
-            }
-            // Sources that can fall inside this tile during the band: on a PEC
-            // axis the cell is inside B_tau for tau in [p - o - w + 1, p - o];
-            // periodic axes are not narrowed.  The test at use stays exact.
-            if (tid == 0) s_srcmask = 0u;
-            __syncthreads();
-            if (tid < nl) {
-                int lo = t0 + 1, hi = t1;
-                const int p3[3] = {s_src[tid][1], s_src[tid][2], s_src[tid][3]};
-                const int o3[3] = {ox, oy, oz}, w3[3] = {wxr, wyr, wzr};
-                const bool per3[3] = {perx, pery, perz};
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    if (!per3[d]) {
-                        lo = max(lo, p3[d] - o3[d] - w3[d] + 1);
-                        hi = min(hi, p3[d] - o3[d]);
-                    }
-                // and the waveform covers some of those steps
-                const long long first = s_srcw[tid][0], len = s_srcw[tid][1];
-                lo = (int)max((long long)lo, first + 1 - P.step0);
-                hi = (int)min((long long)hi, first + len - P.step0);
-                if (lo <= hi) atomicOr(&s_srcmask, 1u << tid);
-            }
-        }
-        // ---- load the slot box of step t0 + 1 (lower corner o + t0) and
-        //      read the upwind progress once
+        // ---- load the slot box of step t0 + 1 (lower corner o + t0); the
+        //      loads stay in flight through the scalar and LDS work below
         {
             const int by = oy + t0, bz = oz + t0;
             int y, z;
@@ -744,18 +740,56 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             }
         }
-        if (!wait_tiles<DEV>(A, ups, nup, 0u, &s_abort, &s_up[0])) break;
         // (a register copy, the same in every wavefront: every wavefront takes
         // the same branch at each progress check)
         unsigned up_reg = __builtin_amdgcn_readfirstlane(s_up[0]);
         int upar = 1;  // the word of s_up the next wait writes
+        // consumers of this tile's x, y and z faces in this band
+        const int has_xc = band_has(bi, wrap_tile<PER>(P, 0, a - 1), b, c);
+        const int has_yc = band_has(bi, a, wrap_tile<PER>(P, 1, b - 1), c);
+        const int has_consumer = band_has(bi, a, b, wrap_tile<PER>(P, 2, c - 1));
+
+        // ---- the band's samples of the LDS-cached sources (step tau reads
+        //      sample step0 + tau - 1 - first; the range test is repeated at use)
+        {
+            const int nl = min(P.nsrc, kLdsSrc);
+            for (int i = restage ? tid : nl * kMaxBand; i < nl * kMaxBand; i += 64 * NW) {
+                const int q = i / kMaxBand, l = i % kMaxBand;
+                const long long m = P.step0 + t0 + l - s_srcw[q][0];
+                s_wv[q][l] = (l < t1 - t0 && m >= 0 && m < s_srcw[q][1]) ? s_srcp[q][m] : 0.f;
+            }
+            // Sources that can fall inside this tile during the band: on a PEC
+            // axis the cell is inside B_tau for tau in [p - o - w + 1, p - o];
+            // periodic axes are not narrowed.  The test at use stays exact.
+            if (tid == 0) s_srcmask = 0u;
+            lds_barrier();
+            if (tid < nl) {
+                int lo = t0 + 1, hi = t1;
+                const int p3[3] = {s_src[tid][1], s_src[tid][2], s_src[tid][3]};
+                const int o3[3] = {ox, oy, oz}, w3[3] = {wxr, wyr, wzr};
+                const bool per3[3] = {perx, pery, perz};
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (!per3[d]) {
+                        lo = max(lo, p3[d] - o3[d] - w3[d] + 1);
+                        hi = min(hi, p3[d] - o3[d]);
+                    }
+                // and the waveform covers some of those steps
+                const long long first = s_srcw[tid][0], len = s_srcw[tid][1];
+                lo = (int)max((long long)lo, first + 1 - P.step0);
+                hi = (int)min((long long)hi, first + len - P.step0);
+                if (lo <= hi) atomicOr(&s_srcmask, 1u << tid);
+            }
+        }
+        lds_barrier();  // (s_srcmask and the samples are complete)
+
         // The box has landed before the step loop (a wait the compiler sees:
         // left to its own accounting, loads still in flight at the loop's
         // entry would make it drain the vector memory counter inside the
         // loop on every step).
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 
-        // (s_srcmask is complete: wait_tiles ends with a barrier)
+        // (s_srcmask is complete: the barrier above)
         const unsigned srcmask = __builtin_amdgcn_readfirstlane(s_srcmask);
         bool aborted = false;
         for (int tau = t0 + 1; tau <= t1; ++tau) {

@@ -57,6 +57,25 @@ def test_batch_bitwise(band, wg):
             s.close()
 
 
+def test_batch_pec_members_two_workgroups():
+    """PEC members only, on a persistent grid of two workgroups with bands of 3
+    steps: the face ring holds few slots, so a ticket's slot was last held a
+    few tickets earlier, often by another member, and its slot-reuse wait and
+    band-start wait take effect on nearly every ticket."""
+    pec = [m for m in MEMBERS if m[1] == (PEC, PEC, PEC)]
+    ws = [wl.small_case(shape, bc, seed=300 + q, nsteps=17, dipoles=d)
+          for q, (shape, bc, d) in enumerate(pec)]
+    sims = [_sim(ws[0], {fdtd.OPT_BAND_STEPS: 3, fdtd.OPT_WORKGROUPS: 2})] + [_sim(w) for w in ws[1:]]
+    try:
+        fdtd.step_batch(sims, 17)
+        for w, s in zip(ws, sims):
+            assert s.current_step == 17
+            assert_bitwise(s.read_fields(), oracle_f32(w, 17), "batch member %s, 2 workgroups" % (w.shape,))
+    finally:
+        for s in sims:
+            s.close()
+
+
 def test_batch_split_calls_and_mixed_with_solo_steps():
     """Batch calls, solo calls and plain steps interleave on the members'
     own streams; the state stays exact throughout (sources keep their step

@@ -56,6 +56,25 @@ def test_systolic_bitwise_small(shape, nsteps, band, seed, wx):
     assert_bitwise(run_sys(w, band=band, wx=wx), oracle_f32(w), "systolic %s wx=%d" % (shape, wx))
 
 
+@pytest.mark.parametrize("shape,seed", [
+    ((30, 1, 30), 41),     # one cell along y: every y row but one holds ghosts
+    ((30, 30, 1), 42),     # one cell along z
+    ((40, 1, 1), 43),      # a line along x
+    ((1, 1, 40), 44),      # a line along z
+    ((2, 2, 2), 45),       # fewer cells than lanes on every axis
+    ((20, 3, 17), 46),     # thin y beside ragged x and z
+])
+def test_systolic_thin_axes(shape, seed):
+    """PEC grids with one to three cells along some axes, over several bands:
+    the tile's slots along those axes are ghosts but for a few cells.  (The
+    z-directed dipole goes only where Ez is not frozen by the PEC planes x = 0
+    and y = 0; the random initial fields drive every case.)"""
+    c = tuple(s // 2 for s in shape)
+    dips = [c] if c[0] >= 1 and c[1] >= 1 else []
+    w = wl.small_case(shape, (PEC, PEC, PEC), seed=seed, nsteps=13, dipoles=dips)
+    assert_bitwise(run_sys(w, band=5), oracle_f32(w), "systolic thin %s" % (shape,))
+
+
 @pytest.mark.parametrize("wg", [1, 2, 7, 64])
 def test_systolic_few_workgroups(wg):
     w = wl.small_case((50, 40, 45), (PEC, PEC, PEC), seed=11, nsteps=19, dipoles=[(25, 20, 22)])

@@ -64,7 +64,8 @@ def test_systolic_bitwise_small(shape, nsteps, band, seed, wx):
     ((2, 2, 2), 45),       # fewer cells than lanes on every axis
     ((20, 3, 17), 46),     # thin y beside ragged x and z
 ])
-def test_systolic_thin_axes(shape, seed):
+@pytest.mark.parametrize("wx", [0, 15, 11])
+def test_systolic_thin_axes(shape, seed, wx):
     """PEC grids with one to three cells along some axes, over several bands:
     the tile's slots along those axes are ghosts but for a few cells.  (The
     z-directed dipole goes only where Ez is not frozen by the PEC planes x = 0
@@ -72,7 +73,7 @@ def test_systolic_thin_axes(shape, seed):
     c = tuple(s // 2 for s in shape)
     dips = [c] if c[0] >= 1 and c[1] >= 1 else []
     w = wl.small_case(shape, (PEC, PEC, PEC), seed=seed, nsteps=13, dipoles=dips)
-    assert_bitwise(run_sys(w, band=5), oracle_f32(w), "systolic thin %s" % (shape,))
+    assert_bitwise(run_sys(w, band=5, wx=wx), oracle_f32(w), "systolic thin %s wx=%d" % (shape, wx))
 
 
 @pytest.mark.parametrize("wg", [1, 2, 7, 64])
